@@ -1,0 +1,254 @@
+"""CPU oracle (test infrastructure only).
+
+ctypes front end of `oracle.c`.  Only the tests, the smoke check and the
+CPU-baseline leg of the benchmark may import this package; the HIP product
+path never does.  Every function works on one periodic cubic box in the
+caller's (original) atom order; multi-box helpers loop over boxes, each box
+independent of the others (the paper's multiple-box scheme keeps boxes
+independent, Section 4.4).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+
+KAPPA = 1.602176634e-19 / 1.66053906660e-27 * 1e-10
+KB_EV = 8.617333262e-5
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (plain C, OpenMP, no FP contraction)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fopenmp", "-shared",
+               "-fPIC", _SRC, "-o", _LIB + ".tmp", "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _Pot(C.Structure):
+    _fields_ = [("kind", C.c_int), ("rc", C.c_double), ("par", C.c_void_p),
+                ("tab", C.c_void_p * 3), ("ntab", C.c_int * 3),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        P = C.POINTER(_Pot)
+        i64, dbl, i32 = C.c_int64, C.c_double, C.c_int
+        L.orc_pot_eval.argtypes = [P, i32, dbl, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl)]
+        L.orc_wrap.argtypes = [i64, _f64p, _f64p, _f64p, dbl]
+        for fn in (L.orc_list_cells, L.orc_list_brute):
+            fn.argtypes = [i64, _f64p, _f64p, _f64p, dbl, dbl, i32, _i32p, _i32p]
+            fn.restype = i32
+        L.orc_density.argtypes = [i64, _f64p, _f64p, _f64p, dbl, P, _i32p, _i32p, i32, _f64p]
+        L.orc_embed.argtypes = [i64, P, _f64p, _f64p, _f64p, _f64p]
+        L.orc_forces.argtypes = [i64, _f64p, _f64p, _f64p, dbl, P, _i32p, _i32p, i32, _f64p,
+                                 _f64p, _f64p, _f64p, _f64p, _f64p]
+        L.orc_energy_direct.argtypes = [i64, _f64p, _f64p, _f64p, dbl, P]
+        L.orc_energy_direct.restype = dbl
+        L.orc_forces_direct.argtypes = [i64, _f64p, _f64p, _f64p, dbl, P, _f64p, _f64p, _f64p,
+                                        _f64p, _f64p]
+        L.orc_sample_forces.argtypes = [i64, _f64p, _f64p, _f64p, dbl, P, i64, _i64p, _f64p,
+                                        _f64p, _f64p, _f64p, _f64p]
+        L.orc_sample_list.argtypes = [i64, _f64p, _f64p, _f64p, dbl, dbl, i64, _i64p, i32,
+                                      _i32p, _i32p]
+        L.orc_rlist.argtypes = [dbl, dbl, dbl]
+        L.orc_rlist.restype = dbl
+        L.orc_vv.argtypes = [i64, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p, dbl, P, dbl, dbl,
+                             dbl, i32, i32, C.c_void_p, C.c_void_p]
+        L.orc_vv.restype = i32
+        L.orc_adjoint.argtypes = [i64, _f64p, _f64p, _f64p, dbl, P, _i32p, _i32p, i32, _f64p,
+                                  _f64p, _f64p, dbl, _f64p]
+        _lib = L
+    return _lib
+
+
+class Pot:
+    """Holds a potential (from workloads.Potential) in oracle form."""
+
+    def __init__(self, pot):
+        self.pot = pot
+        self._par = np.ascontiguousarray(np.asarray(pot.params, dtype=np.float64).ravel())
+        if self._par.size == 0:
+            self._par = np.zeros(1)
+        self._tabs = [np.ascontiguousarray(np.asarray(t, dtype=np.float64)) for t in pot.tables]
+        s = _Pot()
+        s.kind = int(pot.kind)
+        s.rc = float(pot.rc)
+        s.par = self._par.ctypes.data
+        for k, t in enumerate(self._tabs):
+            s.tab[k] = t.ctypes.data
+            s.ntab[k] = t.shape[0]
+        for k in range(3):
+            s.lo[k] = float(pot.lo[k])
+            s.hi[k] = float(pot.hi[k])
+        self.s = s
+
+    @property
+    def ref(self):
+        return C.byref(self.s)
+
+    @property
+    def rc(self):
+        return float(self.pot.rc)
+
+    def eval(self, which: int, x: float):
+        v, d1, d2 = C.c_double(), C.c_double(), C.c_double()
+        lib().orc_pot_eval(self.ref, which, float(x), C.byref(v), C.byref(d1), C.byref(d2))
+        return v.value, d1.value, d2.value
+
+
+def _xyz(pos):
+    pos = np.asarray(pos, dtype=np.float64)
+    return (np.ascontiguousarray(pos[:, 0]), np.ascontiguousarray(pos[:, 1]),
+            np.ascontiguousarray(pos[:, 2]))
+
+
+def rlist(rc: float, skin: float, L: float) -> float:
+    return lib().orc_rlist(rc, skin, L)
+
+
+def wrap(pos, L):
+    x, y, z = _xyz(pos)
+    lib().orc_wrap(x.size, x, y, z, float(L))
+    return np.stack([x, y, z], axis=1)
+
+
+def neighbor_list(pos, L, r_list, maxn=256, brute=False):
+    """Full neighbour list (ascending ids per row).  Returns (count, ids[n, maxn])."""
+    x, y, z = _xyz(pos)
+    n = x.size
+    count = np.zeros(n, dtype=np.int32)
+    ids = np.full((n, maxn), -1, dtype=np.int32)
+    fn = lib().orc_list_brute if brute else lib().orc_list_cells
+    worst = fn(n, x, y, z, float(L), float(r_list), maxn, count, ids)
+    if worst > maxn:
+        raise ValueError(f"neighbour row overflow: {worst} > {maxn}")
+    return count, ids
+
+
+def forces(pos, L, pot: Pot, count=None, ids=None, skin=0.3):
+    """Density, embedding and force passes over a (fresh) list.
+    Returns dict rho, F, Fp, Fpp, f[n,3], e_atom, E."""
+    x, y, z = _xyz(pos)
+    n = x.size
+    if count is None:
+        count, ids = neighbor_list(pos, L, rlist(pot.rc, skin, L))
+    maxn = ids.shape[1]
+    ids = np.ascontiguousarray(ids, dtype=np.int32)
+    rho = np.zeros(n)
+    lib().orc_density(n, x, y, z, float(L), pot.ref, count, ids, maxn, rho)
+    F, Fp, Fpp = np.zeros(n), np.zeros(n), np.zeros(n)
+    lib().orc_embed(n, pot.ref, rho, F, Fp, Fpp)
+    fx, fy, fz, e = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n)
+    lib().orc_forces(n, x, y, z, float(L), pot.ref, count, ids, maxn, F, Fp, fx, fy, fz, e)
+    return {"rho": rho, "F": F, "Fp": Fp, "Fpp": Fpp, "f": np.stack([fx, fy, fz], axis=1),
+            "e_atom": e, "E": float(e.sum())}
+
+
+def forces_direct(pos, L, pot: Pot):
+    x, y, z = _xyz(pos)
+    n = x.size
+    rho, fx, fy, fz, e = (np.zeros(n) for _ in range(5))
+    lib().orc_forces_direct(n, x, y, z, float(L), pot.ref, rho, fx, fy, fz, e)
+    return {"rho": rho, "f": np.stack([fx, fy, fz], axis=1), "e_atom": e, "E": float(e.sum())}
+
+
+def energy_direct(pos, L, pot: Pot) -> float:
+    x, y, z = _xyz(pos)
+    return lib().orc_energy_direct(x.size, x, y, z, float(L), pot.ref)
+
+
+def sample_forces(pos, L, pot: Pot, idx):
+    x, y, z = _xyz(pos)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    m = idx.size
+    rho, fx, fy, fz, e = (np.zeros(m) for _ in range(5))
+    lib().orc_sample_forces(x.size, x, y, z, float(L), pot.ref, m, idx, rho, fx, fy, fz, e)
+    return {"rho": rho, "f": np.stack([fx, fy, fz], axis=1), "e_atom": e}
+
+
+def sample_list(pos, L, r_list, idx, maxn=256):
+    x, y, z = _xyz(pos)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    count = np.zeros(idx.size, dtype=np.int32)
+    ids = np.full((idx.size, maxn), -1, dtype=np.int32)
+    lib().orc_sample_list(x.size, x, y, z, float(L), float(r_list), idx.size, idx, maxn,
+                          count, ids)
+    return count, ids
+
+
+def vv(pos, vel, L, pot: Pot, mass, dt, skin, nsteps, maxn=256, energies=True):
+    """Velocity-Verlet trajectory of one box.  Returns (pos, vel, epot, ekin, rebuilds)."""
+    x, y, z = _xyz(pos)
+    vx, vy, vz = _xyz(vel)
+    ep = np.zeros(nsteps + 1)
+    ek = np.zeros(nsteps + 1)
+    nreb = lib().orc_vv(x.size, x, y, z, vx, vy, vz, float(L), pot.ref, float(mass),
+                        float(dt), float(skin), int(nsteps), int(maxn),
+                        ep.ctypes.data if energies else None,
+                        ek.ctypes.data if energies else None)
+    if nreb < 0:
+        raise ValueError("neighbour row overflow in orc_vv")
+    return (np.stack([x, y, z], axis=1), np.stack([vx, vy, vz], axis=1), ep, ek, nreb)
+
+
+def adjoint(pos, L, pot: Pot, g, e, skin=0.3, gtheta=None):
+    """VJP of (forces, box energy) w.r.t. the B-spline coefficients of one box."""
+    x, y, z = _xyz(pos)
+    count, ids = neighbor_list(pos, L, rlist(pot.rc, skin, L))
+    gx, gy, gz = _xyz(g)
+    K = pot.s.ntab[0]
+    if gtheta is None:
+        gtheta = np.zeros(3 * K)
+    lib().orc_adjoint(x.size, x, y, z, float(L), pot.ref, count, ids, ids.shape[1], gx, gy, gz,
+                      float(e), gtheta)
+    return gtheta
+
+
+# ------------------------------------------------------------------ multi-box
+
+def boxes(W):
+    """Yield (b, slice, L) for the boxes of a workload."""
+    for b in range(W.n_boxes):
+        s = slice(int(W.box_offset[b]), int(W.box_offset[b + 1]))
+        yield b, s, float(W.box_len[b, 0])
+
+
+def forces_multi(W, pos=None, pot=None):
+    pos = W.pos if pos is None else pos
+    pot = pot or Pot(W.pot)
+    n = pos.shape[0]
+    out = {"rho": np.zeros(n), "f": np.zeros((n, 3)), "e_atom": np.zeros(n),
+           "Fp": np.zeros(n), "E_box": np.zeros(W.n_boxes)}
+    for b, s, L in boxes(W):
+        r = forces(wrap(pos[s], L), L, pot, skin=W.skin)
+        out["rho"][s] = r["rho"]
+        out["f"][s] = r["f"]
+        out["e_atom"][s] = r["e_atom"]
+        out["Fp"][s] = r["Fp"]
+        out["E_box"][b] = r["E"]
+    return out
+
+
+def kinetic(vel, mass):
+    return 0.5 * mass * float((np.asarray(vel) ** 2).sum()) / KAPPA
