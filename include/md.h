@@ -1,0 +1,203 @@
+/*
+ * md.h -- C ABI of the MI355X many-body MD force path (libmd.so).
+ *
+ * The library evaluates, on one gfx950 GPU and in double precision, the
+ * per-timestep force of embedded-atom-model (EAM) and second-moment
+ * tight-binding potentials (Hou et al., Section 2, eqs. 1-3):
+ *
+ *   E_i  = F(rho_i) + 1/2 sum_{j != i} V(r_ij),   rho_i = sum_{j != i} rho(r_ij)
+ *   f_i  = -sum_j [(F'(rho_i) + F'(rho_j)) rho'(r_ij) + V'(r_ij)] (x_i - x_j)/r_ij
+ *
+ * over full Verlet neighbour lists built from periodic linked cells
+ * (Section 3.2), driven by velocity Verlet.  Several independent periodic
+ * boxes may share one context (the multiple-box scheme of Section 4.4).
+ *
+ * Conventions for every entry point
+ *   - Units: Angstrom, eV, fs, amu.  All floating point is IEEE double.
+ *   - Per-atom input/output buffers are DEVICE pointers owned by the caller,
+ *     in the caller's original atom order.  Vectors are packed [N][3]
+ *     (x, y, z of atom 0, then atom 1, ...).  The library never frees them.
+ *   - `stream` is a hipStream_t passed as void* (NULL: the null stream).
+ *     Calls are stream ordered and asynchronous unless stated otherwise.
+ *   - Descriptors passed by pointer (md_system, md_potential) and the host
+ *     arrays they reference are read during the call only.
+ *   - Return value: MD_OK or a negative MD_ERR_* code.  Argument, capacity
+ *     and state errors are detected on the host and returned at once.
+ *     Conditions found by kernels (list overflow, table range, non-finite
+ *     coordinates) set bits in a device status word read by md_status().
+ *   - A context belongs to the device that was current at md_create(); it
+ *     allocates its device workspace there, once.  No entry point allocates
+ *     device memory after md_create() except md_set_max_neighbors().
+ *   - One context must not be used from two host threads at once.
+ */
+#ifndef MD_H
+#define MD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct md_ctx md_ctx;
+
+/* Return codes. */
+enum {
+    MD_OK = 0,
+    MD_ERR_ARG = -1,             /* invalid argument or descriptor                 */
+    MD_ERR_BOX = -2,             /* box shorter than twice the force cutoff        */
+    MD_ERR_NLIST_OVERFLOW = -3,  /* a neighbour row exceeded the list capacity     */
+    MD_ERR_TABLE_RANGE = -4,     /* a table lookup fell outside the tabulated grid */
+    MD_ERR_NONFINITE = -5,       /* a coordinate became NaN or infinite            */
+    MD_ERR_DEVICE = -6,          /* a HIP runtime call failed                      */
+    MD_ERR_STATE = -7,           /* call out of order (e.g. no state set)          */
+    MD_ERR_NOMEM = -8            /* device allocation failed                       */
+};
+
+/* Bits of the device status word (md_status). */
+enum {
+    MD_FLAG_NLIST_OVERFLOW = 1u,
+    MD_FLAG_TABLE_RANGE = 2u,
+    MD_FLAG_NONFINITE = 4u
+};
+
+/* Potential kinds. */
+enum {
+    MD_POT_FS = 1,      /* Finnis-Sinclair: params c d c0 c1 c2 A
+                           V(r) = (r-c)^2 (c0 + c1 r + c2 r^2) for r < c,
+                           rho(r) = (r-d)^2 for r < d, F(rho) = -A sqrt(rho)  */
+    MD_POT_SMTB = 2,    /* second-moment tight binding: params A xi p q r0
+                           V(r) = 2A exp(-p (r/r0 - 1)),
+                           rho(r) = xi^2 exp(-2q (r/r0 - 1)), F(rho) = -sqrt(rho)
+                           (the SETB form of Section 4)                         */
+    MD_POT_SPLINE = 3,  /* lookup tables (Section 3.3): for V(r), rho(r), F(rho)
+                           each a uniform grid [lo, hi] of n intervals with cubic
+                           coefficients (a, b, c, d): S = a + b t + c t^2 + d t^3,
+                           t = (x - lo)/h - m in interval m, h = (hi - lo)/n    */
+    MD_POT_BSPLINE = 4  /* uniform cubic B-splines: for each function K
+                           coefficients theta_0..theta_{K-1} over K-3 intervals
+                           of [lo, hi]; S = sum_l theta_{m+l} b_l(t)            */
+};
+
+typedef struct {
+    int32_t kind;            /* MD_POT_*                                          */
+    int32_t n_params;        /* entries of params (FS 6, SMTB 5, else 0)          */
+    double rc;               /* force cutoff: pairs with r < rc interact          */
+    const double *params;    /* host, analytic parameters                         */
+    const double *tab[3];    /* host; V(r), rho(r), F(rho):
+                                SPLINE  [n_tab[k]][4] coefficients,
+                                BSPLINE [n_tab[k]] coefficients                   */
+    int32_t n_tab[3];        /* SPLINE: intervals; BSPLINE: coefficients          */
+    double lo[3], hi[3];     /* grid range of each table                          */
+} md_potential;
+
+typedef struct {
+    int32_t n_boxes;            /* B >= 1 independent periodic cubic boxes          */
+    int32_t max_neighbors;      /* list capacity per atom; 0 = estimate from density */
+    const int64_t *box_offset;  /* host [B+1]: atoms of box b are
+                                   box_offset[b] .. box_offset[b+1]-1; [0] = 0       */
+    const double *box_len;      /* host [B]: edge length of each cubic box           */
+    double mass;                /* amu, all atoms                                    */
+    double dt;                  /* fs                                                */
+    double skin;                /* Verlet skin (Angstrom); the list radius of box b is
+                                   min(rc + skin, box_len[b]/2 - 1e-9), and the list is
+                                   rebuilt when an atom of the box has moved more than
+                                   half of (list radius - rc) since the last build    */
+} md_system;
+
+/* Create a context on the current device.  Validates the descriptors
+ * (MD_ERR_ARG), requires box_len[b] > 2 rc for every box (MD_ERR_BOX),
+ * uploads the potential, and allocates all device memory of the context. */
+int md_create(const md_system *sys, const md_potential *pot, md_ctx **out);
+
+/* Free every device and host resource of the context. */
+void md_destroy(md_ctx *ctx);
+
+/* Human-readable text of a return code. */
+const char *md_strerror(int code);
+
+/* Replace the potential (same kind and table sizes as at creation). */
+int md_set_potential(md_ctx *ctx, const md_potential *pot, void *stream);
+
+/* B-spline potentials only: upload 3K coefficients (device pointer, order
+ * V, rho, F) and convert them on the device to per-interval cubics. */
+int md_set_theta(md_ctx *ctx, const double *theta, void *stream);
+
+/* Load positions pos[N][3] and velocities vel[N][3] (vel may be NULL: zero).
+ * The next pass rebuilds the neighbour list first. */
+int md_set_state(md_ctx *ctx, const double *pos, const double *vel, void *stream);
+
+/* Copy the current positions and velocities out (either may be NULL).
+ * Positions are wrapped into the box at each list build and integrated
+ * without wrapping in between. */
+int md_get_state(md_ctx *ctx, double *pos, double *vel, void *stream);
+
+/* Steps a1-a3 (Section 3.2): wrap positions into each box, bin atoms into
+ * cells of edge >= list radius, sort them by (cell, original index) with a
+ * counting sort, and build the full neighbour list of every atom (all j != i
+ * of the same box within the list radius under the minimum image; squared
+ * distance (dx dx + dy dy) + dz dz without fused multiply-add, strict <). */
+int md_build_neighbors(md_ctx *ctx, void *stream);
+
+/* Density pass (Fig. 5) with the embedding fused: rho_i = sum of rho(r_ij)
+ * over listed j with r_ij < rc.  rho_out[N] may be NULL. */
+int md_density(md_ctx *ctx, double *rho_out, void *stream);
+
+/* Embedding pass: F(rho_i) and F'(rho_i) of the last density pass.
+ * Either output [N] may be NULL. */
+int md_embed(md_ctx *ctx, double *F_out, double *Fp_out, void *stream);
+
+/* Force pass (Fig. 6, eq. 3) after md_density: forces f_out[N][3], per-atom
+ * energies e_atom[N] = F(rho_i) + 1/2 sum_j V(r_ij), and per-box energies
+ * e_box[B] (deterministic sums).  Any output may be NULL. */
+int md_forces(md_ctx *ctx, double *f_out, double *e_atom, double *e_box, void *stream);
+
+/* nsteps of velocity Verlet: half kick, drift, conditional list rebuild
+ * decided on the device, density + embedding, force, half kick.  Brings the
+ * list and forces up to date first if needed.  The step sequence is captured
+ * once in a HIP graph and replayed. */
+int md_step(md_ctx *ctx, int nsteps, void *stream);
+
+/* Kinetic energy per box, ke_box[B] = sum m v^2 / 2 (eV). */
+int md_kinetic(md_ctx *ctx, double *ke_box, void *stream);
+
+/* Neighbour rows in original indices: counts[N] and ids[N][max_cols]
+ * (row order is the device's summation order; rows longer than max_cols
+ * are cut).  Synchronises the stream. */
+int md_get_neighbors(md_ctx *ctx, int32_t *counts, int32_t *ids, int32_t max_cols,
+                     void *stream);
+
+/* Capacity of the neighbour list per atom. */
+int md_max_neighbors(const md_ctx *ctx, int32_t *out);
+
+/* Reallocate the list for a new capacity; the next pass rebuilds it. */
+int md_set_max_neighbors(md_ctx *ctx, int32_t max_neighbors);
+
+/* Synchronise the stream, return the device status bits in *flags and clear
+ * them.  Also reports counters[0] = list builds and counters[1] = steps
+ * since creation (counters may be NULL). */
+int md_status(md_ctx *ctx, void *stream, uint32_t *flags, int64_t *counters);
+
+/* Form (3): vector-Jacobian product of the forces and per-box energies with
+ * respect to the B-spline coefficients (MD_POT_BSPLINE only).  g[N][3] =
+ * dL/df_i, e[B] = dL/dE_b (device); writes gtheta[3K] (device, order V, rho,
+ * F).  Recomputes rho, F'(rho) and F''(rho) from the current positions and
+ * list; the reduction order is fixed, so results are bitwise reproducible. */
+int md_adjoint(md_ctx *ctx, const double *g, const double *e, double *gtheta, void *stream);
+
+/* Options. */
+enum {
+    MD_OPT_BATCHED = 1,     /* multi-box md_step: 1 persistent box-per-workgroup kernel
+                               (default when B > 1), 0 the merged-box kernels     */
+    MD_OPT_BATCH_BLOCK = 2, /* workgroup size of the persistent kernel (256/512/1024) */
+    MD_OPT_USE_GRAPH = 3,   /* md_step replays a captured HIP graph (default 1)     */
+    MD_OPT_GRAPH_STEPS = 4  /* steps per captured graph (default 8)                 */
+};
+int md_set_option(md_ctx *ctx, int32_t key, int64_t value);
+int md_get_option(const md_ctx *ctx, int32_t key, int64_t *value);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MD_H */

@@ -1,0 +1,637 @@
+// Host implementation of the C ABI declared in include/md.h.
+//
+// A context owns one device workspace sized at creation: the sorted atom
+// state, the cell structure, the neighbour list, per-box geometry, partial
+// sums and the status word.  Entry points enqueue kernels on the caller's
+// stream; md_step replays a captured HIP graph of several velocity-Verlet
+// steps in which the list rebuild is decided on the device, so the host
+// never waits inside a trajectory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "md_internal.h"
+
+using namespace mdk;
+
+#define HIP_TRY(call)                              \
+    do {                                           \
+        if ((call) != hipSuccess) return MD_ERR_DEVICE; \
+    } while (0)
+
+namespace {
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+template <class T>
+int dev_alloc(Ctx &c, T **p, size_t count)
+{
+    void *q = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) return MD_ERR_NOMEM;
+    c.allocs.push_back(q);
+    *p = static_cast<T *>(q);
+    return MD_OK;
+}
+
+#define ALLOC(ptr, n)                          \
+    do {                                       \
+        int rc_ = dev_alloc(c, &(ptr), (n));   \
+        if (rc_ != MD_OK) return rc_;          \
+    } while (0)
+
+double list_radius(double rc, double skin, double L)
+{
+    double r = rc + skin, half = 0.5 * L - 1e-9;
+    return r < half ? r : half;
+}
+
+int cells_per_dim(double L, double rl)
+{
+    int nc = (int)std::floor(L / rl);
+    while (nc > 1 && L / nc < rl) --nc;
+    return nc < 1 ? 1 : nc;
+}
+
+int check_potential(const md_potential *p)
+{
+    if (!p || !(p->rc > 0.0)) return MD_ERR_ARG;
+    switch (p->kind) {
+    case MD_POT_FS: return (p->params && p->n_params >= 6) ? MD_OK : MD_ERR_ARG;
+    case MD_POT_SMTB: return (p->params && p->n_params >= 5) ? MD_OK : MD_ERR_ARG;
+    case MD_POT_SPLINE:
+    case MD_POT_BSPLINE:
+        for (int k = 0; k < 3; ++k) {
+            int need = p->kind == MD_POT_SPLINE ? 1 : 4;
+            if (!p->tab[k] || p->n_tab[k] < need || !(p->hi[k] > p->lo[k])) return MD_ERR_ARG;
+        }
+        if (p->kind == MD_POT_BSPLINE && (p->n_tab[0] != p->n_tab[1] || p->n_tab[0] != p->n_tab[2]))
+            return MD_ERR_ARG;
+        return MD_OK;
+    }
+    return MD_ERR_ARG;
+}
+
+void graph_reset(Ctx &c)
+{
+    if (c.graph_exec) (void)hipGraphExecDestroy(c.graph_exec);
+    c.graph_exec = nullptr;
+    c.graph_len = 0;
+}
+
+// Analytic constants and device tables of a potential.
+int upload_potential(Ctx &c, const md_potential *p, hipStream_t s, bool first)
+{
+    Pot &q = c.pot;
+    q.rc = p->rc;
+    q.rc2 = p->rc * p->rc;
+    if (p->kind == MD_POT_FS) {
+        q.kind = MD_POT_FS;
+        q.c = p->params[0];
+        q.d = p->params[1];
+        q.c0 = p->params[2];
+        q.c1 = p->params[3];
+        q.c2 = p->params[4];
+        q.A = p->params[5];
+    } else if (p->kind == MD_POT_SMTB) {
+        q.kind = MD_POT_SMTB;
+        double A = p->params[0], xi = p->params[1], pp = p->params[2], qq = p->params[3],
+               r0 = p->params[4];
+        if (!(A > 0.0 && xi > 0.0 && r0 > 0.0)) return MD_ERR_ARG;
+        // V = 2A exp(-p (r/r0 - 1)) = exp(av r + bv); rho = xi^2 exp(-2q (r/r0 - 1)) = exp(af r + bf)
+        q.av = -pp / r0;
+        q.bv = pp + std::log(2.0 * A);
+        q.af = -2.0 * qq / r0;
+        q.bf = 2.0 * qq + 2.0 * std::log(xi);
+    } else {
+        q.kind = MD_POT_SPLINE;
+        if (first) {
+            size_t total = 0;
+            c.tab_len.assign(3, 0);
+            for (int k = 0; k < 3; ++k) {
+                int nint = p->kind == MD_POT_SPLINE ? p->n_tab[k] : p->n_tab[k] - 3;
+                c.tab_len[k] = 4 * nint;
+                total += 4 * (size_t)nint;
+            }
+            ALLOC(c.tables, total);
+            if (p->kind == MD_POT_BSPLINE) {
+                c.n_theta = p->n_tab[0];
+                ALLOC(c.theta, 3 * (size_t)c.n_theta);
+            }
+        } else {
+            for (int k = 0; k < 3; ++k) {
+                int nint = p->kind == MD_POT_SPLINE ? p->n_tab[k] : p->n_tab[k] - 3;
+                if (c.tab_len[k] != 4 * nint) return MD_ERR_ARG;
+            }
+        }
+        size_t off = 0;
+        for (int k = 0; k < 3; ++k) {
+            int nint = c.tab_len[k] / 4;
+            q.tab[k].c = c.tables + off;
+            q.tab[k].n = nint;
+            q.tab[k].lo = p->lo[k];
+            q.tab[k].hi = p->hi[k];
+            q.tab[k].inv_h = nint / (p->hi[k] - p->lo[k]);
+            off += c.tab_len[k];
+        }
+        if (p->kind == MD_POT_SPLINE) {
+            off = 0;
+            for (int k = 0; k < 3; ++k) {
+                HIP_TRY(hipMemcpyAsync(c.tables + off, p->tab[k], sizeof(double) * c.tab_len[k],
+                                       hipMemcpyHostToDevice, s));
+                off += c.tab_len[k];
+            }
+        } else {
+            for (int k = 0; k < 3; ++k)
+                HIP_TRY(hipMemcpyAsync(c.theta + (size_t)k * c.n_theta, p->tab[k],
+                                       sizeof(double) * c.n_theta, hipMemcpyHostToDevice, s));
+            launch_bspline_tables(c, c.theta, s);
+        }
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    graph_reset(c);
+    c.density_valid = c.forces_valid = false;
+    return MD_OK;
+}
+
+int alloc_list(Ctx &c, int mn)
+{
+    c.nl.mn = mn;
+    ALLOC(c.nl.idx, (size_t)mn * c.N);
+    return MD_OK;
+}
+
+// Bring the list, density and forces up to date on stream s.
+void ensure_list(Ctx &c, hipStream_t s)
+{
+    if (!c.list_valid) {
+        launch_build(c, false, s);
+        c.list_valid = true;
+        c.density_valid = c.forces_valid = false;
+    }
+}
+
+void ensure_density(Ctx &c, hipStream_t s)
+{
+    ensure_list(c, s);
+    if (!c.density_valid) {
+        launch_density(c, s);
+        c.density_valid = true;
+    }
+}
+
+int capture_steps(Ctx &c, int nsteps)
+{
+    graph_reset(c);
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeRelaxed));
+    for (int k = 0; k < nsteps; ++k) {
+        launch_kick_drift(c, c.cap_stream);
+        launch_build(c, true, c.cap_stream);
+        launch_density(c, c.cap_stream);
+        launch_force(c, false, true, c.cap_stream);
+        launch_step_end(c, c.cap_stream);
+    }
+    HIP_TRY(hipStreamEndCapture(c.cap_stream, &g));
+    hipError_t e = hipGraphInstantiate(&c.graph_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c.graph_exec = nullptr;
+        return MD_ERR_DEVICE;
+    }
+    c.graph_len = nsteps;
+    return MD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *md_strerror(int code)
+{
+    switch (code) {
+    case MD_OK: return "ok";
+    case MD_ERR_ARG: return "invalid argument";
+    case MD_ERR_BOX: return "box edge must exceed twice the force cutoff";
+    case MD_ERR_NLIST_OVERFLOW: return "neighbour list capacity exceeded";
+    case MD_ERR_TABLE_RANGE: return "table lookup outside the tabulated range";
+    case MD_ERR_NONFINITE: return "non-finite coordinate";
+    case MD_ERR_DEVICE: return "HIP runtime error";
+    case MD_ERR_STATE: return "call out of order";
+    case MD_ERR_NOMEM: return "device allocation failed";
+    }
+    return "unknown error";
+}
+
+int md_create(const md_system *sys, const md_potential *pot, md_ctx **out)
+{
+    if (!out) return MD_ERR_ARG;
+    *out = nullptr;
+    if (!sys || sys->n_boxes < 1 || !sys->box_offset || !sys->box_len) return MD_ERR_ARG;
+    if (!(sys->mass > 0.0) || !(sys->dt > 0.0) || !(sys->skin >= 0.0)) return MD_ERR_ARG;
+    int prc = check_potential(pot);
+    if (prc != MD_OK) return prc;
+    int B = sys->n_boxes;
+    if (sys->box_offset[0] != 0) return MD_ERR_ARG;
+    for (int b = 0; b < B; ++b) {
+        if (sys->box_offset[b + 1] - sys->box_offset[b] < 2) return MD_ERR_ARG;
+        if (!(sys->box_len[b] > 0.0)) return MD_ERR_ARG;
+        if (!(0.5 * sys->box_len[b] - 1e-9 > pot->rc)) return MD_ERR_BOX;
+    }
+    int64_t N = sys->box_offset[B];
+    if (N >= (int64_t)1 << 31) return MD_ERR_ARG;
+
+    md_ctx *h = new (std::nothrow) md_ctx();
+    if (!h) return MD_ERR_NOMEM;
+    Ctx &c = h->c;
+    auto fail = [&](int code) {
+        md_destroy(h);
+        return code;
+    };
+    if (hipGetDevice(&c.device) != hipSuccess) return fail(MD_ERR_DEVICE);
+    c.N = N;
+    c.B = B;
+    c.mass = sys->mass;
+    c.dt = sys->dt;
+    c.skin = sys->skin;
+    c.kind_user = pot->kind;
+    c.batched = false;
+    c.box_off.assign(sys->box_offset, sys->box_offset + B + 1);
+    c.box_len.assign(sys->box_len, sys->box_len + B);
+    c.box_rlist.resize(B);
+    c.box_nc.resize(B);
+    c.box_cell_off.resize(B + 1);
+    int64_t cells = 0;
+    double mn_est = 0.0;
+    for (int b = 0; b < B; ++b) {
+        double L = c.box_len[b];
+        double rl = list_radius(pot->rc, sys->skin, L);
+        c.box_rlist[b] = rl;
+        int nc = cells_per_dim(L, rl);
+        c.box_nc[b] = nc;
+        c.box_cell_off[b] = (int)cells;
+        cells += (int64_t)nc * nc * nc;
+        double nb = (double)(c.box_off[b + 1] - c.box_off[b]);
+        double expect = nb / (L * L * L) * 4.0 / 3.0 * M_PI * rl * rl * rl;
+        double est = std::min(nb - 1.0, std::ceil(1.4 * expect + 16.0));
+        mn_est = std::max(mn_est, est);
+    }
+    if (cells >= (int64_t)1 << 30) return fail(MD_ERR_ARG);
+    c.box_cell_off[B] = (int)cells;
+    c.bd.n_cells = (int)cells;
+    int mn = sys->max_neighbors > 0 ? sys->max_neighbors : ((int)mn_est + 7) / 8 * 8;
+    if (mn < 1) mn = 1;
+
+    if (hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return fail(MD_ERR_DEVICE);
+    hipStream_t s = c.cap_stream;
+
+    // per-box geometry
+    int rc;
+    if ((rc = dev_alloc(c, &c.d_boxd, 4 * (size_t)B)) != MD_OK) return fail(rc);
+    if ((rc = dev_alloc(c, &c.d_boxi, 3 * (size_t)B + 1 + N)) != MD_OK) return fail(rc);
+    {
+        std::vector<double> hd(4 * (size_t)B);
+        std::vector<int> hi(3 * (size_t)B + 1 + N);
+        for (int b = 0; b < B; ++b) {
+            double L = c.box_len[b], rl = c.box_rlist[b], half = 0.5 * (rl - pot->rc);
+            hd[b] = L;
+            hd[B + b] = 1.0 / L;
+            hd[2 * B + b] = rl * rl;
+            hd[3 * B + b] = half * half;
+            hi[b] = c.box_nc[b];
+            hi[B + b] = c.box_cell_off[b];
+        }
+        for (int b = 0; b <= B; ++b) hi[2 * B + b] = (int)c.box_off[b];
+        for (int b = 0; b < B; ++b)
+            for (int64_t i = c.box_off[b]; i < c.box_off[b + 1]; ++i) hi[3 * B + 1 + i] = b;
+        if (hipMemcpy(c.d_boxd, hd.data(), hd.size() * sizeof(double), hipMemcpyHostToDevice) !=
+                hipSuccess ||
+            hipMemcpy(c.d_boxi, hi.data(), hi.size() * sizeof(int), hipMemcpyHostToDevice) !=
+                hipSuccess)
+            return fail(MD_ERR_DEVICE);
+        c.bx.L = c.d_boxd;
+        c.bx.invL = c.d_boxd + B;
+        c.bx.rl2 = c.d_boxd + 2 * B;
+        c.bx.thr2 = c.d_boxd + 3 * B;
+        c.bx.nc = c.d_boxi;
+        c.bx.cell_off = c.d_boxi + B;
+        c.bx.atom_off = c.d_boxi + 2 * B;
+        c.bx.box_of = c.d_boxi + 3 * B + 1;
+    }
+
+    // atom state and build scratch
+    double **dbl[] = {&c.st.x, &c.st.y, &c.st.z, &c.st.vx, &c.st.vy, &c.st.vz, &c.st.fx,
+                      &c.st.fy, &c.st.fz, &c.st.xr, &c.st.yr, &c.st.zr, &c.st.rho, &c.st.Fp,
+                      &c.st.Femb, &c.st.eat, &c.bd.sx, &c.bd.sy, &c.bd.sz, &c.bd.svx,
+                      &c.bd.svy, &c.bd.svz};
+    for (double **p : dbl)
+        if ((rc = dev_alloc(c, p, (size_t)N)) != MD_OK) return fail(rc);
+    int **ints[] = {&c.st.id, &c.bd.sid, &c.bd.cell_of, &c.bd.slot, &c.bd.tmp, &c.bd.perm,
+                    &c.nl.count};
+    for (int **p : ints)
+        if ((rc = dev_alloc(c, p, (size_t)N)) != MD_OK) return fail(rc);
+    if ((rc = dev_alloc(c, &c.bd.cell_count, (size_t)cells)) != MD_OK) return fail(rc);
+    if ((rc = dev_alloc(c, &c.bd.cell_start, (size_t)cells + 1)) != MD_OK) return fail(rc);
+    if ((rc = alloc_list(c, mn)) != MD_OK) return fail(rc);
+    if ((rc = dev_alloc(c, &c.dev.flags, 8)) != MD_OK) return fail(rc);
+    if (hipMemset(c.dev.flags, 0, 8 * sizeof(unsigned)) != hipSuccess) return fail(MD_ERR_DEVICE);
+    if (hipMemset(c.nl.count, 0, sizeof(int) * N) != hipSuccess) return fail(MD_ERR_DEVICE);
+
+    // chunks of the fixed-order per-box sums
+    {
+        std::vector<int> cs, ce, bc(B + 1);
+        for (int b = 0; b < B; ++b) {
+            bc[b] = (int)cs.size();
+            for (int64_t a = c.box_off[b]; a < c.box_off[b + 1]; a += kChunk) {
+                cs.push_back((int)a);
+                ce.push_back((int)std::min<int64_t>(a + kChunk, c.box_off[b + 1]));
+            }
+        }
+        bc[B] = (int)cs.size();
+        c.n_chunks = (int)cs.size();
+        std::vector<int> all;
+        all.insert(all.end(), cs.begin(), cs.end());
+        all.insert(all.end(), ce.begin(), ce.end());
+        all.insert(all.end(), bc.begin(), bc.end());
+        if ((rc = dev_alloc(c, &c.d_chunks, all.size())) != MD_OK) return fail(rc);
+        if ((rc = dev_alloc(c, &c.d_partial, (size_t)c.n_chunks)) != MD_OK) return fail(rc);
+        if (hipMemcpy(c.d_chunks, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice) !=
+            hipSuccess)
+            return fail(MD_ERR_DEVICE);
+    }
+
+    if ((rc = upload_potential(c, pot, s, true)) != MD_OK) return fail(rc);
+    if (c.B > 1) {
+        if ((rc = batched_prepare(c)) != MD_OK) return fail(rc);
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(MD_ERR_DEVICE);
+    *out = h;
+    return MD_OK;
+}
+
+void md_destroy(md_ctx *h)
+{
+    if (!h) return;
+    Ctx &c = h->c;
+    graph_reset(c);
+    if (c.cap_stream) {
+        (void)hipStreamSynchronize(c.cap_stream);
+        (void)hipStreamDestroy(c.cap_stream);
+    }
+    (void)hipDeviceSynchronize();
+    for (void *p : c.allocs) (void)hipFree(p);
+    delete h;
+}
+
+int md_set_potential(md_ctx *h, const md_potential *pot, void *stream)
+{
+    if (!h) return MD_ERR_ARG;
+    int rc = check_potential(pot);
+    if (rc != MD_OK) return rc;
+    if (pot->kind != h->c.kind_user) return MD_ERR_ARG;
+    return upload_potential(h->c, pot, as_stream(stream), false);
+}
+
+int md_set_theta(md_ctx *h, const double *theta, void *stream)
+{
+    if (!h || !theta) return MD_ERR_ARG;
+    Ctx &c = h->c;
+    if (c.kind_user != MD_POT_BSPLINE) return MD_ERR_ARG;
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(hipMemcpyAsync(c.theta, theta, sizeof(double) * 3 * c.n_theta,
+                           hipMemcpyDeviceToDevice, s));
+    launch_bspline_tables(c, c.theta, s);
+    c.density_valid = c.forces_valid = false;
+    return MD_OK;
+}
+
+int md_set_state(md_ctx *h, const double *pos, const double *vel, void *stream)
+{
+    if (!h || !pos) return MD_ERR_ARG;
+    Ctx &c = h->c;
+    launch_set_state(c, pos, vel, as_stream(stream));
+    c.state_set = true;
+    c.list_valid = c.density_valid = c.forces_valid = false;
+    return MD_OK;
+}
+
+int md_get_state(md_ctx *h, double *pos, double *vel, void *stream)
+{
+    if (!h) return MD_ERR_ARG;
+    if (!h->c.state_set) return MD_ERR_STATE;
+    launch_get_state(h->c, pos, vel, as_stream(stream));
+    return MD_OK;
+}
+
+int md_build_neighbors(md_ctx *h, void *stream)
+{
+    if (!h) return MD_ERR_ARG;
+    Ctx &c = h->c;
+    if (!c.state_set) return MD_ERR_STATE;
+    launch_build(c, false, as_stream(stream));
+    c.list_valid = true;
+    c.density_valid = c.forces_valid = false;
+    return MD_OK;
+}
+
+int md_density(md_ctx *h, double *rho_out, void *stream)
+{
+    if (!h) return MD_ERR_ARG;
+    Ctx &c = h->c;
+    if (!c.state_set) return MD_ERR_STATE;
+    hipStream_t s = as_stream(stream);
+    ensure_list(c, s);
+    launch_density(c, s);
+    c.density_valid = true;
+    c.forces_valid = false;
+    if (rho_out) launch_scatter_scalar(c, c.st.rho, rho_out, s);
+    return MD_OK;
+}
+
+int md_embed(md_ctx *h, double *F_out, double *Fp_out, void *stream)
+{
+    if (!h) return MD_ERR_ARG;
+    Ctx &c = h->c;
+    if (!c.state_set) return MD_ERR_STATE;
+    hipStream_t s = as_stream(stream);
+    ensure_density(c, s);
+    launch_embed(c, s);
+    if (F_out) launch_scatter_scalar(c, c.st.Femb, F_out, s);
+    if (Fp_out) launch_scatter_scalar(c, c.st.Fp, Fp_out, s);
+    return MD_OK;
+}
+
+int md_forces(md_ctx *h, double *f_out, double *e_atom, double *e_box, void *stream)
+{
+    if (!h) return MD_ERR_ARG;
+    Ctx &c = h->c;
+    if (!c.state_set) return MD_ERR_STATE;
+    hipStream_t s = as_stream(stream);
+    ensure_density(c, s);
+    bool energy = e_atom || e_box;
+    launch_force(c, energy, false, s);
+    c.forces_valid = true;
+    if (f_out) launch_scatter_vec3(c, c.st.fx, c.st.fy, c.st.fz, f_out, s);
+    if (e_atom) launch_scatter_scalar(c, c.st.eat, e_atom, s);
+    if (e_box) launch_box_sums(c, 0, e_box, s);
+    return MD_OK;
+}
+
+int md_step(md_ctx *h, int nsteps, void *stream)
+{
+    if (!h || nsteps < 0) return MD_ERR_ARG;
+    Ctx &c = h->c;
+    if (!c.state_set) return MD_ERR_STATE;
+    if (nsteps == 0) return MD_OK;
+    hipStream_t s = as_stream(stream);
+    if (c.B > 1 && c.batched) {
+        launch_batched_steps(c, nsteps, s);
+        c.list_valid = c.density_valid = c.forces_valid = false;
+        return MD_OK;
+    }
+    if (!c.forces_valid) {
+        ensure_density(c, s);
+        launch_force(c, false, false, s);
+        c.forces_valid = true;
+    }
+    int done = 0;
+    if (c.use_graph && nsteps >= c.graph_steps) {
+        if (!c.graph_exec || c.graph_len != c.graph_steps) {
+            int rc = capture_steps(c, c.graph_steps);
+            if (rc != MD_OK) return rc;
+        }
+        for (; done + c.graph_len <= nsteps; done += c.graph_len)
+            HIP_TRY(hipGraphLaunch(c.graph_exec, s));
+    }
+    for (; done < nsteps; ++done) {
+        launch_kick_drift(c, s);
+        launch_build(c, true, s);
+        launch_density(c, s);
+        launch_force(c, false, true, s);
+        launch_step_end(c, s);
+    }
+    c.list_valid = c.density_valid = c.forces_valid = true;
+    return MD_OK;
+}
+
+int md_kinetic(md_ctx *h, double *ke_box, void *stream)
+{
+    if (!h || !ke_box) return MD_ERR_ARG;
+    if (!h->c.state_set) return MD_ERR_STATE;
+    launch_box_sums(h->c, 1, ke_box, as_stream(stream));
+    return MD_OK;
+}
+
+int md_get_neighbors(md_ctx *h, int32_t *counts, int32_t *ids, int32_t max_cols, void *stream)
+{
+    if (!h || !counts || !ids || max_cols < 1) return MD_ERR_ARG;
+    Ctx &c = h->c;
+    if (!c.state_set) return MD_ERR_STATE;
+    hipStream_t s = as_stream(stream);
+    ensure_list(c, s);
+    launch_get_neighbors(c, counts, ids, max_cols, s);
+    HIP_TRY(hipStreamSynchronize(s));
+    return MD_OK;
+}
+
+int md_max_neighbors(const md_ctx *h, int32_t *out)
+{
+    if (!h || !out) return MD_ERR_ARG;
+    *out = h->c.nl.mn;
+    return MD_OK;
+}
+
+int md_set_max_neighbors(md_ctx *h, int32_t mn)
+{
+    if (!h || mn < 1) return MD_ERR_ARG;
+    Ctx &c = h->c;
+    HIP_TRY(hipDeviceSynchronize());
+    auto it = std::find(c.allocs.begin(), c.allocs.end(), (void *)c.nl.idx);
+    if (it != c.allocs.end()) {
+        (void)hipFree(*it);
+        c.allocs.erase(it);
+    }
+    c.nl.idx = nullptr;
+    int rc = alloc_list(c, mn);
+    if (rc != MD_OK) return rc;
+    graph_reset(c);
+    c.list_valid = c.density_valid = c.forces_valid = false;
+    if (c.B > 1) {
+        rc = batched_prepare(c);
+        if (rc != MD_OK) return rc;
+    }
+    return MD_OK;
+}
+
+int md_status(md_ctx *h, void *stream, uint32_t *flags, int64_t *counters)
+{
+    if (!h) return MD_ERR_ARG;
+    Ctx &c = h->c;
+    HIP_TRY(hipStreamSynchronize(as_stream(stream)));
+    unsigned w[8];
+    HIP_TRY(hipMemcpy(w, c.dev.flags, sizeof(w), hipMemcpyDeviceToHost));
+    if (flags) *flags = w[0];
+    if (counters) {
+        counters[0] = ((int64_t)w[4] << 32) | w[2];
+        counters[1] = ((int64_t)w[5] << 32) | w[3];
+    }
+    HIP_TRY(hipMemset(c.dev.flags, 0, sizeof(unsigned)));
+    HIP_TRY(hipDeviceSynchronize());
+    return MD_OK;
+}
+
+int md_adjoint(md_ctx *h, const double *g, const double *e, double *gtheta, void *stream)
+{
+    if (!h || !g || !e || !gtheta) return MD_ERR_ARG;
+    Ctx &c = h->c;
+    if (c.kind_user != MD_POT_BSPLINE) return MD_ERR_ARG;
+    if (!c.state_set) return MD_ERR_STATE;
+    hipStream_t s = as_stream(stream);
+    ensure_density(c, s);
+    launch_adjoint(c, g, e, gtheta, s);
+    return MD_OK;
+}
+
+int md_set_option(md_ctx *h, int32_t key, int64_t v)
+{
+    if (!h) return MD_ERR_ARG;
+    Ctx &c = h->c;
+    switch (key) {
+    case MD_OPT_BATCHED:
+        if (v && c.B < 2) return MD_ERR_ARG;
+        c.batched = v != 0;
+        return MD_OK;
+    case MD_OPT_BATCH_BLOCK:
+        if (v != 256 && v != 512 && v != 1024) return MD_ERR_ARG;
+        c.batch_block = (int)v;
+        return MD_OK;
+    case MD_OPT_USE_GRAPH:
+        c.use_graph = v != 0;
+        return MD_OK;
+    case MD_OPT_GRAPH_STEPS:
+        if (v < 1 || v > 1024) return MD_ERR_ARG;
+        c.graph_steps = (int)v;
+        graph_reset(c);
+        return MD_OK;
+    }
+    return MD_ERR_ARG;
+}
+
+int md_get_option(const md_ctx *h, int32_t key, int64_t *v)
+{
+    if (!h || !v) return MD_ERR_ARG;
+    const Ctx &c = h->c;
+    switch (key) {
+    case MD_OPT_BATCHED: *v = c.batched; return MD_OK;
+    case MD_OPT_BATCH_BLOCK: *v = c.batch_block; return MD_OK;
+    case MD_OPT_USE_GRAPH: *v = c.use_graph; return MD_OK;
+    case MD_OPT_GRAPH_STEPS: *v = c.graph_steps; return MD_OK;
+    }
+    return MD_ERR_ARG;
+}
+
+}  // extern "C"

@@ -1,0 +1,151 @@
+// Internal declarations shared by the host ABI (md_api.hip) and the kernel
+// files of libmd.so.  Nothing here is part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/md.h"
+
+namespace mdk {
+
+constexpr int kBlock = 256;        // threads per workgroup of the per-atom kernels
+constexpr int kChunk = 4096;       // atoms per partial sum of the energy reductions
+
+// Per-interval cubic table on a uniform grid: c[4*m + {0,1,2,3}] = a, b, c, d.
+struct Table {
+    const double *c;
+    int n;
+    double lo, hi, inv_h;
+};
+
+// Potential as the kernels see it.  B-spline potentials are converted to
+// per-interval tables on the device and evaluated as kind MD_POT_SPLINE.
+struct Pot {
+    int kind;
+    double rc, rc2;
+    double c, d, c0, c1, c2, A;        // Finnis-Sinclair
+    double av, bv, af, bf;             // SMTB: V = exp(av r + bv), rho = exp(af r + bf)
+    Table tab[3];                      // V(r), rho(r), F(rho)
+};
+
+// Atom state in sorted (cell) order, structure of arrays.
+struct State {
+    double *x, *y, *z, *vx, *vy, *vz, *fx, *fy, *fz, *xr, *yr, *zr;
+    int *id;                           // original index of each sorted slot
+    double *rho, *Fp, *Femb, *eat;     // density, F'(rho), F(rho), per-atom energy
+};
+
+// Per-box geometry (device arrays of length B, box_of of length N).
+struct Boxes {
+    const double *L, *invL, *rl2, *thr2;
+    const int *nc, *cell_off, *atom_off, *box_of;
+};
+
+// Scratch of the list build.
+struct Build {
+    double *sx, *sy, *sz, *svx, *svy, *svz;
+    int *sid;
+    int *cell_of, *slot, *cell_count, *cell_start, *tmp, *perm;
+    int n_cells;
+};
+
+struct NList {
+    int *count;                        // [N]
+    int *idx;                          // [MN][N], column major (slot-fastest)
+    int mn;
+};
+
+// Device words: flags[0] status bits, flags[1] rebuild request,
+// flags[2] builds (low), flags[3] steps (low), flags[4] builds (high), flags[5] steps (high).
+struct Dev {
+    unsigned *flags;
+};
+
+struct Ctx;
+
+// Launchers (md_kernels.hip).
+void launch_set_state(Ctx &c, const double *pos, const double *vel, hipStream_t s);
+void launch_get_state(Ctx &c, double *pos, double *vel, hipStream_t s);
+void launch_build(Ctx &c, bool gated, hipStream_t s);
+void launch_density(Ctx &c, hipStream_t s);
+void launch_embed(Ctx &c, hipStream_t s);
+void launch_force(Ctx &c, bool energy, bool kick, hipStream_t s);
+void launch_kick_drift(Ctx &c, hipStream_t s);
+void launch_step_end(Ctx &c, hipStream_t s);
+void launch_scatter_scalar(Ctx &c, const double *src, double *dst, hipStream_t s);
+void launch_scatter_vec3(Ctx &c, const double *sx, const double *sy, const double *sz,
+                         double *dst, hipStream_t s);
+void launch_box_sums(Ctx &c, int what, double *out, hipStream_t s);
+void launch_get_neighbors(Ctx &c, int32_t *counts, int32_t *ids, int32_t max_cols,
+                          hipStream_t s);
+void launch_bspline_tables(Ctx &c, const double *theta, hipStream_t s);
+void launch_fill_u32(unsigned *p, int n, unsigned v, hipStream_t s);
+
+// Form (2), md_batched.hip.
+int batched_prepare(Ctx &c);
+void launch_batched_steps(Ctx &c, int nsteps, hipStream_t s);
+// Form (3), md_adjoint.hip.
+void launch_adjoint(Ctx &c, const double *g, const double *e, double *gtheta, hipStream_t s);
+
+struct Ctx {
+    int device = 0;
+    int64_t N = 0;
+    int B = 0;
+    double mass = 0, dt = 0, skin = 0;
+    Pot pot{};
+    int kind_user = 0;                 // kind given at creation (BSPLINE stays BSPLINE here)
+    int n_theta = 0;                   // B-spline coefficients per function
+    double theta_lo[3]{}, theta_hi[3]{};
+    std::vector<int> tab_len;          // doubles per table on the device
+    double *tables = nullptr;          // device, 3 tables back to back
+    double *theta = nullptr;           // device copy of B-spline coefficients [3K]
+
+    // host mirrors of the box geometry
+    std::vector<int64_t> box_off;
+    std::vector<double> box_len, box_rlist;
+    std::vector<int> box_nc, box_cell_off;
+    double *d_boxd = nullptr;          // L | invL | rl2 | thr2, each [B]
+    int *d_boxi = nullptr;             // nc | cell_off | atom_off(B+1) | box_of(N)
+    Boxes bx{};
+
+    State st{};
+    Build bd{};
+    NList nl{};
+    Dev dev{};
+
+    // energy reductions
+    int n_chunks = 0;
+    int *d_chunks = nullptr;           // start | end | box_chunk_start(B+1)
+    double *d_partial = nullptr;       // [n_chunks]
+
+    // adjoint scratch
+    double *adj = nullptr;             // sized at first use
+    size_t adj_len = 0;
+
+    // batched persistent kernel (form 2)
+    int batch_block = 256;
+    bool batched = false;
+    void *batch = nullptr;             // opaque, owned by md_batched.hip
+
+    // host-side state machine
+    bool state_set = false, list_valid = false, density_valid = false, forces_valid = false;
+
+    // graph replay of md_step
+    bool use_graph = true;
+    int graph_steps = 8;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_len = 0;
+
+    // allocations to free
+    std::vector<void *> allocs;
+};
+
+}  // namespace mdk
+
+struct md_ctx {
+    mdk::Ctx c;
+};

@@ -1,0 +1,768 @@
+// Per-atom kernels of the many-body MD force path on gfx950 (CDNA4).
+//
+// Layout: every per-atom array is structure-of-arrays FP64 in cell-sorted
+// order, so that a 64-lane wavefront reads 64 consecutive atoms (coalesced)
+// and the neighbours of those atoms lie in a few nearby cells (cache
+// friendly gathers).  The neighbour list is stored slot-fastest,
+// idx[n * N + i], so the n-th neighbour of 64 consecutive atoms is one
+// coalesced 256-byte read.  Lists are full (each pair stored twice): the
+// force on atom i is gathered by the thread of atom i alone, with no
+// scatter and no floating-point atomics, which makes every pass
+// deterministic.
+//
+// Passes follow Hou et al.: density (Fig. 5) with the embedding of
+// Section 4 fused into its epilogue, then force (Fig. 6, eq. 3), with the
+// cutoff re-checked for every listed pair (the list radius exceeds rc by
+// the skin).  Binning and the counting sort replace the host-side linked
+// lists and sort of Section 3.2; the list build scans the (deduplicated)
+// 27-cell stencil of Fig. 3.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "md_internal.h"
+
+namespace mdk {
+
+namespace {
+
+constexpr int kXcds = 8;
+
+// Workgroups are dispatched to the 8 XCDs round robin.  Renumber them so
+// that each XCD works on one contiguous eighth of the (cell-sorted) atoms;
+// the neighbour gathers of a workgroup then mostly hit its own XCD's L2.
+__device__ __forceinline__ int xcd_block(int b, int G)
+{
+    int q = G / kXcds, r = G % kXcds, k = b % kXcds, w = b / kXcds;
+    return (k < r) ? k * (q + 1) + w : r * (q + 1) + (k - r) * q + w;
+}
+
+__device__ __forceinline__ int atom_index()
+{
+    return xcd_block((int)blockIdx.x, (int)gridDim.x) * (int)blockDim.x + (int)threadIdx.x;
+}
+
+// Minimum image of a separation component: d - L * rint(d / L).  For the
+// separations that can be listed (|d| < L/2 after the correction) this
+// equals subtracting or adding L once, exactly.
+__device__ __forceinline__ double min_image(double d, double L, double invL)
+{
+    return fma(-L, rint(d * invL), d);
+}
+
+// ---------------------------------------------------------------- potential
+
+__device__ __forceinline__ void table_eval(const Table &t, double x, double &s, double &ds,
+                                           unsigned &bad)
+{
+    double u = (x - t.lo) * t.inv_h;
+    double fm = floor(u);
+    int m = (int)fm;
+    if (!(x >= t.lo && x <= t.hi)) bad |= MD_FLAG_TABLE_RANGE;
+    m = m < 0 ? 0 : (m > t.n - 1 ? t.n - 1 : m);
+    double tt = u - (double)m;
+    const double2 *p = reinterpret_cast<const double2 *>(t.c + 4 * m);
+    double2 ab = p[0], cd = p[1];
+    s = fma(tt, fma(tt, fma(tt, cd.y, cd.x), ab.y), ab.x);
+    ds = fma(tt, fma(tt, 3.0 * cd.y, 2.0 * cd.x), ab.y) * t.inv_h;
+}
+
+// Density contribution rho(r).
+template <int KIND>
+__device__ __forceinline__ double dens(const Pot &p, double r, unsigned &bad)
+{
+    if constexpr (KIND == MD_POT_FS) {
+        double u = r - p.d;
+        return r < p.d ? u * u : 0.0;
+    } else if constexpr (KIND == MD_POT_SMTB) {
+        return exp(fma(p.af, r, p.bf));
+    } else {
+        double s, ds;
+        table_eval(p.tab[1], r, s, ds, bad);
+        return s;
+    }
+}
+
+// rho'(r), V(r), V'(r).
+template <int KIND>
+__device__ __forceinline__ void pair_terms(const Pot &p, double r, double &dfr, double &v,
+                                           double &dv, unsigned &bad)
+{
+    if constexpr (KIND == MD_POT_FS) {
+        double u = r - p.d;
+        dfr = r < p.d ? 2.0 * u : 0.0;
+        double w = r - p.c;
+        double poly = fma(r, fma(r, p.c2, p.c1), p.c0);
+        double dpoly = fma(2.0 * p.c2, r, p.c1);
+        bool in = r < p.c;
+        v = in ? w * w * poly : 0.0;
+        dv = in ? w * fma(w, dpoly, 2.0 * poly) : 0.0;
+    } else if constexpr (KIND == MD_POT_SMTB) {
+        double ef = exp(fma(p.af, r, p.bf));
+        double ev = exp(fma(p.av, r, p.bv));
+        dfr = p.af * ef;
+        v = ev;
+        dv = p.av * ev;
+    } else {
+        double s;
+        table_eval(p.tab[1], r, s, dfr, bad);
+        table_eval(p.tab[0], r, v, dv, bad);
+    }
+}
+
+// F(rho), F'(rho), F''(rho).
+template <int KIND>
+__device__ __forceinline__ void embed(const Pot &p, double rho, double &F, double &Fp,
+                                      unsigned &bad)
+{
+    if constexpr (KIND == MD_POT_FS || KIND == MD_POT_SMTB) {
+        double A = (KIND == MD_POT_FS) ? p.A : 1.0;
+        if (rho > 0.0) {
+            double s = sqrt(rho);
+            F = -A * s;
+            Fp = -0.5 * A / s;
+        } else {
+            F = 0.0;
+            Fp = 0.0;
+        }
+    } else {
+        table_eval(p.tab[2], rho, F, Fp, bad);
+    }
+}
+
+template <bool MULTI>
+__device__ __forceinline__ void box_geom(const Boxes &bx, int i, double L1, double invL1,
+                                         double &L, double &invL)
+{
+    if constexpr (MULTI) {
+        int b = bx.box_of[i];
+        L = bx.L[b];
+        invL = bx.invL[b];
+    } else {
+        L = L1;
+        invL = invL1;
+    }
+}
+
+__device__ __forceinline__ void raise_flags(unsigned *flags, unsigned bad)
+{
+    if (bad) atomicOr(flags, bad);
+}
+
+// ---------------------------------------------------------------- state I/O
+
+__global__ void k_set_state(int N, const double *__restrict__ pos, const double *__restrict__ vel,
+                            State st)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    st.x[i] = pos[3 * (size_t)i];
+    st.y[i] = pos[3 * (size_t)i + 1];
+    st.z[i] = pos[3 * (size_t)i + 2];
+    st.vx[i] = vel ? vel[3 * (size_t)i] : 0.0;
+    st.vy[i] = vel ? vel[3 * (size_t)i + 1] : 0.0;
+    st.vz[i] = vel ? vel[3 * (size_t)i + 2] : 0.0;
+    st.id[i] = i;
+}
+
+__global__ void k_get_state(int N, State st, double *__restrict__ pos, double *__restrict__ vel)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    size_t o = 3 * (size_t)st.id[i];
+    if (pos) {
+        pos[o] = st.x[i];
+        pos[o + 1] = st.y[i];
+        pos[o + 2] = st.z[i];
+    }
+    if (vel) {
+        vel[o] = st.vx[i];
+        vel[o + 1] = st.vy[i];
+        vel[o + 2] = st.vz[i];
+    }
+}
+
+__global__ void k_scatter_scalar(int N, const int *__restrict__ id, const double *__restrict__ src,
+                                 double *__restrict__ dst)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) dst[id[i]] = src[i];
+}
+
+__global__ void k_scatter_vec3(int N, const int *__restrict__ id, const double *__restrict__ sx,
+                               const double *__restrict__ sy, const double *__restrict__ sz,
+                               double *__restrict__ dst)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    size_t o = 3 * (size_t)id[i];
+    dst[o] = sx[i];
+    dst[o + 1] = sy[i];
+    dst[o + 2] = sz[i];
+}
+
+__global__ void k_fill_u32(unsigned *p, int n, unsigned v)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------- list build
+
+// Build kernels run unconditionally (gate == nullptr) or only when the device
+// rebuild request is set (inside replayed steps).
+__device__ __forceinline__ bool skip(const unsigned *gate) { return gate && gate[1] == 0u; }
+
+__global__ void k_clear_cells(const unsigned *gate, int C, int *cell_count)
+{
+    if (skip(gate)) return;
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < C) cell_count[c] = 0;
+}
+
+// Cell of a wrapped coordinate along one axis.
+__device__ __forceinline__ int cell_coord(double x, double ncL, int nc)
+{
+    int c = (int)(x * ncL);
+    return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
+__device__ __forceinline__ double wrap1(double x, double L)
+{
+    while (x < 0.0) x += L;
+    while (x >= L) x -= L;
+    return x;
+}
+
+// a1: wrap into the box, find the cell, count atoms per cell.
+__global__ void k_bin(const unsigned *gate, int N, State st, Boxes bx, Build bd, unsigned *flags)
+{
+    if (skip(gate)) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int b = bx.box_of[i];
+    double L = bx.L[b];
+    int nc = bx.nc[b];
+    double x = st.x[i], y = st.y[i], z = st.z[i];
+    if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
+        atomicOr(flags, (unsigned)MD_FLAG_NONFINITE);
+        x = y = z = 0.0;
+    }
+    x = wrap1(x, L);
+    y = wrap1(y, L);
+    z = wrap1(z, L);
+    st.x[i] = x;
+    st.y[i] = y;
+    st.z[i] = z;
+    double ncL = nc * bx.invL[b];
+    int cx = cell_coord(x, ncL, nc), cy = cell_coord(y, ncL, nc), cz = cell_coord(z, ncL, nc);
+    int cell = bx.cell_off[b] + (cz * nc + cy) * nc + cx;
+    bd.cell_of[i] = cell;
+    bd.slot[i] = atomicAdd(&bd.cell_count[cell], 1);
+}
+
+// Exclusive scan of the per-cell counts (one workgroup of 1024 threads).
+__global__ __launch_bounds__(1024) void k_scan(const unsigned *gate, int C,
+                                               const int *__restrict__ cnt, int *__restrict__ start)
+{
+    if (skip(gate)) return;
+    __shared__ int part[1024];
+    int t = threadIdx.x;
+    int per = (C + 1023) / 1024;
+    int lo = t * per, hi = min(C, lo + per);
+    int s = 0;
+    for (int c = lo; c < hi; ++c) s += cnt[c];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - s;
+    for (int c = lo; c < hi; ++c) {
+        start[c] = run;
+        run += cnt[c];
+    }
+    if (t == 1023) start[C] = part[1023];
+}
+
+// a2 (first half): place every atom in its cell's segment (order inside a
+// cell is not yet deterministic).
+__global__ void k_scatter(const unsigned *gate, int N, Build bd)
+{
+    if (skip(gate)) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    bd.tmp[bd.cell_start[bd.cell_of[i]] + bd.slot[i]] = i;
+}
+
+// a2 (second half): order each cell by original index.  The rank of an atom
+// is the number of atoms of its cell with a smaller original index.
+__global__ void k_rank(const unsigned *gate, int N, State st, Build bd)
+{
+    if (skip(gate)) return;
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N) return;
+    int p = bd.tmp[q];
+    int c = bd.cell_of[p];
+    int s = bd.cell_start[c], e = bd.cell_start[c + 1];
+    int mine = st.id[p];
+    int rank = 0;
+    for (int k = s; k < e; ++k) rank += st.id[bd.tmp[k]] < mine;
+    bd.perm[s + rank] = p;
+}
+
+__global__ void k_gather(const unsigned *gate, int N, State st, Build bd)
+{
+    if (skip(gate)) return;
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N) return;
+    int p = bd.perm[q];
+    bd.sx[q] = st.x[p];
+    bd.sy[q] = st.y[p];
+    bd.sz[q] = st.z[p];
+    bd.svx[q] = st.vx[p];
+    bd.svy[q] = st.vy[p];
+    bd.svz[q] = st.vz[p];
+    bd.sid[q] = st.id[p];
+}
+
+__global__ void k_commit(const unsigned *gate, int N, State st, Build bd)
+{
+    if (skip(gate)) return;
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N) return;
+    double x = bd.sx[q], y = bd.sy[q], z = bd.sz[q];
+    st.x[q] = x;
+    st.y[q] = y;
+    st.z[q] = z;
+    st.xr[q] = x;
+    st.yr[q] = y;
+    st.zr[q] = z;
+    st.vx[q] = bd.svx[q];
+    st.vy[q] = bd.svy[q];
+    st.vz[q] = bd.svz[q];
+    st.id[q] = bd.sid[q];
+}
+
+// Distinct cells {c-1, c, c+1} modulo nc along one axis.
+__device__ __forceinline__ int stencil_1d(int c, int nc, int out[3])
+{
+    if (nc == 1) {
+        out[0] = 0;
+        return 1;
+    }
+    if (nc == 2) {
+        out[0] = 0;
+        out[1] = 1;
+        return 2;
+    }
+    out[0] = c == 0 ? nc - 1 : c - 1;
+    out[1] = c;
+    out[2] = c == nc - 1 ? 0 : c + 1;
+    return 3;
+}
+
+// a3: full list of slot i.  r^2 = (dx*dx + dy*dy) + dz*dz with separate
+// roundings (no contraction) so that membership is reproducible exactly.
+__global__ __launch_bounds__(kBlock) void k_nlist(const unsigned *gate, int N, State st, Boxes bx,
+                                                  Build bd, NList nl, unsigned *flags)
+{
+#pragma clang fp contract(off)
+    if (skip(gate)) return;
+    int i = atom_index();
+    if (i >= N) return;
+    int b = bx.box_of[i];
+    double L = bx.L[b], invL = bx.invL[b], rl2 = bx.rl2[b];
+    int nc = bx.nc[b], coff = bx.cell_off[b];
+    double xi = st.x[i], yi = st.y[i], zi = st.z[i];
+    double ncL = nc * invL;
+    int sx[3], sy[3], sz[3];
+    int kx = stencil_1d(cell_coord(xi, ncL, nc), nc, sx);
+    int ky = stencil_1d(cell_coord(yi, ncL, nc), nc, sy);
+    int kz = stencil_1d(cell_coord(zi, ncL, nc), nc, sz);
+    int n = 0;
+    const int mn = nl.mn;
+    int *out = nl.idx + i;
+    for (int a = 0; a < kz; ++a)
+        for (int bb = 0; bb < ky; ++bb)
+            for (int c = 0; c < kx; ++c) {
+                int cell = coff + (sz[a] * nc + sy[bb]) * nc + sx[c];
+                int s = bd.cell_start[cell], e = bd.cell_start[cell + 1];
+                for (int j = s; j < e; ++j) {
+                    if (j == i) continue;
+                    double dx = st.x[j] - xi;
+                    double dy = st.y[j] - yi;
+                    double dz = st.z[j] - zi;
+                    dx = dx - rint(dx * invL) * L;
+                    dy = dy - rint(dy * invL) * L;
+                    dz = dz - rint(dz * invL) * L;
+                    double r2 = (dx * dx + dy * dy) + dz * dz;
+                    if (r2 < rl2) {
+                        if (n < mn) out[(size_t)n * N] = j;
+                        ++n;
+                    }
+                }
+            }
+    nl.count[i] = n;
+    if (n > mn) atomicOr(flags, (unsigned)MD_FLAG_NLIST_OVERFLOW);
+}
+
+// ---------------------------------------------------------------- passes
+
+// a5 + a6: rho_i over listed neighbours with r < rc, then F and F'.
+template <int KIND, bool MULTI>
+__global__ __launch_bounds__(kBlock) void k_density(int N, State st, Boxes bx, NList nl, Pot pot,
+                                                    double L1, double invL1, unsigned *flags)
+{
+    int i = atom_index();
+    if (i >= N) return;
+    double L, invL;
+    box_geom<MULTI>(bx, i, L1, invL1, L, invL);
+    const double *__restrict__ X = st.x;
+    const double *__restrict__ Y = st.y;
+    const double *__restrict__ Z = st.z;
+    double xi = X[i], yi = Y[i], zi = Z[i];
+    int cnt = min(nl.count[i], nl.mn);
+    const int *__restrict__ lp = nl.idx + i;
+    unsigned bad = 0;
+    double rho = 0.0;
+    for (int n = 0; n < cnt; ++n, lp += N) {
+        int j = *lp;
+        double dx = min_image(X[j] - xi, L, invL);
+        double dy = min_image(Y[j] - yi, L, invL);
+        double dz = min_image(Z[j] - zi, L, invL);
+        double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        if (r2 < pot.rc2) rho += dens<KIND>(pot, sqrt(r2), bad);
+    }
+    double F, Fp;
+    embed<KIND>(pot, rho, F, Fp, bad);
+    st.rho[i] = rho;
+    st.Femb[i] = F;
+    st.Fp[i] = Fp;
+    raise_flags(flags, bad);
+}
+
+template <int KIND>
+__global__ void k_embed(int N, State st, Pot pot, unsigned *flags)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    unsigned bad = 0;
+    double F, Fp;
+    embed<KIND>(pot, st.rho[i], F, Fp, bad);
+    st.Femb[i] = F;
+    st.Fp[i] = Fp;
+    raise_flags(flags, bad);
+}
+
+// a7 (+ second half kick of a8): eq. 3 gathered per atom.
+template <int KIND, bool MULTI, bool ENERGY, bool KICK>
+__global__ __launch_bounds__(kBlock) void k_force(int N, State st, Boxes bx, NList nl, Pot pot,
+                                                  double L1, double invL1, double kick,
+                                                  unsigned *flags)
+{
+    int i = atom_index();
+    if (i >= N) return;
+    double L, invL;
+    box_geom<MULTI>(bx, i, L1, invL1, L, invL);
+    const double *__restrict__ X = st.x;
+    const double *__restrict__ Y = st.y;
+    const double *__restrict__ Z = st.z;
+    const double *__restrict__ FP = st.Fp;
+    double xi = X[i], yi = Y[i], zi = Z[i];
+    double fpi = FP[i];
+    int cnt = min(nl.count[i], nl.mn);
+    const int *__restrict__ lp = nl.idx + i;
+    unsigned bad = 0;
+    double ax = 0.0, ay = 0.0, az = 0.0, ep = 0.0;
+    for (int n = 0; n < cnt; ++n, lp += N) {
+        int j = *lp;
+        double dx = min_image(X[j] - xi, L, invL);
+        double dy = min_image(Y[j] - yi, L, invL);
+        double dz = min_image(Z[j] - zi, L, invL);
+        double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        if (r2 < pot.rc2) {
+            double r = sqrt(r2);
+            double dfr, v, dv;
+            pair_terms<KIND>(pot, r, dfr, v, dv, bad);
+            // f_i += [(F'_i + F'_j) rho'(r) + V'(r)] (x_j - x_i) / r
+            double coef = fma(fpi + FP[j], dfr, dv) / r;
+            ax = fma(coef, dx, ax);
+            ay = fma(coef, dy, ay);
+            az = fma(coef, dz, az);
+            if constexpr (ENERGY) ep += v;
+        }
+    }
+    st.fx[i] = ax;
+    st.fy[i] = ay;
+    st.fz[i] = az;
+    if constexpr (ENERGY) st.eat[i] = fma(0.5, ep, st.Femb[i]);
+    if constexpr (KICK) {
+        st.vx[i] = fma(kick, ax, st.vx[i]);
+        st.vy[i] = fma(kick, ay, st.vy[i]);
+        st.vz[i] = fma(kick, az, st.vz[i]);
+    }
+    raise_flags(flags, bad);
+}
+
+// a8 first half: v += (dt/2) a; x += dt v; request a rebuild when an atom has
+// moved more than half the skin since the last build (a4).
+template <bool MULTI>
+__global__ __launch_bounds__(kBlock) void k_kick_drift(int N, State st, Boxes bx, double kick,
+                                                       double dt, double thr2_1, unsigned *flags)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool need = false, bad = false;
+    if (i < N) {
+        double vx = fma(kick, st.fx[i], st.vx[i]);
+        double vy = fma(kick, st.fy[i], st.vy[i]);
+        double vz = fma(kick, st.fz[i], st.vz[i]);
+        double x = fma(dt, vx, st.x[i]);
+        double y = fma(dt, vy, st.y[i]);
+        double z = fma(dt, vz, st.z[i]);
+        st.vx[i] = vx;
+        st.vy[i] = vy;
+        st.vz[i] = vz;
+        st.x[i] = x;
+        st.y[i] = y;
+        st.z[i] = z;
+        double ddx = x - st.xr[i], ddy = y - st.yr[i], ddz = z - st.zr[i];
+        double d2 = fma(ddz, ddz, fma(ddy, ddy, ddx * ddx));
+        double thr2 = MULTI ? bx.thr2[bx.box_of[i]] : thr2_1;
+        need = d2 > thr2;
+        bad = !isfinite(d2);
+    }
+    if (__any(need) && (threadIdx.x & 63) == 0) atomicOr(flags + 1, 1u);
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flags, (unsigned)MD_FLAG_NONFINITE);
+}
+
+// End of a replayed step: count the build if one happened, clear the request.
+__global__ void k_step_end(unsigned *flags)
+{
+    unsigned b = flags[1] ? 1u : 0u;
+    unsigned lo = flags[2] + b;
+    if (lo < flags[2]) flags[4] += 1u;
+    flags[2] = lo;
+    unsigned s = flags[3] + 1u;
+    if (s == 0u) flags[5] += 1u;
+    flags[3] = s;
+    flags[1] = 0u;
+}
+
+__global__ void k_count_build(unsigned *flags)
+{
+    unsigned lo = flags[2] + 1u;
+    if (lo == 0u) flags[4] += 1u;
+    flags[2] = lo;
+}
+
+// ---------------------------------------------------------------- reductions
+
+// Fixed-order sums per box: chunk partials (one workgroup per chunk of at
+// most kChunk atoms of one box) then one thread per box over its chunks.
+__global__ __launch_bounds__(kBlock) void k_chunk_sums(int what, State st, double half_m_over_k,
+                                                       const int *__restrict__ cstart,
+                                                       const int *__restrict__ cend,
+                                                       double *__restrict__ partial)
+{
+    __shared__ double red[kBlock];
+    int c = blockIdx.x;
+    int s = cstart[c], e = cend[c];
+    double acc = 0.0;
+    for (int i = s + threadIdx.x; i < e; i += blockDim.x) {
+        if (what == 0) {
+            acc += st.eat[i];
+        } else {
+            double vx = st.vx[i], vy = st.vy[i], vz = st.vz[i];
+            acc += half_m_over_k * fma(vz, vz, fma(vy, vy, vx * vx));
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[c] = red[0];
+}
+
+__global__ void k_box_sums(int B, const int *__restrict__ box_chunk, const double *__restrict__ partial,
+                           double *__restrict__ out)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double s = 0.0;
+    for (int c = box_chunk[b]; c < box_chunk[b + 1]; ++c) s += partial[c];
+    out[b] = s;
+}
+
+// ---------------------------------------------------------------- neighbours out
+
+__global__ void k_get_neighbors(int N, State st, NList nl, int32_t *counts, int32_t *ids, int cols)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int o = st.id[i];
+    int cnt = nl.count[i];
+    counts[o] = cnt;
+    int m = min(min(cnt, nl.mn), cols);
+    for (int n = 0; n < m; ++n) ids[(size_t)o * cols + n] = st.id[nl.idx[(size_t)n * N + i]];
+}
+
+// ---------------------------------------------------------------- B-spline
+
+// Uniform cubic B-spline -> per-interval cubic in t: on interval m
+// S(t) = sum_l theta_{m+l} b_l(t) with the standard pieces
+// b0 = (1-t)^3/6, b1 = (3t^3 - 6t^2 + 4)/6, b2 = (-3t^3 + 3t^2 + 3t + 1)/6, b3 = t^3/6.
+__global__ void k_bspline_tables(int K, const double *__restrict__ theta, double *__restrict__ tab)
+{
+    int nint = K - 3;
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= 3 * nint) return;
+    int f = g / nint, m = g % nint;
+    const double *th = theta + f * K + m;
+    double t0 = th[0], t1 = th[1], t2 = th[2], t3 = th[3];
+    double *o = tab + (size_t)f * nint * 4 + 4 * m;
+    o[0] = (t0 + 4.0 * t1 + t2) / 6.0;
+    o[1] = (t2 - t0) / 2.0;
+    o[2] = (t0 - 2.0 * t1 + t2) / 2.0;
+    o[3] = (-t0 + 3.0 * t1 - 3.0 * t2 + t3) / 6.0;
+}
+
+inline int grid_for(int64_t n, int block = kBlock) { return (int)((n + block - 1) / block); }
+
+template <int KIND, bool MULTI>
+void density_t(Ctx &c, hipStream_t s)
+{
+    k_density<KIND, MULTI><<<grid_for(c.N), kBlock, 0, s>>>(
+        (int)c.N, c.st, c.bx, c.nl, c.pot, c.box_len[0], 1.0 / c.box_len[0], c.dev.flags);
+}
+
+template <int KIND, bool MULTI>
+void force_t(Ctx &c, bool energy, bool kick, hipStream_t s)
+{
+    double k = 0.5 * c.dt * (1.602176634e-19 / 1.66053906660e-27 * 1e-10) / c.mass;
+    double L = c.box_len[0], iL = 1.0 / c.box_len[0];
+    int g = grid_for(c.N);
+    int N = (int)c.N;
+    if (energy && kick)
+        k_force<KIND, MULTI, true, true><<<g, kBlock, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.dev.flags);
+    else if (energy)
+        k_force<KIND, MULTI, true, false><<<g, kBlock, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.dev.flags);
+    else if (kick)
+        k_force<KIND, MULTI, false, true><<<g, kBlock, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.dev.flags);
+    else
+        k_force<KIND, MULTI, false, false><<<g, kBlock, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.dev.flags);
+}
+
+}  // namespace
+
+// Acceleration unit (eV/Angstrom)/amu -> Angstrom/fs^2.
+static constexpr double kKappa = 1.602176634e-19 / 1.66053906660e-27 * 1e-10;
+
+void launch_fill_u32(unsigned *p, int n, unsigned v, hipStream_t s)
+{
+    k_fill_u32<<<grid_for(n), kBlock, 0, s>>>(p, n, v);
+}
+
+void launch_set_state(Ctx &c, const double *pos, const double *vel, hipStream_t s)
+{
+    k_set_state<<<grid_for(c.N), kBlock, 0, s>>>((int)c.N, pos, vel, c.st);
+}
+
+void launch_get_state(Ctx &c, double *pos, double *vel, hipStream_t s)
+{
+    k_get_state<<<grid_for(c.N), kBlock, 0, s>>>((int)c.N, c.st, pos, vel);
+}
+
+void launch_build(Ctx &c, bool gated, hipStream_t s)
+{
+    const unsigned *gate = gated ? c.dev.flags : nullptr;
+    int N = (int)c.N;
+    int C = c.bd.n_cells;
+    k_clear_cells<<<grid_for(C), kBlock, 0, s>>>(gate, C, c.bd.cell_count);
+    k_bin<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.st, c.bx, c.bd, c.dev.flags);
+    k_scan<<<1, 1024, 0, s>>>(gate, C, c.bd.cell_count, c.bd.cell_start);
+    k_scatter<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.bd);
+    k_rank<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.st, c.bd);
+    k_gather<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.st, c.bd);
+    k_commit<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.st, c.bd);
+    k_nlist<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.st, c.bx, c.bd, c.nl, c.dev.flags);
+    if (!gated) k_count_build<<<1, 1, 0, s>>>(c.dev.flags);
+}
+
+void launch_density(Ctx &c, hipStream_t s)
+{
+    bool multi = c.B > 1;
+    switch (c.pot.kind) {
+    case MD_POT_FS: multi ? density_t<MD_POT_FS, true>(c, s) : density_t<MD_POT_FS, false>(c, s); break;
+    case MD_POT_SMTB: multi ? density_t<MD_POT_SMTB, true>(c, s) : density_t<MD_POT_SMTB, false>(c, s); break;
+    default: multi ? density_t<MD_POT_SPLINE, true>(c, s) : density_t<MD_POT_SPLINE, false>(c, s); break;
+    }
+}
+
+void launch_embed(Ctx &c, hipStream_t s)
+{
+    int g = grid_for(c.N);
+    switch (c.pot.kind) {
+    case MD_POT_FS: k_embed<MD_POT_FS><<<g, kBlock, 0, s>>>((int)c.N, c.st, c.pot, c.dev.flags); break;
+    case MD_POT_SMTB: k_embed<MD_POT_SMTB><<<g, kBlock, 0, s>>>((int)c.N, c.st, c.pot, c.dev.flags); break;
+    default: k_embed<MD_POT_SPLINE><<<g, kBlock, 0, s>>>((int)c.N, c.st, c.pot, c.dev.flags); break;
+    }
+}
+
+void launch_force(Ctx &c, bool energy, bool kick, hipStream_t s)
+{
+    bool multi = c.B > 1;
+    switch (c.pot.kind) {
+    case MD_POT_FS: multi ? force_t<MD_POT_FS, true>(c, energy, kick, s) : force_t<MD_POT_FS, false>(c, energy, kick, s); break;
+    case MD_POT_SMTB: multi ? force_t<MD_POT_SMTB, true>(c, energy, kick, s) : force_t<MD_POT_SMTB, false>(c, energy, kick, s); break;
+    default: multi ? force_t<MD_POT_SPLINE, true>(c, energy, kick, s) : force_t<MD_POT_SPLINE, false>(c, energy, kick, s); break;
+    }
+}
+
+void launch_kick_drift(Ctx &c, hipStream_t s)
+{
+    double k = 0.5 * c.dt * kKappa / c.mass;
+    double h = 0.5 * (c.box_rlist[0] - c.pot.rc);
+    if (c.B > 1)
+        k_kick_drift<true><<<grid_for(c.N), kBlock, 0, s>>>((int)c.N, c.st, c.bx, k, c.dt, 0.0, c.dev.flags);
+    else
+        k_kick_drift<false><<<grid_for(c.N), kBlock, 0, s>>>((int)c.N, c.st, c.bx, k, c.dt, h * h, c.dev.flags);
+}
+
+void launch_step_end(Ctx &c, hipStream_t s) { k_step_end<<<1, 1, 0, s>>>(c.dev.flags); }
+
+void launch_scatter_scalar(Ctx &c, const double *src, double *dst, hipStream_t s)
+{
+    k_scatter_scalar<<<grid_for(c.N), kBlock, 0, s>>>((int)c.N, c.st.id, src, dst);
+}
+
+void launch_scatter_vec3(Ctx &c, const double *sx, const double *sy, const double *sz, double *dst,
+                         hipStream_t s)
+{
+    k_scatter_vec3<<<grid_for(c.N), kBlock, 0, s>>>((int)c.N, c.st.id, sx, sy, sz, dst);
+}
+
+void launch_box_sums(Ctx &c, int what, double *out, hipStream_t s)
+{
+    const int *cs = c.d_chunks, *ce = c.d_chunks + c.n_chunks, *bc = c.d_chunks + 2 * c.n_chunks;
+    k_chunk_sums<<<c.n_chunks, kBlock, 0, s>>>(what, c.st, 0.5 * c.mass / kKappa, cs, ce, c.d_partial);
+    k_box_sums<<<grid_for(c.B), kBlock, 0, s>>>(c.B, bc, c.d_partial, out);
+}
+
+void launch_get_neighbors(Ctx &c, int32_t *counts, int32_t *ids, int32_t max_cols, hipStream_t s)
+{
+    k_get_neighbors<<<grid_for(c.N), kBlock, 0, s>>>((int)c.N, c.st, c.nl, counts, ids, max_cols);
+}
+
+void launch_bspline_tables(Ctx &c, const double *theta, hipStream_t s)
+{
+    int K = c.n_theta;
+    k_bspline_tables<<<grid_for(3 * (K - 3)), kBlock, 0, s>>>(K, theta, c.tables);
+}
+
+}  // namespace mdk

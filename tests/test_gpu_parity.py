@@ -1,0 +1,231 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bars: neighbour rows (sorted, original ids) bit-exact; densities, embedding
+values, forces and energies within 1e-11 normwise relative (max |diff| over
+max |oracle value|); perfect-lattice forces within 1e-12 eV/Angstrom.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1212_6332_amd import md, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    scale = np.abs(b).max()
+    return float(np.abs(a - b).max() / (scale if scale > 0 else 1.0))
+
+
+def gpu_eval(wl, pot=None, **kw):
+    S = md.System.from_workload(wl, pot, **kw)
+    S.set_state(wl.pos, wl.vel)
+    S.build_neighbors()
+    rho = S.density()
+    F, Fp = S.embed()
+    f, e, eb = S.forces()
+    counts, ids = S.neighbors()
+    flags, builds, steps = S.status()
+    out = {k: v.cpu().numpy() for k, v in dict(rho=rho, F=F, Fp=Fp, f=f, e_atom=e, E_box=eb,
+                                                 counts=counts, ids=ids).items()}
+    out["flags"] = flags
+    S.close()
+    return out
+
+
+def oracle_eval(wl, pot=None):
+    pot = O.Pot(pot or wl.pot)
+    n = wl.n_atoms
+    res = {"rho": np.zeros(n), "F": np.zeros(n), "Fp": np.zeros(n), "f": np.zeros((n, 3)),
+           "e_atom": np.zeros(n), "E_box": np.zeros(wl.n_boxes), "rows": [None] * n}
+    for b, s, L in O.boxes(wl):
+        p = O.wrap(wl.pos[s], L)
+        rl = O.rlist(pot.rc, wl.skin, L)
+        count, ids = O.neighbor_list(p, L, rl)
+        r = O.forces(p, L, pot, count, ids)
+        for k in ("rho", "F", "Fp", "f", "e_atom"):
+            res[k][s] = r[k]
+        res["E_box"][b] = r["E"]
+        for i in range(s.stop - s.start):
+            res["rows"][s.start + i] = (ids[i, :count[i]] + s.start).tolist()
+    return res
+
+
+def compare(g, o, tol=TOL):
+    assert g["flags"] == 0
+    for i, row in enumerate(o["rows"]):
+        assert g["counts"][i] == len(row), i
+        assert sorted(g["ids"][i, :g["counts"][i]].tolist()) == row, i
+    for k in ("rho", "F", "Fp", "e_atom", "E_box"):
+        assert rel(g[k], o[k]) <= tol, (k, rel(g[k], o[k]))
+    assert rel(g["f"], o["f"]) <= tol, ("f", rel(g["f"], o["f"]))
+
+
+CASES = {
+    "fs256": lambda: W.fs256(),
+    "smtb864": lambda: W.fcc4m(ncell=6),
+    "smtb1372": lambda: W.fcc4m(ncell=7),          # ragged: not a multiple of the workgroup
+    "spline1024": lambda: W.bcc128k(ncell=8),
+    "spline2662": lambda: W.bcc128k(ncell=11),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_single_box_parity(name):
+    wl = CASES[name]()
+    compare(gpu_eval(wl), oracle_eval(wl))
+
+
+def test_multibox_merged_parity():
+    """Boxes of different sizes in one context (the merged-box scheme)."""
+    wl = W.batch2048(n_boxes=24)
+    compare(gpu_eval(wl), oracle_eval(wl))
+    wa = W.adjoint64(n_boxes=5)
+    tp = wa.extra["target_pot"]
+    compare(gpu_eval(wa, tp), oracle_eval(wa, tp))
+
+
+def test_perfect_lattice_zero_force():
+    for wl in (W.fcc4m(ncell=7), W.fs256(), W.bcc128k(ncell=6)):
+        wl.pos = W.lattice(wl.structure, round(wl.box_len[0, 0] / wl.lattice_const),
+                           wl.lattice_const)
+        g = gpu_eval(wl)
+        assert np.abs(g["f"]).max() <= 1e-12
+        assert np.all(g["counts"] == g["counts"][0])
+
+
+@pytest.mark.parametrize("name,nsample", [("bcc128k", 96), ("fcc4m", 48)])
+def test_full_size_sampled(name, nsample):
+    """Full-size workloads in the configuration the benchmark times, checked on
+    sampled atoms the oracle evaluates one by one."""
+    wl = W.WORKLOADS[name]()
+    L = wl.box_len[0, 0]
+    S = md.System.from_workload(wl)
+    S.set_state(wl.pos, wl.vel)
+    S.build_neighbors()
+    S.density()
+    f, e, eb = S.forces()
+    rho = S.density()
+    counts, ids = S.neighbors()
+    flags, _, _ = S.status()
+    assert flags == 0
+    f, e, rho = f.cpu().numpy(), e.cpu().numpy(), rho.cpu().numpy()
+    counts, ids = counts.cpu().numpy(), ids.cpu().numpy()
+    S.close()
+    rng = np.random.default_rng(7)
+    idx = np.unique(np.concatenate([[0, wl.n_atoms - 1], rng.integers(0, wl.n_atoms, nsample)]))
+    pos = O.wrap(wl.pos, L)
+    ref = O.sample_forces(pos, L, O.Pot(wl.pot), idx)
+    scale = np.abs(ref["f"]).max()
+    assert np.abs(f[idx] - ref["f"]).max() <= TOL * scale
+    assert rel(rho[idx], ref["rho"]) <= TOL
+    assert rel(e[idx], ref["e_atom"]) <= TOL
+    oc, oi = O.sample_list(pos, L, O.rlist(wl.pot.rc, wl.skin, L), idx)
+    for k, i in enumerate(idx):
+        assert counts[i] == oc[k]
+        assert sorted(ids[i, :counts[i]].tolist()) == oi[k, :oc[k]].tolist()
+    # property at any size: the forces sum to zero
+    assert np.abs(f.sum(axis=0)).max() <= 1e-12 * np.abs(f).sum()
+
+
+def test_deterministic_bitwise():
+    wl = W.fcc4m(ncell=7)
+    a, b = gpu_eval(wl), gpu_eval(wl)
+    for k in ("rho", "f", "e_atom", "E_box"):
+        assert np.array_equal(a[k], b[k])
+
+
+def test_input_order_invariance():
+    wl = W.bcc128k(ncell=7)
+    a = gpu_eval(wl)
+    perm = np.random.default_rng(3).permutation(wl.n_atoms)
+    wl2 = W.bcc128k(ncell=7)
+    wl2.pos, wl2.vel = wl.pos[perm], wl.vel[perm]
+    b = gpu_eval(wl2)
+    assert rel(b["f"], a["f"][perm]) <= 1e-13
+    assert rel(b["rho"], a["rho"][perm]) <= 1e-13
+
+
+def test_step_matches_oracle_trajectory():
+    """Velocity Verlet with device-decided rebuilds against the oracle."""
+    wl = W.fs256()
+    L = wl.box_len[0, 0]
+    S = md.System.from_workload(wl)
+    S.set_state(wl.pos, wl.vel)
+    for nsteps in (10, 40):
+        S.set_state(wl.pos, wl.vel)
+        S.step(nsteps)
+        p, v = S.get_state()
+        flags, builds, steps = S.status()
+        assert flags == 0
+        x, vv, ep, ek, nreb = O.vv(wl.pos, wl.vel, L, O.Pot(wl.pot), wl.mass, wl.dt, wl.skin,
+                                   nsteps)
+        d = p.cpu().numpy() - x
+        d -= L * np.round(d / L)
+        assert np.abs(d).max() < 1e-10
+        assert rel(v.cpu().numpy(), vv) < 1e-9
+    S.close()
+
+
+def test_step_energy_conservation():
+    wl = W.fs256()
+    S = md.System.from_workload(wl)
+    S.set_state(wl.pos, wl.vel)
+    _, _, eb0 = S.forces()
+    E0 = float(eb0[0] + S.kinetic()[0])
+    worst = 0.0
+    for _ in range(10):
+        S.step(10)
+        _, _, eb = S.forces()
+        worst = max(worst, abs(float(eb[0] + S.kinetic()[0]) - E0))
+    flags, builds, steps = S.status()
+    assert flags == 0 and steps == 100 and builds >= 2
+    assert worst / wl.n_atoms < 1e-4
+    S.close()
+
+
+def test_graph_replay_equals_direct_launches():
+    wl = W.bcc128k(ncell=8)
+    out = []
+    for use_graph in (1, 0):
+        S = md.System.from_workload(wl)
+        S.set_option(md.MD_OPT_USE_GRAPH, use_graph)
+        S.set_state(wl.pos, wl.vel)
+        S.step(37)
+        p, v = S.get_state()
+        out.append((p.cpu().numpy(), v.cpu().numpy(), S.status()))
+        S.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    assert out[0][2] == out[1][2]
+
+
+def test_error_flags():
+    wl = W.fs256()
+    S = md.System.from_workload(wl, max_neighbors=8)
+    S.set_state(wl.pos, wl.vel)
+    S.build_neighbors()
+    flags, _, _ = S.status()
+    assert flags & md.MD_FLAG_NLIST_OVERFLOW
+    S.set_max_neighbors(96)
+    S.set_state(wl.pos, wl.vel)
+    S.forces()
+    assert S.status()[0] == 0
+    pos = wl.pos.copy()
+    pos[5, 1] = np.nan
+    S.set_state(pos, wl.vel)
+    S.build_neighbors()
+    assert S.status()[0] & md.MD_FLAG_NONFINITE
+    S.close()
+    ws = W.bcc128k(ncell=6)
+    t = ws.pot
+    small = W.Potential(t.kind, t.rc, t.params, t.tables, t.lo, (t.hi[0], t.hi[1], 50.0))
+    S = md.System.from_workload(ws, small)
+    S.set_state(ws.pos, ws.vel)
+    S.density()
+    assert S.status()[0] & md.MD_FLAG_TABLE_RANGE
+    S.close()
