@@ -1,17 +1,226 @@
-// Form (3): adjoint of forces and box energies w.r.t. B-spline coefficients.
+// Form (3): vector-Jacobian product of the forces f_i (eq. 3) and per-box
+// energies E_b (eq. 2) with respect to uniform cubic B-spline coefficients
+// of V(r) (phi), rho(r) (f) and F(rho).
+//
+// Varying the three functions at fixed positions in eqs. (2)-(3) gives, with
+// u_ij = (x_i - x_j)/r_ij, c_ij = g_i . u_ij, g_i = dL/df_i, e = dL/dE_b:
+//   s_i      = sum_j f'(r_ij) (g_i - g_j) . u_ij
+//   lambda_i = e F'(rho_i) - F''(rho_i) s_i
+//   dL/dphi_k = sum_{i->j} [ e/2 B_k(r) - B'_k(r) c_ij ]
+//   dL/df_k   = sum_{i->j} [ lambda_i B_k(r) - (F'_i + F'_j) B'_k(r) c_ij ]
+//   dL/dF_k   = sum_i [ e C_k(rho_i) - C'_k(rho_i) s_i ]
+// Every term is gathered by the thread of atom i (full lists), so no atom
+// receives a scatter.  The only reduction is into the 3K coefficients: each
+// lane accumulates its atom's contributions into a private LDS column, the
+// columns of a workgroup are summed in lane order, and the workgroup partials
+// are summed in workgroup order -- a fixed order, so results are bitwise
+// reproducible with no floating-point atomics.  F'(rho) and F''(rho) are
+// re-evaluated from the density, never taken from the forward pass.
 #include <hip/hip_runtime.h>
+
+#include <cmath>
 
 #include "md_internal.h"
 
 namespace mdk {
 
+namespace {
+
+__device__ __forceinline__ double min_image(double d, double L, double invL)
+{
+    return fma(-L, rint(d * invL), d);
+}
+
+// Interval m and local t of x on a table grid (same grid as the B-spline).
+__device__ __forceinline__ void locate(const Table &t, double x, int &m, double &tt)
+{
+    double u = (x - t.lo) * t.inv_h;
+    int k = (int)floor(u);
+    k = k < 0 ? 0 : (k > t.n - 1 ? t.n - 1 : k);
+    m = k;
+    tt = u - (double)k;
+}
+
+// B-spline pieces b_l(t) and db_l/dx = b_l'(t) inv_h on one interval.
+__device__ __forceinline__ void basis(double t, double inv_h, double b[4], double db[4])
+{
+    double s = 1.0 - t;
+    b[0] = s * s * s * (1.0 / 6.0);
+    b[1] = (t * t * (3.0 * t - 6.0) + 4.0) * (1.0 / 6.0);
+    b[2] = (t * (t * (-3.0 * t + 3.0) + 3.0) + 1.0) * (1.0 / 6.0);
+    b[3] = t * t * t * (1.0 / 6.0);
+    db[0] = -0.5 * s * s * inv_h;
+    db[1] = t * (1.5 * t - 2.0) * inv_h;
+    db[2] = (t * (-1.5 * t + 1.0) + 0.5) * inv_h;
+    db[3] = 0.5 * t * t * inv_h;
+}
+
+// Table value, first and second derivative (per-interval cubic).
+__device__ __forceinline__ void table_eval2(const Table &t, double x, double &s, double &ds,
+                                            double &dds)
+{
+    int m;
+    double tt;
+    locate(t, x, m, tt);
+    const double *c = t.c + 4 * m;
+    s = fma(tt, fma(tt, fma(tt, c[3], c[2]), c[1]), c[0]);
+    ds = fma(tt, fma(tt, 3.0 * c[3], 2.0 * c[2]), c[1]) * t.inv_h;
+    dds = fma(6.0 * c[3], tt, 2.0 * c[2]) * t.inv_h * t.inv_h;
+}
+
+__global__ void k_adj_gather(int N, const int *__restrict__ id, const double *__restrict__ g,
+                             double *__restrict__ gs)
+{
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N) return;
+    size_t o = 3 * (size_t)id[q];
+    gs[q] = g[o];
+    gs[N + q] = g[o + 1];
+    gs[2 * N + q] = g[o + 2];
+}
+
+// s_i and lambda_i.
+__global__ __launch_bounds__(kBlock) void k_adj_s(int N, State st, Boxes bx, NList nl, Pot pot,
+                                                  const double *__restrict__ gs,
+                                                  const double *__restrict__ e,
+                                                  double *__restrict__ sv, double *__restrict__ lam)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int b = bx.box_of[i];
+    double L = bx.L[b], invL = bx.invL[b];
+    const double *gx = gs, *gy = gs + N, *gz = gs + 2 * N;
+    double xi = st.x[i], yi = st.y[i], zi = st.z[i];
+    double gxi = gx[i], gyi = gy[i], gzi = gz[i];
+    int cnt = min(nl.count[i], nl.mn);
+    double s = 0.0;
+    for (int n = 0; n < cnt; ++n) {
+        int j = nl.idx[(size_t)n * N + i];
+        double dx = min_image(st.x[j] - xi, L, invL);
+        double dy = min_image(st.y[j] - yi, L, invL);
+        double dz = min_image(st.z[j] - zi, L, invL);
+        double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        if (r2 >= pot.rc2) continue;
+        double r = sqrt(r2);
+        double f, df, ddf;
+        table_eval2(pot.tab[1], r, f, df, ddf);
+        // (g_i - g_j) . u_ij with u_ij = -(dx, dy, dz)/r
+        double proj = fma(gzi - gz[j], dz, fma(gyi - gy[j], dy, (gxi - gx[j]) * dx));
+        s -= df * proj / r;
+    }
+    double F, Fp, Fpp;
+    table_eval2(pot.tab[2], st.rho[i], F, Fp, Fpp);
+    sv[i] = s;
+    lam[i] = e[b] * Fp - Fpp * s;
+}
+
+// Coefficient gradients: W lanes per workgroup, each with an LDS column of 3K.
+template <int W>
+__global__ __launch_bounds__(W) void k_adj_theta(int N, int K, State st, Boxes bx, NList nl,
+                                                 Pot pot, const double *__restrict__ gs,
+                                                 const double *__restrict__ e,
+                                                 const double *__restrict__ sv,
+                                                 const double *__restrict__ lam,
+                                                 double *__restrict__ partial)
+{
+    extern __shared__ double acc[];  // [3K][W]
+    int lane = threadIdx.x;
+    for (int k = 0; k < 3 * K; ++k) acc[k * W + lane] = 0.0;
+    int i = blockIdx.x * W + lane;
+    if (i < N) {
+        int b = bx.box_of[i];
+        double L = bx.L[b], invL = bx.invL[b];
+        double eb = e[b];
+        const double *gx = gs, *gy = gs + N, *gz = gs + 2 * N;
+        double xi = st.x[i], yi = st.y[i], zi = st.z[i];
+        double gxi = gx[i], gyi = gy[i], gzi = gz[i];
+        double lami = lam[i], si = sv[i];
+        double F, fpi, fppi;
+        table_eval2(pot.tab[2], st.rho[i], F, fpi, fppi);
+        int cnt = min(nl.count[i], nl.mn);
+        double bb[4], db[4];
+        for (int n = 0; n < cnt; ++n) {
+            int j = nl.idx[(size_t)n * N + i];
+            double dx = min_image(st.x[j] - xi, L, invL);
+            double dy = min_image(st.y[j] - yi, L, invL);
+            double dz = min_image(st.z[j] - zi, L, invL);
+            double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            if (r2 >= pot.rc2) continue;
+            double r = sqrt(r2);
+            double cij = -fma(gzi, dz, fma(gyi, dy, gxi * dx)) / r;
+            int m;
+            double t;
+            locate(pot.tab[0], r, m, t);
+            basis(t, pot.tab[0].inv_h, bb, db);
+            for (int l = 0; l < 4; ++l)
+                acc[(m + l) * W + lane] += fma(0.5 * eb, bb[l], -db[l] * cij);
+            double Fj, fpj, fppj;
+            table_eval2(pot.tab[2], st.rho[j], Fj, fpj, fppj);
+            locate(pot.tab[1], r, m, t);
+            basis(t, pot.tab[1].inv_h, bb, db);
+            double w = (fpi + fpj) * cij;
+            for (int l = 0; l < 4; ++l)
+                acc[(K + m + l) * W + lane] += fma(lami, bb[l], -db[l] * w);
+        }
+        int m;
+        double t;
+        locate(pot.tab[2], st.rho[i], m, t);
+        basis(t, pot.tab[2].inv_h, bb, db);
+        for (int l = 0; l < 4; ++l) acc[(2 * K + m + l) * W + lane] += fma(eb, bb[l], -db[l] * si);
+    }
+    __syncthreads();
+    for (int k = lane; k < 3 * K; k += W) {
+        double s = 0.0;
+        for (int l = 0; l < W; ++l) s += acc[k * W + l];
+        partial[(size_t)blockIdx.x * 3 * K + k] = s;
+    }
+}
+
+__global__ void k_adj_reduce(int nblk, int K3, const double *__restrict__ partial,
+                             double *__restrict__ out)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K3) return;
+    double s = 0.0;
+    for (int w = 0; w < nblk; ++w) s += partial[(size_t)w * K3 + k];
+    out[k] = s;
+}
+
+}  // namespace
+
+// Lanes per workgroup of the coefficient kernel: 3K W doubles must fit in 64 KiB.
+int adjoint_lanes(int K)
+{
+    for (int w = 32; w >= 8; w /= 2)
+        if ((size_t)3 * K * w * sizeof(double) <= 65536) return w;
+    return 0;
+}
+
+size_t adjoint_scratch_doubles(int64_t N, int K)
+{
+    int w = adjoint_lanes(K);
+    if (w == 0) return 0;
+    size_t nblk = (size_t)((N + w - 1) / w);
+    return 5 * (size_t)N + nblk * 3 * (size_t)K;
+}
+
 void launch_adjoint(Ctx &c, const double *g, const double *e, double *gtheta, hipStream_t s)
 {
-    (void)c;
-    (void)g;
-    (void)e;
-    (void)gtheta;
-    (void)s;
+    int N = (int)c.N, K = c.n_theta, W = adjoint_lanes(K);
+    double *gs = c.adj, *sv = c.adj + 3 * (size_t)N, *lam = c.adj + 4 * (size_t)N;
+    double *partial = c.adj + 5 * (size_t)N;
+    int g1 = (N + kBlock - 1) / kBlock;
+    k_adj_gather<<<g1, kBlock, 0, s>>>(N, c.st.id, g, gs);
+    k_adj_s<<<g1, kBlock, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, gs, e, sv, lam);
+    int nblk = (N + W - 1) / W;
+    size_t lds = (size_t)3 * K * W * sizeof(double);
+    if (W == 32)
+        k_adj_theta<32><<<nblk, 32, lds, s>>>(N, K, c.st, c.bx, c.nl, c.pot, gs, e, sv, lam, partial);
+    else if (W == 16)
+        k_adj_theta<16><<<nblk, 16, lds, s>>>(N, K, c.st, c.bx, c.nl, c.pot, gs, e, sv, lam, partial);
+    else
+        k_adj_theta<8><<<nblk, 8, lds, s>>>(N, K, c.st, c.bx, c.nl, c.pot, gs, e, sv, lam, partial);
+    k_adj_reduce<<<(3 * K + kBlock - 1) / kBlock, kBlock, 0, s>>>(nblk, 3 * K, partial, gtheta);
 }
 
 }  // namespace mdk

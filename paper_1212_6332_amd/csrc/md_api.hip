@@ -171,6 +171,7 @@ void ensure_list(Ctx &c, hipStream_t s)
         launch_build(c, false, s);
         c.list_valid = true;
         c.density_valid = c.forces_valid = false;
+        batched_invalidate(c);
     }
 }
 
@@ -365,6 +366,12 @@ int md_create(const md_system *sys, const md_potential *pot, md_ctx **out)
     }
 
     if ((rc = upload_potential(c, pot, s, true)) != MD_OK) return fail(rc);
+    if (c.kind_user == MD_POT_BSPLINE) {
+        size_t nd = adjoint_scratch_doubles(N, c.n_theta);
+        if (nd == 0) return fail(MD_ERR_ARG);
+        if ((rc = dev_alloc(c, &c.adj, nd)) != MD_OK) return fail(rc);
+        c.adj_len = nd;
+    }
     if (c.B > 1) {
         if ((rc = batched_prepare(c)) != MD_OK) return fail(rc);
     }
@@ -384,6 +391,7 @@ void md_destroy(md_ctx *h)
     }
     (void)hipDeviceSynchronize();
     for (void *p : c.allocs) (void)hipFree(p);
+    batched_release(c);
     delete h;
 }
 
@@ -435,6 +443,7 @@ int md_build_neighbors(md_ctx *h, void *stream)
     launch_build(c, false, as_stream(stream));
     c.list_valid = true;
     c.density_valid = c.forces_valid = false;
+    batched_invalidate(c);
     return MD_OK;
 }
 
@@ -490,9 +499,14 @@ int md_step(md_ctx *h, int nsteps, void *stream)
     hipStream_t s = as_stream(stream);
     if (c.B > 1 && c.batched) {
         launch_batched_steps(c, nsteps, s);
-        c.list_valid = c.density_valid = c.forces_valid = false;
+        c.host_steps += nsteps;
+        // forces in the state arrays match the new positions; the merged-box
+        // list and densities do not
+        c.list_valid = c.density_valid = false;
+        c.forces_valid = true;
         return MD_OK;
     }
+    ensure_list(c, s);
     if (!c.forces_valid) {
         ensure_density(c, s);
         launch_force(c, false, false, s);
@@ -515,6 +529,7 @@ int md_step(md_ctx *h, int nsteps, void *stream)
         launch_step_end(c, s);
     }
     c.list_valid = c.density_valid = c.forces_valid = true;
+    batched_invalidate(c);
     return MD_OK;
 }
 
@@ -577,7 +592,7 @@ int md_status(md_ctx *h, void *stream, uint32_t *flags, int64_t *counters)
     if (flags) *flags = w[0];
     if (counters) {
         counters[0] = ((int64_t)w[4] << 32) | w[2];
-        counters[1] = ((int64_t)w[5] << 32) | w[3];
+        counters[1] = (((int64_t)w[5] << 32) | w[3]) + c.host_steps;
     }
     HIP_TRY(hipMemset(c.dev.flags, 0, sizeof(unsigned)));
     HIP_TRY(hipDeviceSynchronize());
@@ -602,7 +617,7 @@ int md_set_option(md_ctx *h, int32_t key, int64_t v)
     Ctx &c = h->c;
     switch (key) {
     case MD_OPT_BATCHED:
-        if (v && c.B < 2) return MD_ERR_ARG;
+        if (v && !c.batch_feasible) return MD_ERR_ARG;
         c.batched = v != 0;
         return MD_OK;
     case MD_OPT_BATCH_BLOCK:

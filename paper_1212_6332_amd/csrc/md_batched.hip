@@ -1,21 +1,543 @@
-// Form (2): persistent box-per-workgroup stepping of many small boxes.
+// Form (2): many small independent periodic boxes stepped by one persistent
+// kernel.
+//
+// The paper runs many small boxes in one job by merging them into one large
+// box whose cells are offset box by box (Section 4.4).  Here each workgroup
+// takes whole boxes from a queue (largest first) and advances a box through
+// all requested velocity-Verlet steps before taking the next one.  A box's
+// positions (and F'(rho)) stay in LDS for the whole launch; the phases of a
+// step (kick + drift, optional list rebuild, density + embedding, force +
+// kick) are separated by workgroup barriers only, since no box spans two
+// workgroups.  The rebuild (wrap, bin, in-cell order by local index, stencil
+// scan) runs inside the workgroup on LDS data, and each box decides its own
+// rebuilds.  Neighbour rows hold 16-bit local indices, slot-fastest.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
 
 #include "md_internal.h"
 
 namespace mdk {
 
+namespace {
+
+constexpr double kKappa = 1.602176634e-19 / 1.66053906660e-27 * 1e-10;
+constexpr int kMaxSteps = 100;  // steps per launch (bounds one launch's duration)
+
+struct BBox {
+    double L, invL, rl2, thr2;
+    int nc, n, off, ncell;
+};
+
+struct BArgs {
+    State st;
+    const BBox *boxes;
+    const int *order;
+    int B;
+    unsigned *queue;
+    uint16_t *list;   // per box: [mn][n] at off * mn
+    int *count;       // [N]
+    int mn;
+    Pot pot;
+    double kick, dt;
+    int nsteps;
+    int mode;         // bit 0: rebuild every box first; bit 1: compute forces first
+    unsigned *flags;
+    int nmax;
+};
+
+struct Batch {
+    BBox *boxes = nullptr;
+    int *order = nullptr;
+    unsigned *queue = nullptr;
+    uint16_t *list = nullptr;
+    int *count = nullptr;
+    int nmax = 0, cmax = 0, grid = 0;
+    size_t lds = 0;
+    bool list_valid = false;
+};
+
+__device__ __forceinline__ double min_image(double d, double L, double invL)
+{
+    return fma(-L, rint(d * invL), d);
+}
+
+__device__ __forceinline__ double wrap1(double x, double L)
+{
+    while (x < 0.0) x += L;
+    while (x >= L) x -= L;
+    return x;
+}
+
+__device__ __forceinline__ int cell_coord(double x, double ncL, int nc)
+{
+    int c = (int)(x * ncL);
+    return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
+__device__ __forceinline__ void table_eval(const Table &t, double x, double &s, double &ds,
+                                           unsigned &bad)
+{
+    double u = (x - t.lo) * t.inv_h;
+    int m = (int)floor(u);
+    if (!(x >= t.lo && x <= t.hi)) bad |= MD_FLAG_TABLE_RANGE;
+    m = m < 0 ? 0 : (m > t.n - 1 ? t.n - 1 : m);
+    double tt = u - (double)m;
+    const double2 *p = reinterpret_cast<const double2 *>(t.c + 4 * m);
+    double2 ab = p[0], cd = p[1];
+    s = fma(tt, fma(tt, fma(tt, cd.y, cd.x), ab.y), ab.x);
+    ds = fma(tt, fma(tt, 3.0 * cd.y, 2.0 * cd.x), ab.y) * t.inv_h;
+}
+
+template <int KIND>
+__device__ __forceinline__ double dens(const Pot &p, double r, unsigned &bad)
+{
+    if constexpr (KIND == MD_POT_FS) {
+        double u = r - p.d;
+        return r < p.d ? u * u : 0.0;
+    } else if constexpr (KIND == MD_POT_SMTB) {
+        return exp(fma(p.af, r, p.bf));
+    } else {
+        double s, ds;
+        table_eval(p.tab[1], r, s, ds, bad);
+        return s;
+    }
+}
+
+template <int KIND>
+__device__ __forceinline__ void pair_terms(const Pot &p, double r, double &dfr, double &v,
+                                           double &dv, unsigned &bad)
+{
+    if constexpr (KIND == MD_POT_FS) {
+        double u = r - p.d;
+        dfr = r < p.d ? 2.0 * u : 0.0;
+        double w = r - p.c;
+        double poly = fma(r, fma(r, p.c2, p.c1), p.c0);
+        double dpoly = fma(2.0 * p.c2, r, p.c1);
+        bool in = r < p.c;
+        v = in ? w * w * poly : 0.0;
+        dv = in ? w * fma(w, dpoly, 2.0 * poly) : 0.0;
+    } else if constexpr (KIND == MD_POT_SMTB) {
+        double ef = exp(fma(p.af, r, p.bf));
+        double ev = exp(fma(p.av, r, p.bv));
+        dfr = p.af * ef;
+        v = ev;
+        dv = p.av * ev;
+    } else {
+        double s;
+        table_eval(p.tab[1], r, s, dfr, bad);
+        table_eval(p.tab[0], r, v, dv, bad);
+    }
+}
+
+template <int KIND>
+__device__ __forceinline__ double embed_fp(const Pot &p, double rho, unsigned &bad)
+{
+    if constexpr (KIND == MD_POT_FS || KIND == MD_POT_SMTB) {
+        double A = (KIND == MD_POT_FS) ? p.A : 1.0;
+        return rho > 0.0 ? -0.5 * A / sqrt(rho) : 0.0;
+    } else {
+        double F, Fp;
+        table_eval(p.tab[2], rho, F, Fp, bad);
+        return Fp;
+    }
+}
+
+__device__ __forceinline__ int stencil_1d(int c, int nc, int out[3])
+{
+    if (nc == 1) {
+        out[0] = 0;
+        return 1;
+    }
+    if (nc == 2) {
+        out[0] = 0;
+        out[1] = 1;
+        return 2;
+    }
+    out[0] = c == 0 ? nc - 1 : c - 1;
+    out[1] = c;
+    out[2] = c == nc - 1 ? 0 : c + 1;
+    return 3;
+}
+
+template <int KIND, int T>
+__global__ __launch_bounds__(T) void k_batched(BArgs a)
+{
+    extern __shared__ double smem[];
+    const int nmax = a.nmax;
+    double *X = smem, *Y = smem + nmax, *Z = smem + 2 * nmax, *FP = smem + 3 * nmax;
+    // rebuild scratch aliases FP (F' is recomputed after every rebuild)
+    uint16_t *cell_of = reinterpret_cast<uint16_t *>(FP);
+    uint16_t *slot = cell_of + nmax, *tmp = slot + nmax, *srt = tmp + nmax;
+    int *cstart = reinterpret_cast<int *>(smem + 4 * nmax);
+    __shared__ int s_box;
+    __shared__ unsigned s_flag[2];
+    const int tid = threadIdx.x;
+    const Pot &pot = a.pot;
+
+    for (;;) {
+        if (tid == 0) s_box = (int)atomicAdd(a.queue, 1u);
+        __syncthreads();
+        const int k = s_box;
+        __syncthreads();
+        if (k >= a.B) break;
+        const BBox bx = a.boxes[a.order[k]];
+        const int n = bx.n, off = bx.off, nc = bx.nc;
+        const double L = bx.L, invL = bx.invL;
+        double *gx = a.st.x + off, *gy = a.st.y + off, *gz = a.st.z + off;
+        double *vx = a.st.vx + off, *vy = a.st.vy + off, *vz = a.st.vz + off;
+        double *fx = a.st.fx + off, *fy = a.st.fy + off, *fz = a.st.fz + off;
+        double *xr = a.st.xr + off, *yr = a.st.yr + off, *zr = a.st.zr + off;
+        uint16_t *lst = a.list + (size_t)off * a.mn;
+        int *cnt = a.count + off;
+        unsigned bad = 0;
+        for (int i = tid; i < n; i += T) {
+            X[i] = gx[i];
+            Y[i] = gy[i];
+            Z[i] = gz[i];
+        }
+        if (tid < 2) s_flag[tid] = 0u;
+        __syncthreads();
+
+        auto rebuild = [&]() {
+#pragma clang fp contract(off)
+            for (int c = tid; c <= bx.ncell; c += T) cstart[c] = 0;
+            __syncthreads();
+            const double ncL = nc * invL;
+            for (int i = tid; i < n; i += T) {
+                double x = wrap1(X[i], L), y = wrap1(Y[i], L), z = wrap1(Z[i], L);
+                X[i] = x;
+                Y[i] = y;
+                Z[i] = z;
+                int c = (cell_coord(z, ncL, nc) * nc + cell_coord(y, ncL, nc)) * nc +
+                        cell_coord(x, ncL, nc);
+                cell_of[i] = (uint16_t)c;
+                slot[i] = (uint16_t)atomicAdd(&cstart[c], 1);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                int run = 0;
+                for (int c = 0; c < bx.ncell; ++c) {
+                    int t = cstart[c];
+                    cstart[c] = run;
+                    run += t;
+                }
+                cstart[bx.ncell] = run;
+            }
+            __syncthreads();
+            for (int i = tid; i < n; i += T) tmp[cstart[cell_of[i]] + slot[i]] = (uint16_t)i;
+            __syncthreads();
+            // deterministic order inside each cell: ascending local index
+            for (int q = tid; q < n; q += T) {
+                int p = tmp[q], c = cell_of[p];
+                int s = cstart[c], e = cstart[c + 1], rank = 0;
+                for (int m = s; m < e; ++m) rank += tmp[m] < p;
+                srt[s + rank] = (uint16_t)p;
+            }
+            __syncthreads();
+            for (int i = tid; i < n; i += T) {
+                double xi = X[i], yi = Y[i], zi = Z[i];
+                xr[i] = xi;
+                yr[i] = yi;
+                zr[i] = zi;
+                int c = cell_of[i];
+                int cx = c % nc, cy = (c / nc) % nc, cz = c / (nc * nc);
+                int sx[3], sy[3], sz[3];
+                int kx = stencil_1d(cx, nc, sx), ky = stencil_1d(cy, nc, sy),
+                    kz = stencil_1d(cz, nc, sz);
+                int m = 0;
+                for (int u = 0; u < kz; ++u)
+                    for (int v = 0; v < ky; ++v)
+                        for (int w = 0; w < kx; ++w) {
+                            int cc = (sz[u] * nc + sy[v]) * nc + sx[w];
+                            for (int q = cstart[cc]; q < cstart[cc + 1]; ++q) {
+                                int j = srt[q];
+                                if (j == i) continue;
+                                double dx = X[j] - xi, dy = Y[j] - yi, dz = Z[j] - zi;
+                                dx = dx - rint(dx * invL) * L;
+                                dy = dy - rint(dy * invL) * L;
+                                dz = dz - rint(dz * invL) * L;
+                                double r2 = (dx * dx + dy * dy) + dz * dz;
+                                if (r2 < bx.rl2) {
+                                    if (m < a.mn) lst[(size_t)m * n + i] = (uint16_t)j;
+                                    ++m;
+                                }
+                            }
+                        }
+                cnt[i] = m;
+                if (m > a.mn) bad |= MD_FLAG_NLIST_OVERFLOW;
+            }
+            __syncthreads();
+        };
+
+        auto density = [&]() {
+            for (int i = tid; i < n; i += T) {
+                double xi = X[i], yi = Y[i], zi = Z[i];
+                int c = min(cnt[i], a.mn);
+                double rho = 0.0;
+                const uint16_t *lp = lst + i;
+                for (int m = 0; m < c; ++m, lp += n) {
+                    int j = *lp;
+                    double dx = min_image(X[j] - xi, L, invL);
+                    double dy = min_image(Y[j] - yi, L, invL);
+                    double dz = min_image(Z[j] - zi, L, invL);
+                    double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                    if (r2 < pot.rc2) rho += dens<KIND>(pot, sqrt(r2), bad);
+                }
+                FP[i] = embed_fp<KIND>(pot, rho, bad);
+            }
+            __syncthreads();
+        };
+
+        auto force = [&](bool kick) {
+            for (int i = tid; i < n; i += T) {
+                double xi = X[i], yi = Y[i], zi = Z[i], fpi = FP[i];
+                int c = min(cnt[i], a.mn);
+                double ax = 0.0, ay = 0.0, az = 0.0;
+                const uint16_t *lp = lst + i;
+                for (int m = 0; m < c; ++m, lp += n) {
+                    int j = *lp;
+                    double dx = min_image(X[j] - xi, L, invL);
+                    double dy = min_image(Y[j] - yi, L, invL);
+                    double dz = min_image(Z[j] - zi, L, invL);
+                    double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                    if (r2 < pot.rc2) {
+                        double r = sqrt(r2), dfr, v, dv;
+                        pair_terms<KIND>(pot, r, dfr, v, dv, bad);
+                        double coef = fma(fpi + FP[j], dfr, dv) / r;
+                        ax = fma(coef, dx, ax);
+                        ay = fma(coef, dy, ay);
+                        az = fma(coef, dz, az);
+                    }
+                }
+                fx[i] = ax;
+                fy[i] = ay;
+                fz[i] = az;
+                if (kick) {
+                    vx[i] = fma(a.kick, ax, vx[i]);
+                    vy[i] = fma(a.kick, ay, vy[i]);
+                    vz[i] = fma(a.kick, az, vz[i]);
+                }
+            }
+            __syncthreads();
+        };
+
+        if (a.mode & 1) rebuild();
+        if (a.mode & 2) {
+            density();
+            force(false);
+        }
+        for (int s = 0; s < a.nsteps; ++s) {
+            unsigned *flag = &s_flag[s & 1];
+            for (int i = tid; i < n; i += T) {
+                double ux = fma(a.kick, fx[i], vx[i]);
+                double uy = fma(a.kick, fy[i], vy[i]);
+                double uz = fma(a.kick, fz[i], vz[i]);
+                vx[i] = ux;
+                vy[i] = uy;
+                vz[i] = uz;
+                double x = fma(a.dt, ux, X[i]), y = fma(a.dt, uy, Y[i]), z = fma(a.dt, uz, Z[i]);
+                X[i] = x;
+                Y[i] = y;
+                Z[i] = z;
+                double ddx = x - xr[i], ddy = y - yr[i], ddz = z - zr[i];
+                double d2 = fma(ddz, ddz, fma(ddy, ddy, ddx * ddx));
+                if (d2 > bx.thr2) atomicOr(flag, 1u);
+                if (!isfinite(d2)) bad |= MD_FLAG_NONFINITE;
+            }
+            __syncthreads();
+            const bool need = *flag != 0u;
+            // the other flag was last read one step ago; clear it for the next step
+            if (tid == 0) s_flag[(s + 1) & 1] = 0u;
+            if (need) rebuild();
+            density();
+            force(true);
+        }
+        for (int i = tid; i < n; i += T) {
+            gx[i] = X[i];
+            gy[i] = Y[i];
+            gz[i] = Z[i];
+        }
+        if (bad) atomicOr(a.flags, bad);
+        __syncthreads();
+    }
+}
+
+__global__ void k_reset_queue(unsigned *q) { *q = 0u; }
+
+template <int KIND>
+void launch_kind(Ctx &c, const BArgs &a, hipStream_t s)
+{
+    Batch &b = *static_cast<Batch *>(c.batch);
+    switch (c.batch_block) {
+    case 1024: k_batched<KIND, 1024><<<b.grid, 1024, b.lds, s>>>(a); break;
+    case 512: k_batched<KIND, 512><<<b.grid, 512, b.lds, s>>>(a); break;
+    default: k_batched<KIND, 256><<<b.grid, 256, b.lds, s>>>(a); break;
+    }
+}
+
+template <int KIND, int T>
+int occupancy(size_t lds)
+{
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batched<KIND, T>, T, lds) !=
+        hipSuccess)
+        return 0;
+    return blocks;
+}
+
+template <int KIND>
+int occupancy_for(int T, size_t lds)
+{
+    if (T == 1024) return occupancy<KIND, 1024>(lds);
+    if (T == 512) return occupancy<KIND, 512>(lds);
+    return occupancy<KIND, 256>(lds);
+}
+
+template <int KIND, int T>
+void allow_lds(size_t lds)
+{
+    (void)hipFuncSetAttribute((const void *)k_batched<KIND, T>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+}  // namespace
+
 int batched_prepare(Ctx &c)
 {
-    (void)c;
+    Batch *b = static_cast<Batch *>(c.batch);
+    if (!b) {
+        b = new Batch();
+        c.batch = b;
+    }
+    int nmax = 0, cmax = 0;
+    for (int i = 0; i < c.B; ++i) {
+        nmax = std::max<int>(nmax, (int)(c.box_off[i + 1] - c.box_off[i]));
+        cmax = std::max(cmax, c.box_nc[i] * c.box_nc[i] * c.box_nc[i]);
+    }
+    b->nmax = nmax;
+    b->cmax = cmax;
+    b->lds = sizeof(double) * 4 * (size_t)nmax + sizeof(int) * (size_t)(cmax + 2);
+    int max_lds = 0;
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c.device) !=
+        hipSuccess)
+        return MD_ERR_DEVICE;
+    // 16-bit local indices; LDS must hold one box
+    bool feasible = nmax <= 65535 && cmax <= 65535 && b->lds <= (size_t)max_lds;
+    c.batch_feasible = feasible;
+    c.batched = feasible;
+    if (!feasible) return MD_OK;
+    if (b->lds > 65536) {
+        if (c.pot.kind == MD_POT_FS) {
+            allow_lds<MD_POT_FS, 256>(b->lds);
+            allow_lds<MD_POT_FS, 512>(b->lds);
+            allow_lds<MD_POT_FS, 1024>(b->lds);
+        } else if (c.pot.kind == MD_POT_SMTB) {
+            allow_lds<MD_POT_SMTB, 256>(b->lds);
+            allow_lds<MD_POT_SMTB, 512>(b->lds);
+            allow_lds<MD_POT_SMTB, 1024>(b->lds);
+        } else {
+            allow_lds<MD_POT_SPLINE, 256>(b->lds);
+            allow_lds<MD_POT_SPLINE, 512>(b->lds);
+            allow_lds<MD_POT_SPLINE, 1024>(b->lds);
+        }
+    }
+    if (!b->boxes) {
+        int rc = hipMalloc(&b->boxes, sizeof(BBox) * c.B) == hipSuccess &&
+                         hipMalloc(&b->order, sizeof(int) * c.B) == hipSuccess &&
+                         hipMalloc(&b->queue, sizeof(unsigned) * 4) == hipSuccess &&
+                         hipMalloc(&b->count, sizeof(int) * c.N) == hipSuccess
+                     ? MD_OK
+                     : MD_ERR_NOMEM;
+        if (rc != MD_OK) return rc;
+        c.allocs.push_back(b->boxes);
+        c.allocs.push_back(b->order);
+        c.allocs.push_back(b->queue);
+        c.allocs.push_back(b->count);
+        std::vector<BBox> hb(c.B);
+        for (int i = 0; i < c.B; ++i) {
+            double L = c.box_len[i], rl = c.box_rlist[i], half = 0.5 * (rl - c.pot.rc);
+            hb[i] = BBox{L, 1.0 / L, rl * rl, half * half, c.box_nc[i],
+                         (int)(c.box_off[i + 1] - c.box_off[i]), (int)c.box_off[i],
+                         c.box_nc[i] * c.box_nc[i] * c.box_nc[i]};
+        }
+        std::vector<int> order(c.B);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return hb[x].n > hb[y].n; });
+        if (hipMemcpy(b->boxes, hb.data(), sizeof(BBox) * c.B, hipMemcpyHostToDevice) !=
+                hipSuccess ||
+            hipMemcpy(b->order, order.data(), sizeof(int) * c.B, hipMemcpyHostToDevice) !=
+                hipSuccess)
+            return MD_ERR_DEVICE;
+    }
+    // list storage follows the capacity (reallocated with it)
+    if (b->list) {
+        auto it = std::find(c.allocs.begin(), c.allocs.end(), (void *)b->list);
+        if (it != c.allocs.end()) c.allocs.erase(it);
+        (void)hipFree(b->list);
+        b->list = nullptr;
+    }
+    if (hipMalloc(&b->list, sizeof(uint16_t) * (size_t)c.N * c.nl.mn) != hipSuccess)
+        return MD_ERR_NOMEM;
+    c.allocs.push_back(b->list);
+    b->list_valid = false;
     return MD_OK;
+}
+
+void batched_invalidate(Ctx &c)
+{
+    if (c.batch) static_cast<Batch *>(c.batch)->list_valid = false;
+}
+
+void batched_release(Ctx &c)
+{
+    delete static_cast<Batch *>(c.batch);
+    c.batch = nullptr;
 }
 
 void launch_batched_steps(Ctx &c, int nsteps, hipStream_t s)
 {
-    (void)c;
-    (void)nsteps;
-    (void)s;
+    Batch &b = *static_cast<Batch *>(c.batch);
+    int T = c.batch_block;
+    int kind = c.pot.kind;
+    int occ = kind == MD_POT_FS ? occupancy_for<MD_POT_FS>(T, b.lds)
+              : kind == MD_POT_SMTB ? occupancy_for<MD_POT_SMTB>(T, b.lds)
+                                    : occupancy_for<MD_POT_SPLINE>(T, b.lds);
+    int cus = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device);
+    b.grid = std::max(1, std::min(c.B, std::max(1, occ) * std::max(1, cus)));
+    BArgs a{};
+    a.st = c.st;
+    a.boxes = b.boxes;
+    a.order = b.order;
+    a.B = c.B;
+    a.queue = b.queue;
+    a.list = b.list;
+    a.count = b.count;
+    a.mn = c.nl.mn;
+    a.pot = c.pot;
+    a.kick = 0.5 * c.dt * kKappa / c.mass;
+    a.dt = c.dt;
+    a.flags = c.dev.flags;
+    a.nmax = b.nmax;
+    int mode = (b.list_valid ? 0 : 1) | (c.forces_valid ? 0 : 2);
+    for (int done = 0; done < nsteps;) {
+        int k = std::min(kMaxSteps, nsteps - done);
+        a.nsteps = k;
+        a.mode = mode;
+        k_reset_queue<<<1, 1, 0, s>>>(b.queue);
+        if (kind == MD_POT_FS) launch_kind<MD_POT_FS>(c, a, s);
+        else if (kind == MD_POT_SMTB) launch_kind<MD_POT_SMTB>(c, a, s);
+        else launch_kind<MD_POT_SPLINE>(c, a, s);
+        mode = 0;
+        done += k;
+    }
+    b.list_valid = true;
 }
 
 }  // namespace mdk

@@ -87,8 +87,12 @@ void launch_fill_u32(unsigned *p, int n, unsigned v, hipStream_t s);
 // Form (2), md_batched.hip.
 int batched_prepare(Ctx &c);
 void launch_batched_steps(Ctx &c, int nsteps, hipStream_t s);
+void batched_invalidate(Ctx &c);
+void batched_release(Ctx &c);
 // Form (3), md_adjoint.hip.
 void launch_adjoint(Ctx &c, const double *g, const double *e, double *gtheta, hipStream_t s);
+int adjoint_lanes(int K);
+size_t adjoint_scratch_doubles(int64_t N, int K);
 
 struct Ctx {
     int device = 0;
@@ -128,6 +132,8 @@ struct Ctx {
     // batched persistent kernel (form 2)
     int batch_block = 256;
     bool batched = false;
+    bool batch_feasible = false;
+    int64_t host_steps = 0;            // steps taken by the persistent kernel
     void *batch = nullptr;             // opaque, owned by md_batched.hip
 
     // host-side state machine

@@ -1,0 +1,176 @@
+"""Forms (2) and (3) on the GPU against the oracle: the persistent batched
+stepper for many uneven boxes, and the adjoint with respect to B-spline
+coefficients."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1212_6332_amd import md, workloads as W
+from paper_1212_6332_amd.autograd import SplineEAMFunction, force_matching_loss
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def run_batch(wl, nsteps, batched=True, block=256):
+    S = md.System.from_workload(wl)
+    if batched:
+        assert S.get_option(md.MD_OPT_BATCHED) == 1
+        S.set_option(md.MD_OPT_BATCH_BLOCK, block)
+    else:
+        S.set_option(md.MD_OPT_BATCHED, 0)
+    S.set_state(wl.pos, wl.vel)
+    S.step(nsteps)
+    p, v = S.get_state()
+    flags, builds, steps = S.status()
+    out = (p.cpu().numpy(), v.cpu().numpy(), flags, steps)
+    S.close()
+    return out
+
+
+def oracle_batch(wl, nsteps):
+    pot = O.Pot(wl.pot)
+    P, V = np.zeros_like(wl.pos), np.zeros_like(wl.vel)
+    for b, s, L in O.boxes(wl):
+        x, v, *_ = O.vv(wl.pos[s], wl.vel[s], L, pot, wl.mass, wl.dt, wl.skin, nsteps,
+                        energies=False)
+        P[s], V[s] = x, v
+    return P, V
+
+
+def wrapped_diff(p, q, wl):
+    d = p - q
+    L = np.repeat(wl.box_len[:, 0], np.diff(wl.box_offset))[:, None]
+    return d - L * np.round(d / L)
+
+
+@pytest.mark.parametrize("block", [256, 512, 1024])
+def test_batched_matches_oracle(block):
+    wl = W.batch2048(n_boxes=40)
+    nsteps = 25
+    p, v, flags, steps = run_batch(wl, nsteps, block=block)
+    assert flags == 0 and steps == nsteps
+    P, V = oracle_batch(wl, nsteps)
+    assert np.abs(wrapped_diff(p, P, wl)).max() < 1e-10
+    assert rel(v, V) < 1e-9
+
+
+def test_batched_equals_merged_box_path():
+    wl = W.batch2048(n_boxes=32)
+    a = run_batch(wl, 30, batched=True)
+    b = run_batch(wl, 30, batched=False)
+    assert np.abs(wrapped_diff(a[0], b[0], wl)).max() < 1e-10
+    assert rel(a[1], b[1]) < 1e-9
+
+
+def test_batched_box_independence_and_determinism():
+    wl = W.batch2048(n_boxes=24)
+    a = run_batch(wl, 20)
+    a2 = run_batch(wl, 20)
+    assert np.array_equal(a[0], a2[0]) and np.array_equal(a[1], a2[1])
+    s = slice(int(wl.box_offset[5]), int(wl.box_offset[6]))
+    wl.pos[s] += 0.01
+    b = run_batch(wl, 20)
+    other = np.ones(wl.n_atoms, bool)
+    other[s] = False
+    assert np.array_equal(a[0][other], b[0][other])
+    assert not np.array_equal(a[0][s], b[0][s])
+
+
+def test_batched_forces_then_generic():
+    """After batched steps, md_forces (merged-box list) sees the new state."""
+    wl = W.batch2048(n_boxes=16)
+    S = md.System.from_workload(wl)
+    S.set_state(wl.pos, wl.vel)
+    S.step(15)
+    f, e, eb = S.forces()
+    p, v = S.get_state()
+    S.close()
+    p = p.cpu().numpy()
+    ref = O.forces_multi(wl, pos=p)
+    assert rel(f.cpu().numpy(), ref["f"]) < 1e-11
+    assert rel(eb.cpu().numpy(), ref["E_box"]) < 1e-11
+
+
+# ------------------------------------------------------------------ adjoint
+
+def adjoint_setup(n_boxes):
+    wl = W.adjoint64(n_boxes=n_boxes)
+    S = md.System.from_workload(wl)
+    S.set_state(wl.pos)
+    return wl, S
+
+
+@pytest.mark.parametrize("n_boxes", [3, 64])
+def test_adjoint_vjp_matches_oracle(n_boxes):
+    wl, S = adjoint_setup(n_boxes)
+    rng = np.random.default_rng(11)
+    g = rng.normal(size=(wl.n_atoms, 3))
+    e = rng.normal(size=wl.n_boxes)
+    gt = S.adjoint(torch.tensor(g, device="cuda"), torch.tensor(e, device="cuda")).cpu().numpy()
+    gt2 = S.adjoint(torch.tensor(g, device="cuda"), torch.tensor(e, device="cuda")).cpu().numpy()
+    assert np.array_equal(gt, gt2)
+    assert S.status()[0] == 0
+    S.close()
+    pot = O.Pot(wl.pot)
+    ref = np.zeros(192)
+    for b, s, L in O.boxes(wl):
+        O.adjoint(O.wrap(wl.pos[s], L), L, pot, g[s], e[b], gtheta=ref)
+    for blk in range(3):
+        sl = slice(64 * blk, 64 * blk + 64)
+        assert rel(gt[sl], ref[sl]) < 1e-10, (blk, rel(gt[sl], ref[sl]))
+
+
+def test_autograd_loss_gradient_matches_oracle():
+    wl, S = adjoint_setup(4)
+    w = wl.extra["w"]
+    tgt = O.forces_multi(wl, pot=O.Pot(wl.extra["target_pot"]))
+    th = [torch.tensor(t, device="cuda", requires_grad=True) for t in wl.pot.tables]
+    ft = torch.tensor(tgt["f"], device="cuda")
+    et = torch.tensor(tgt["E_box"], device="cuda")
+    loss = force_matching_loss(S, th[0], th[1], th[2], ft, et, w)
+    loss.backward()
+    grad = torch.cat([t.grad for t in th]).cpu().numpy()
+    S.close()
+    # oracle: forward, loss derivatives, adjoint
+    pot = O.Pot(wl.pot)
+    out = O.forces_multi(wl, pot=pot)
+    L0 = float(((out["f"] - tgt["f"]) ** 2).sum() + w * ((out["E_box"] - tgt["E_box"]) ** 2).sum())
+    assert abs(float(loss) - L0) <= 1e-11 * L0
+    g = 2.0 * (out["f"] - tgt["f"])
+    e = 2.0 * w * (out["E_box"] - tgt["E_box"])
+    ref = np.zeros(192)
+    for b, s, L in O.boxes(wl):
+        O.adjoint(O.wrap(wl.pos[s], L), L, pot, g[s], e[b], gtheta=ref)
+    assert rel(grad, ref) < 1e-9
+
+
+def test_autograd_matches_finite_differences():
+    wl, S = adjoint_setup(2)
+    w = wl.extra["w"]
+    tgt = O.forces_multi(wl, pot=O.Pot(wl.extra["target_pot"]))
+    ft = torch.tensor(tgt["f"], device="cuda")
+    et = torch.tensor(tgt["E_box"], device="cuda")
+    base = [torch.tensor(t, device="cuda") for t in wl.pot.tables]
+    th = [t.clone().requires_grad_(True) for t in base]
+    loss = force_matching_loss(S, *th, ft, et, w)
+    loss.backward()
+    grad = torch.cat([t.grad for t in th]).cpu().numpy()
+    h = 1e-6
+    eps = np.finfo(float).eps
+    for k in (3, 40, 64 + 10, 64 + 55, 128 + 20, 128 + 33):
+        vals = []
+        for sgn in (1, -1):
+            t2 = [t.clone() for t in base]
+            t2[k // 64][k % 64] += sgn * h
+            with torch.no_grad():
+                vals.append(float(force_matching_loss(S, *t2, ft, et, w)))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        tol = 1e-6 * np.abs(grad).max() + 50 * eps * float(loss) / h
+        assert abs(fd - grad[k]) <= tol, (k, fd, grad[k])
+    S.close()
