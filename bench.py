@@ -1,0 +1,279 @@
+#!/usr/bin/env python3
+"""Throughput of the FP64 many-body MD step on one MI355X.
+
+Headline: atom-steps/s of velocity-Verlet steps (list rebuilds decided on the
+device, density + embedding, force + kick) for the 4,000,000-atom FCC
+second-moment tight-binding workload, inputs resident in HBM.  Also reported:
+the roofline position of the dominant kernel (the force pass), the batched
+many-box stepper (box-steps/s), the adjoint (gradient evaluations/s), the
+128,000-atom spline workload, and the CPU oracle on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+FP64_VALU_PEAK = 256 * 64 * 2.4e9  # lane-instructions/s: 256 CUs x 64 lanes x 2.4 GHz
+METRIC = "atom-steps/s FP64 EAM step at 4M atoms; HBM GB/s fraction; batched box-steps/s"
+COUNTERS = os.path.join(ROOT, "profiles", "force_pass_fcc4m_counters.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1212_6332_amd", "csrc", "md_kernels.hip")
+
+
+def force_pass_bytes(n_atoms, mean_list):
+    """Algorithmic HBM bytes of one force pass with the fused half kick:
+    per atom x,y,z (24) + F' (8) + count (4) + list (4 per entry) + force
+    out (24) + velocity in/out (48); neighbour gathers counted once."""
+    return n_atoms * (108.0 + 4.0 * mean_list)
+
+
+def density_pass_bytes(n_atoms, mean_list):
+    """x,y,z (24) + count (4) + list (4 per entry) + rho, F, F' out (24)."""
+    return n_atoms * (52.0 + 4.0 * mean_list)
+
+
+def read_counters():
+    """Traffic of the force pass from the committed rocprofv3 counter summary,
+    or None if it is missing or was taken from a different kernel source."""
+    if not os.path.exists(COUNTERS):
+        return None
+    kv = {}
+    for line in open(COUNTERS):
+        if ":" in line and not line.lstrip().startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if kv.get("kernel_source_sha256") != sha:
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def timed_steps(S, steps, warmup):
+    import torch
+    S.step(warmup)
+    torch.cuda.synchronize()
+    _, b0, _ = S.status()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    S.step(steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    flags, b1, _ = S.status()
+    if flags:
+        raise RuntimeError(f"device status flags {flags} after the timed steps")
+    return t1 - t0, ev0.elapsed_time(ev1) / 1e3, b1 - b0
+
+
+def bench_main(steps, warmup, reps):
+    import torch
+    from paper_1212_6332_amd import md, workloads as W
+
+    wl = W.fcc4m()
+    S = md.System.from_workload(wl)
+    S.set_state(wl.pos, wl.vel)
+    S.forces(energy=False)
+    counts, _ = S.neighbors(1)
+    mean_list = float(counts.double().mean())
+    wall, gpu_s, rebuilds = timed_steps(S, steps, warmup)
+    n = wl.n_atoms
+    ms = {name: S.time_pass(p, reps) for name, p in (
+        ("force", md.MD_PASS_FORCE), ("density", md.MD_PASS_DENSITY),
+        ("kick_drift", md.MD_PASS_KICK_DRIFT), ("build", md.MD_PASS_BUILD))}
+    fbytes = force_pass_bytes(n, mean_list)
+    achieved = fbytes / (ms["force"] * 1e-3) / 1e9
+    res = {
+        "value": n * steps / wall,
+        "ms_per_step": wall / steps * 1e3,
+        "gpu_ms_per_step": gpu_s / steps * 1e3,
+        "rebuilds": int(rebuilds),
+        "mean_list_len": mean_list,
+        "pass_ms": ms,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": read_counters(),
+                     "kernel": "force pass (k_force, fused half kick)",
+                     "bytes_per_launch": fbytes, "ms_per_launch": ms["force"],
+                     "density_pass_gbs": density_pass_bytes(n, mean_list) / (ms["density"] * 1e-3) / 1e9},
+        "n_atoms": n,
+    }
+    S.close()
+    return res
+
+
+def bench_batched(steps=200, warmup=5):
+    import torch
+    from paper_1212_6332_amd import md, workloads as W
+
+    wl = W.batch2048()
+    S = md.System.from_workload(wl)
+    S.set_state(wl.pos, wl.vel)
+    wall, gpu_s, _ = timed_steps(S, steps, warmup)
+    block = S.get_option(md.MD_OPT_BATCH_BLOCK)
+    S.close()
+    return {"workload": "batch2048: 2,048 FCC boxes n^3, n in {3..8}, 5,000-knot splines",
+            "n_boxes": wl.n_boxes, "n_atoms": wl.n_atoms, "steps": steps,
+            "box_steps_per_s": wl.n_boxes * steps / wall,
+            "atom_steps_per_s": wl.n_atoms * steps / wall,
+            "ms_per_step": wall / steps * 1e3, "workgroup": block}
+
+
+def bench_adjoint(evals=50, steps=100):
+    import torch
+    from paper_1212_6332_amd import md, workloads as W
+    from paper_1212_6332_amd.autograd import force_matching_loss
+
+    wl = W.adjoint64()
+    T = md.System.from_workload(wl, wl.extra["target_pot"])
+    T.set_state(wl.pos)
+    ft, _, et = T.forces()
+    T.close()
+    S = md.System.from_workload(wl)
+    S.set_state(wl.pos)
+    th = [torch.tensor(t, device="cuda", requires_grad=True) for t in wl.pot.tables]
+    w = wl.extra["w"]
+
+    def one():
+        for t in th:
+            t.grad = None
+        loss = force_matching_loss(S, th[0], th[1], th[2], ft, et, w)
+        loss.backward()
+
+    for _ in range(3):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(evals):
+        one()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / evals
+    # the plain step on the same boxes and potential, for comparison
+    S.set_state(wl.pos, None)
+    wall, _, _ = timed_steps(S, steps, 5)
+    S.close()
+    return {"workload": "adjoint64: 64 BCC 5^3 boxes (16,000 atoms), 3x64 B-spline coefficients",
+            "grad_evals_per_s": 1.0 / dt, "ms_per_grad_eval": dt * 1e3,
+            "atom_grads_per_s": wl.n_atoms / dt,
+            "plain_step_atom_steps_per_s": wl.n_atoms * steps / wall}
+
+
+def bench_c2(steps=1000, warmup=20):
+    from paper_1212_6332_amd import md, workloads as W
+
+    wl = W.bcc128k()
+    S = md.System.from_workload(wl)
+    S.set_state(wl.pos, wl.vel)
+    wall, _, reb = timed_steps(S, steps, warmup)
+    S.close()
+    return {"workload": "bcc128k: BCC 40^3 (128,000 atoms), 5,000-knot splines",
+            "atom_steps_per_s": wl.n_atoms * steps / wall, "ms_per_step": wall / steps * 1e3,
+            "rebuilds": int(reb), "steps": steps}
+
+
+def cpu_baseline(ncell=50, steps=10):
+    """The CPU oracle on a bounded sample: the same material (FCC SMTB, a =
+    3.615, 300 K, sigma 0.05) in a 50^3-cell box (500,000 atoms, 1/8 of the
+    full system), 10 velocity-Verlet steps; list build and initial forces
+    timed separately and excluded."""
+    import oracle as O
+    from paper_1212_6332_amd import workloads as W
+
+    wl = W.fcc4m(ncell=ncell)
+    L = float(wl.box_len[0, 0])
+    pot = O.Pot(wl.pot)
+    t = time.perf_counter()
+    O.vv(wl.pos, wl.vel, L, pot, wl.mass, wl.dt, wl.skin, 0, energies=False)
+    setup = time.perf_counter() - t
+    t = time.perf_counter()
+    O.vv(wl.pos, wl.vel, L, pot, wl.mass, wl.dt, wl.skin, steps, energies=False)
+    run = time.perf_counter() - t
+    per_step = max(run - setup, 1e-9) / steps
+    return {"value": wl.n_atoms / per_step, "unit": "atom-steps/s", "cores": O.threads(),
+            "kind": "oracle",
+            "sample": f"FCC SMTB {ncell}^3 cells ({wl.n_atoms} atoms, same density, potential "
+                      f"and temperature as the 4M-atom box), {steps} velocity-Verlet steps; "
+                      f"setup (list build + first forces, {setup:.2f} s) excluded",
+            "seconds": run + setup}
+
+
+def pmc_probe(reps):
+    """Short run for hardware-counter collection: force passes of the 4M-atom
+    workload, then one plain 2 GiB device copy used to scale the counters."""
+    import torch
+    from paper_1212_6332_amd import md, workloads as W
+
+    wl = W.fcc4m()
+    S = md.System.from_workload(wl)
+    S.set_state(wl.pos, wl.vel)
+    S.forces(energy=False)
+    counts, _ = S.neighbors(1)
+    print(json.dumps({"mean_list_len": float(counts.double().mean()), "n_atoms": wl.n_atoms,
+                      "force_bytes": force_pass_bytes(wl.n_atoms, float(counts.double().mean()))}))
+    S.time_pass(md.MD_PASS_FORCE, reps)
+    torch.cuda.synchronize()
+    src = torch.ones(2 ** 28, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": src.numel() * 8}))
+    S.close()
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--reps", type=int, default=20, help="launches per timed pass")
+    ap.add_argument("--no-extras", action="store_true", help="headline workload only")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pmc-probe", action="store_true", help="counter-collection run only")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the whole box fits in one MI355X's HBM); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    if args.pmc_probe:
+        pmc_probe(args.reps)
+        return
+    r = bench_main(args.steps, args.warmup, args.reps)
+    out = {
+        "metric": METRIC, "value": r["value"], "unit": "atom-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "fcc4m: FCC 100^3 cells (4,000,000 atoms), second-moment "
+                               "tight binding (Cu), rc 5.85 A, skin 0.3 A, 300 K, dt 1 fs",
+                   "n_atoms": r["n_atoms"], "rebuilds_in_timed_steps": r["rebuilds"],
+                   "mean_list_len": r["mean_list_len"], "gpu_ms_per_step": r["gpu_ms_per_step"],
+                   "pass_ms": r["pass_ms"]},
+        "roofline": r["roofline"],
+    }
+    if not args.no_extras:
+        out["batched"] = bench_batched()
+        out["adjoint"] = bench_adjoint()
+        out["bcc128k"] = bench_c2()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

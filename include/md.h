@@ -133,7 +133,7 @@ int md_set_state(md_ctx *ctx, const double *pos, const double *vel, void *stream
  * without wrapping in between. */
 int md_get_state(md_ctx *ctx, double *pos, double *vel, void *stream);
 
-/* Steps a1-a3 (Section 3.2): wrap positions into each box, bin atoms into
+/* List build (Section 3.2): wrap positions into each box, bin atoms into
  * cells of edge >= list radius, sort them by (cell, original index) with a
  * counting sort, and build the full neighbour list of every atom (all j != i
  * of the same box within the list radius under the minimum image; squared
@@ -185,6 +185,15 @@ int md_status(md_ctx *ctx, void *stream, uint32_t *flags, int64_t *counters);
  * F).  Recomputes rho, F'(rho) and F''(rho) from the current positions and
  * list; the reduction order is fixed, so results are bitwise reproducible. */
 int md_adjoint(md_ctx *ctx, const double *g, const double *e, double *gtheta, void *stream);
+
+/* Benchmarking: launch one pass `reps` times on `stream`, bracketed by HIP
+ * events recorded on that stream, and return the mean duration per launch in
+ * *avg_ms (synchronises).  Passes: MD_PASS_BUILD (list build), MD_PASS_DENSITY
+ * (density + embedding), MD_PASS_FORCE (force + half kick, the variant used by
+ * md_step), MD_PASS_KICK_DRIFT.  Positions and velocities are restored
+ * afterwards, so timing leaves the trajectory unchanged. */
+enum { MD_PASS_BUILD = 0, MD_PASS_DENSITY = 1, MD_PASS_FORCE = 2, MD_PASS_KICK_DRIFT = 3 };
+int md_time_pass(md_ctx *ctx, int32_t pass, int32_t reps, void *stream, double *avg_ms);
 
 /* Options. */
 enum {

@@ -76,6 +76,7 @@ def lib():
         L.orc_vv.argtypes = [i64, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p, dbl, P, dbl, dbl,
                              dbl, i32, i32, C.c_void_p, C.c_void_p]
         L.orc_vv.restype = i32
+        L.orc_threads.restype = i32
         L.orc_adjoint.argtypes = [i64, _f64p, _f64p, _f64p, dbl, P, _i32p, _i32p, i32, _f64p,
                                   _f64p, _f64p, dbl, _f64p]
         _lib = L
@@ -248,6 +249,10 @@ def forces_multi(W, pos=None, pot=None):
         out["Fp"][s] = r["Fp"]
         out["E_box"][b] = r["E"]
     return out
+
+
+def threads() -> int:
+    return int(lib().orc_threads())
 
 
 def kinetic(vel, mass):

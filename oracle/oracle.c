@@ -795,3 +795,16 @@ void orc_adjoint(int64_t n, const double *x, const double *y, const double *z, d
     }
     free(rho); free(F); free(Fp); free(Fpp); free(sv);
 }
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

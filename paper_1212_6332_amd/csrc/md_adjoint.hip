@@ -92,9 +92,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_s(int N, State st, Boxes bx, NLi
     const double *gx = gs, *gy = gs + N, *gz = gs + 2 * N;
     double xi = st.x[i], yi = st.y[i], zi = st.z[i];
     double gxi = gx[i], gyi = gy[i], gzi = gz[i];
-    int cnt = min(nl.count[i], nl.mn);
+    unsigned w = (unsigned)nl.count[i];
+    int np = (int)(w & 0xffffu), n1 = nl.mn - (int)(w >> 16);
     double s = 0.0;
-    for (int n = 0; n < cnt; ++n) {
+    for (int n = 0; n < nl.mn; ++n) {
+        if (n == np) n = n1;  // skip to the boundary-crossing part of the row
+        if (n >= nl.mn) break;
         int j = nl.idx[(size_t)n * N + i];
         double dx = min_image(st.x[j] - xi, L, invL);
         double dy = min_image(st.y[j] - yi, L, invL);
@@ -137,9 +140,12 @@ __global__ __launch_bounds__(W) void k_adj_theta(int N, int K, State st, Boxes b
         double lami = lam[i], si = sv[i];
         double F, fpi, fppi;
         table_eval2(pot.tab[2], st.rho[i], F, fpi, fppi);
-        int cnt = min(nl.count[i], nl.mn);
+        unsigned cw = (unsigned)nl.count[i];
+        int np = (int)(cw & 0xffffu), n1 = nl.mn - (int)(cw >> 16);
         double bb[4], db[4];
-        for (int n = 0; n < cnt; ++n) {
+        for (int n = 0; n < nl.mn; ++n) {
+            if (n == np) n = n1;  // skip to the boundary-crossing part of the row
+            if (n >= nl.mn) break;
             int j = nl.idx[(size_t)n * N + i];
             double dx = min_image(st.x[j] - xi, L, invL);
             double dy = min_image(st.y[j] - yi, L, invL);

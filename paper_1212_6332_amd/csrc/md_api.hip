@@ -106,6 +106,12 @@ int upload_potential(Ctx &c, const md_potential *p, hipStream_t s, bool first)
         q.bv = pp + std::log(2.0 * A);
         q.af = -2.0 * qq / r0;
         q.bf = 2.0 * qq + 2.0 * std::log(xi);
+        // ln 2 split for the exponential's argument reduction: a 32-bit head
+        // (exact products with the reduction multiple) and the remainder
+        long double ln2 = 0.693147180559945309417232121458176568L;
+        double hi = (double)std::ldexp(std::floor(std::ldexp(ln2, 32)), -32);
+        q.l2hi = hi;
+        q.l2lo = (double)(ln2 - (long double)hi);
     } else {
         q.kind = MD_POT_SPLINE;
         if (first) {
@@ -159,8 +165,10 @@ int upload_potential(Ctx &c, const md_potential *p, hipStream_t s, bool first)
 
 int alloc_list(Ctx &c, int mn)
 {
+    if (mn > 65535) return MD_ERR_ARG;
     c.nl.mn = mn;
     ALLOC(c.nl.idx, (size_t)mn * c.N);
+    HIP_TRY(hipMemset(c.nl.idx, 0, sizeof(int) * (size_t)mn * c.N));
     return MD_OK;
 }
 
@@ -243,7 +251,7 @@ int md_create(const md_system *sys, const md_potential *pot, md_ctx **out)
         if (!(0.5 * sys->box_len[b] - 1e-9 > pot->rc)) return MD_ERR_BOX;
     }
     int64_t N = sys->box_offset[B];
-    if (N >= (int64_t)1 << 31) return MD_ERR_ARG;
+    if (N >= (int64_t)1 << 27) return MD_ERR_ARG;  // gathers use 32-bit byte offsets
 
     md_ctx *h = new (std::nothrow) md_ctx();
     if (!h) return MD_ERR_NOMEM;
@@ -272,9 +280,12 @@ int md_create(const md_system *sys, const md_potential *pot, md_ctx **out)
         double rl = list_radius(pot->rc, sys->skin, L);
         c.box_rlist[b] = rl;
         int nc = cells_per_dim(L, rl);
+        if (nc > 1024) nc = 1024;  // Morton cell indices use 10 bits per axis
         c.box_nc[b] = nc;
         c.box_cell_off[b] = (int)cells;
-        cells += (int64_t)nc * nc * nc;
+        int64_t pw = 1;
+        while (pw < nc) pw <<= 1;  // Morton indices of a box span the next power of two
+        cells += pw * pw * pw;
         double nb = (double)(c.box_off[b + 1] - c.box_off[b]);
         double expect = nb / (L * L * L) * 4.0 / 3.0 * M_PI * rl * rl * rl;
         double est = std::min(nb - 1.0, std::ceil(1.4 * expect + 16.0));
@@ -285,6 +296,7 @@ int md_create(const md_system *sys, const md_potential *pot, md_ctx **out)
     c.bd.n_cells = (int)cells;
     int mn = sys->max_neighbors > 0 ? sys->max_neighbors : ((int)mn_est + 7) / 8 * 8;
     if (mn < 1) mn = 1;
+    if (mn > 65535) return fail(MD_ERR_ARG);
 
     if (hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking) != hipSuccess)
         return fail(MD_ERR_DEVICE);
@@ -331,16 +343,22 @@ int md_create(const md_system *sys, const md_potential *pot, md_ctx **out)
                       &c.bd.svy, &c.bd.svz};
     for (double **p : dbl)
         if ((rc = dev_alloc(c, p, (size_t)N)) != MD_OK) return fail(rc);
+    if ((rc = dev_alloc(c, &c.st.pk, 4 * (size_t)N)) != MD_OK) return fail(rc);
     int **ints[] = {&c.st.id, &c.bd.sid, &c.bd.cell_of, &c.bd.slot, &c.bd.tmp, &c.bd.perm,
-                    &c.nl.count};
+                    &c.nl.count, &c.nl.total};
     for (int **p : ints)
         if ((rc = dev_alloc(c, p, (size_t)N)) != MD_OK) return fail(rc);
     if ((rc = dev_alloc(c, &c.bd.cell_count, (size_t)cells)) != MD_OK) return fail(rc);
     if ((rc = dev_alloc(c, &c.bd.cell_start, (size_t)cells + 1)) != MD_OK) return fail(rc);
+    if ((rc = dev_alloc(c, &c.bd.bsum, (size_t)cells / 4096 + 2)) != MD_OK) return fail(rc);
+    if (hipMemset(c.bd.cell_count, 0, sizeof(int) * (size_t)cells) != hipSuccess)
+        return fail(MD_ERR_DEVICE);
     if ((rc = alloc_list(c, mn)) != MD_OK) return fail(rc);
     if ((rc = dev_alloc(c, &c.dev.flags, 8)) != MD_OK) return fail(rc);
     if (hipMemset(c.dev.flags, 0, 8 * sizeof(unsigned)) != hipSuccess) return fail(MD_ERR_DEVICE);
-    if (hipMemset(c.nl.count, 0, sizeof(int) * N) != hipSuccess) return fail(MD_ERR_DEVICE);
+    if (hipMemset(c.nl.count, 0, sizeof(int) * N) != hipSuccess ||
+        hipMemset(c.nl.total, 0, sizeof(int) * N) != hipSuccess)
+        return fail(MD_ERR_DEVICE);
 
     // chunks of the fixed-order per-box sums
     {
@@ -608,6 +626,55 @@ int md_adjoint(md_ctx *h, const double *g, const double *e, double *gtheta, void
     hipStream_t s = as_stream(stream);
     ensure_density(c, s);
     launch_adjoint(c, g, e, gtheta, s);
+    return MD_OK;
+}
+
+int md_time_pass(md_ctx *h, int32_t pass, int32_t reps, void *stream, double *avg_ms)
+{
+    if (!h || !avg_ms || reps < 1 || pass < MD_PASS_BUILD || pass > MD_PASS_KICK_DRIFT)
+        return MD_ERR_ARG;
+    Ctx &c = h->c;
+    if (!c.state_set) return MD_ERR_STATE;
+    hipStream_t s = as_stream(stream);
+    ensure_density(c, s);
+    if (!c.forces_valid) {
+        launch_force(c, false, false, s);
+        c.forces_valid = true;
+    }
+    size_t nb = sizeof(double) * (size_t)c.N;
+    double *save[6] = {c.bd.sx, c.bd.sy, c.bd.sz, c.bd.svx, c.bd.svy, c.bd.svz};
+    double *live[6] = {c.st.x, c.st.y, c.st.z, c.st.vx, c.st.vy, c.st.vz};
+    for (int k = 0; k < 6; ++k) HIP_TRY(hipMemcpyAsync(save[k], live[k], nb, hipMemcpyDeviceToDevice, s));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) {
+        switch (pass) {
+        case MD_PASS_BUILD: launch_build(c, false, s); break;
+        case MD_PASS_DENSITY: launch_density(c, s); break;
+        case MD_PASS_FORCE: launch_force(c, false, true, s); break;
+        case MD_PASS_KICK_DRIFT: launch_kick_drift(c, s); break;
+        }
+    }
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *avg_ms = ms / reps;
+    if (pass == MD_PASS_BUILD) {
+        // the build scratch held the saved state; rebuild on the unchanged positions
+        batched_invalidate(c);
+        c.density_valid = c.forces_valid = false;
+        return MD_OK;
+    }
+    for (int k = 0; k < 6; ++k) HIP_TRY(hipMemcpyAsync(live[k], save[k], nb, hipMemcpyDeviceToDevice, s));
+    launch_pack_positions(c, s);
+    launch_fill_u32(c.dev.flags + 1, 1, 0u, s);
+    if (pass == MD_PASS_KICK_DRIFT) launch_force(c, false, false, s);
+    HIP_TRY(hipStreamSynchronize(s));
     return MD_OK;
 }
 

@@ -28,12 +28,14 @@ struct Pot {
     double rc, rc2;
     double c, d, c0, c1, c2, A;        // Finnis-Sinclair
     double av, bv, af, bf;             // SMTB: V = exp(av r + bv), rho = exp(af r + bf)
+    double l2hi, l2lo;                 // ln 2 = l2hi + l2lo, l2hi with 32 significant bits
     Table tab[3];                      // V(r), rho(r), F(rho)
 };
 
 // Atom state in sorted (cell) order, structure of arrays.
 struct State {
     double *x, *y, *z, *vx, *vy, *vz, *fx, *fy, *fz, *xr, *yr, *zr;
+    double *pk;                        // [N][4] packed x, y, z, F'(rho) for neighbour gathers
     int *id;                           // original index of each sorted slot
     double *rho, *Fp, *Femb, *eat;     // density, F'(rho), F(rho), per-atom energy
 };
@@ -49,11 +51,13 @@ struct Build {
     double *sx, *sy, *sz, *svx, *svy, *svz;
     int *sid;
     int *cell_of, *slot, *cell_count, *cell_start, *tmp, *perm;
-    int n_cells;
+    int *bsum;                         // scan block totals [n_cells / 4096 + 2]
+    int n_cells;                       // Morton cell slots over all boxes
 };
 
 struct NList {
-    int *count;                        // [N]
+    int *count;                        // [N]: plain pairs | (boundary pairs << 16)
+    int *total;                        // [N]: neighbours found (may exceed mn)
     int *idx;                          // [MN][N], column major (slot-fastest)
     int mn;
 };
@@ -83,6 +87,7 @@ void launch_get_neighbors(Ctx &c, int32_t *counts, int32_t *ids, int32_t max_col
                           hipStream_t s);
 void launch_bspline_tables(Ctx &c, const double *theta, hipStream_t s);
 void launch_fill_u32(unsigned *p, int n, unsigned v, hipStream_t s);
+void launch_pack_positions(Ctx &c, hipStream_t s);
 
 // Form (2), md_batched.hip.
 int batched_prepare(Ctx &c);

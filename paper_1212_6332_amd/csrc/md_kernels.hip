@@ -50,6 +50,135 @@ __device__ __forceinline__ double min_image(double d, double L, double invL)
     return fma(-L, rint(d * invL), d);
 }
 
+// Gather with a 32-bit byte offset from a uniform base pointer (the compiler
+// then issues scalar-base global loads; atom counts stay below 2^29).
+__device__ __forceinline__ double ldg(const double *__restrict__ base, unsigned j)
+{
+    return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(base) + (j << 3));
+}
+
+// Packed neighbour record j: (x, y) and (z, F') as two 16-byte loads from
+// one 32-byte record (one cache line), 32-bit byte offsets (N < 2^27).
+__device__ __forceinline__ double2 ldpk(const double *__restrict__ pk, unsigned j, unsigned half)
+{
+    return *reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(pk) + (j << 5) +
+                                              (half << 4));
+}
+
+__device__ __forceinline__ double ldpk_z(const double *__restrict__ pk, unsigned j)
+{
+    return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(pk) + (j << 5) + 16);
+}
+
+// 1/sqrt(a), a > 0: hardware estimate refined by two Newton steps
+// y <- y + y (1/2 - a y^2 / 2).
+__device__ __forceinline__ double rsqrt_nr(double a)
+{
+    double y = __builtin_amdgcn_rsq(a);
+    double h = 0.5 * a;
+    double e = fma(-h * y, y, 0.5);
+    y = fma(y, e, y);
+    e = fma(-h * y, y, 0.5);
+    return fma(y, e, y);
+}
+
+// exp(x) on the vector ALU alone: x = k ln2 + r with |r| <= ln2/2 (ln 2 split
+// in a 32-bit head and a tail so k ln2 is exact), exp(r) by its Taylor
+// polynomial of degree 13 (truncation < 5e-18 relative), then exp(x) =
+// 2^k exp(r).  Arguments are clamped to the range where exp is finite and
+// normal or gradually underflows.
+__device__ __forceinline__ double exp_fast(double x, const Pot &p)
+{
+    x = fmin(fmax(x, -745.0), 709.0);
+    double k = rint(x * 1.4426950408889634074);
+    double r = fma(-k, p.l2hi, x);
+    r = fma(-k, p.l2lo, r);
+    double q = 1.0 / 6227020800.0;          // 1/13!
+    q = fma(q, r, 1.0 / 479001600.0);       // 1/12!
+    q = fma(q, r, 1.0 / 39916800.0);
+    q = fma(q, r, 1.0 / 3628800.0);
+    q = fma(q, r, 1.0 / 362880.0);
+    q = fma(q, r, 1.0 / 40320.0);
+    q = fma(q, r, 1.0 / 5040.0);
+    q = fma(q, r, 1.0 / 720.0);
+    q = fma(q, r, 1.0 / 120.0);
+    q = fma(q, r, 1.0 / 24.0);
+    q = fma(q, r, 1.0 / 6.0);
+    q = fma(q, r, 0.5);
+    q = fma(q, r, 1.0);
+    q = fma(q, r, 1.0);
+    return ldexp(q, (int)k);
+}
+
+// Neighbour row of slot i: `np` pairs that need no periodic correction at
+// rows [0, np), `ni` pairs that cross the box boundary at rows [mn - ni, mn).
+struct Row {
+    int np, ni;
+};
+
+__device__ __forceinline__ Row row_of(const NList &nl, int i)
+{
+    unsigned w = (unsigned)nl.count[i];
+    return Row{(int)(w & 0xffffu), (int)(w >> 16)};
+}
+
+// Visit rows [n0, n1) of the column of slot i.  Software pipelined: while
+// pair n is evaluated, the record of pair n+1 and the index of pair n+2 are
+// already in flight.  Each pair costs one coalesced index load and two
+// 16-byte loads from one 32-byte record.
+template <bool IMG, bool FPJ, class Body>
+__device__ __forceinline__ void for_pairs(const int *__restrict__ col, int N, int n0, int n1,
+                                          const double *__restrict__ pk, double xi, double yi,
+                                          double zi, double L, double invL, Body &&body)
+{
+    if (n0 >= n1) return;
+    const int *p = col + (size_t)n0 * N;
+    unsigned j = (unsigned)p[0];
+    unsigned jn = (n0 + 1 < n1) ? (unsigned)p[N] : j;
+    p += 2 * (size_t)N;
+    double2 a = ldpk(pk, j, 0);
+    double2 b;
+    if constexpr (FPJ) b = ldpk(pk, j, 1);
+    else b.x = ldpk_z(pk, j);
+    for (int n = n0; n < n1; ++n) {
+        unsigned jnn = (n + 2 < n1) ? (unsigned)*p : jn;
+        p += N;
+        double2 an = ldpk(pk, jn, 0);
+        double2 bn;
+        if constexpr (FPJ) bn = ldpk(pk, jn, 1);
+        else bn.x = ldpk_z(pk, jn);
+        double dx = a.x - xi, dy = a.y - yi, dz = b.x - zi;
+        if constexpr (IMG) {
+            dx = min_image(dx, L, invL);
+            dy = min_image(dy, L, invL);
+            dz = min_image(dz, L, invL);
+        }
+        body(dx, dy, dz, FPJ ? b.y : 0.0);
+        jn = jnn;
+        a = an;
+        b = bn;
+    }
+}
+
+// Morton (Z-order) index of a cell: interleaved bits of its three
+// coordinates (each below 1024).  Cells that are close in space get close
+// indices, so the atoms a group of workgroups touches stay in one L2.
+__device__ __forceinline__ unsigned spread3(unsigned v)
+{
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__device__ __forceinline__ int morton3(int cx, int cy, int cz)
+{
+    return (int)(spread3((unsigned)cx) | (spread3((unsigned)cy) << 1) |
+                 (spread3((unsigned)cz) << 2));
+}
+
 // ---------------------------------------------------------------- potential
 
 __device__ __forceinline__ void table_eval(const Table &t, double x, double &s, double &ds,
@@ -75,7 +204,7 @@ __device__ __forceinline__ double dens(const Pot &p, double r, unsigned &bad)
         double u = r - p.d;
         return r < p.d ? u * u : 0.0;
     } else if constexpr (KIND == MD_POT_SMTB) {
-        return exp(fma(p.af, r, p.bf));
+        return exp_fast(fma(p.af, r, p.bf), p);
     } else {
         double s, ds;
         table_eval(p.tab[1], r, s, ds, bad);
@@ -98,8 +227,8 @@ __device__ __forceinline__ void pair_terms(const Pot &p, double r, double &dfr, 
         v = in ? w * w * poly : 0.0;
         dv = in ? w * fma(w, dpoly, 2.0 * poly) : 0.0;
     } else if constexpr (KIND == MD_POT_SMTB) {
-        double ef = exp(fma(p.af, r, p.bf));
-        double ev = exp(fma(p.av, r, p.bv));
+        double ef = exp_fast(fma(p.af, r, p.bf), p);
+        double ev = exp_fast(fma(p.av, r, p.bv), p);
         dfr = p.af * ef;
         v = ev;
         dv = p.av * ev;
@@ -201,6 +330,14 @@ __global__ void k_scatter_vec3(int N, const int *__restrict__ id, const double *
     dst[o + 2] = sz[i];
 }
 
+__global__ void k_pack_positions(int N, State st)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    reinterpret_cast<double2 *>(st.pk)[2 * (size_t)i] = make_double2(st.x[i], st.y[i]);
+    st.pk[4 * (size_t)i + 2] = st.z[i];
+}
+
 __global__ void k_fill_u32(unsigned *p, int n, unsigned v)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -234,61 +371,132 @@ __device__ __forceinline__ double wrap1(double x, double L)
     return x;
 }
 
-// a1: wrap into the box, find the cell, count atoms per cell.
-__global__ void k_bin(const unsigned *gate, int N, State st, Boxes bx, Build bd, unsigned *flags)
+// Binning: wrap into the box, find the cell (Morton index within the box),
+// count atoms per cell.  Consecutive slots mostly share a cell (the state is
+// sorted from the previous build), so each run of equal cells in a
+// wavefront takes its slots with one atomic add.
+__global__ __launch_bounds__(kBlock) void k_bin(const unsigned *gate, int N, State st, Boxes bx,
+                                                Build bd, unsigned *flags)
 {
     if (skip(gate)) return;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    int b = bx.box_of[i];
-    double L = bx.L[b];
-    int nc = bx.nc[b];
-    double x = st.x[i], y = st.y[i], z = st.z[i];
-    if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
-        atomicOr(flags, (unsigned)MD_FLAG_NONFINITE);
-        x = y = z = 0.0;
+    bool valid = i < N;
+    int cell = -1;
+    if (valid) {
+        int b = bx.box_of[i];
+        double L = bx.L[b];
+        int nc = bx.nc[b];
+        double x = st.x[i], y = st.y[i], z = st.z[i];
+        if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
+            atomicOr(flags, (unsigned)MD_FLAG_NONFINITE);
+            x = y = z = 0.0;
+        }
+        x = wrap1(x, L);
+        y = wrap1(y, L);
+        z = wrap1(z, L);
+        st.x[i] = x;
+        st.y[i] = y;
+        st.z[i] = z;
+        double ncL = nc * bx.invL[b];
+        cell = bx.cell_off[b] +
+               morton3(cell_coord(x, ncL, nc), cell_coord(y, ncL, nc), cell_coord(z, ncL, nc));
+        bd.cell_of[i] = cell;
     }
-    x = wrap1(x, L);
-    y = wrap1(y, L);
-    z = wrap1(z, L);
-    st.x[i] = x;
-    st.y[i] = y;
-    st.z[i] = z;
-    double ncL = nc * bx.invL[b];
-    int cx = cell_coord(x, ncL, nc), cy = cell_coord(y, ncL, nc), cz = cell_coord(z, ncL, nc);
-    int cell = bx.cell_off[b] + (cz * nc + cy) * nc + cx;
-    bd.cell_of[i] = cell;
-    bd.slot[i] = atomicAdd(&bd.cell_count[cell], 1);
+    int lane = threadIdx.x & 63;
+    int prev = __shfl_up(cell, 1);
+    bool head = valid && (lane == 0 || prev != cell);
+    unsigned long long heads = __ballot(head);
+    unsigned long long nvalid = __popcll(__ballot(valid));
+    unsigned long long upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    unsigned long long below = heads & upto;
+    int leader = below ? 63 - __clzll(below) : 0;
+    unsigned long long after = heads & ~upto;
+    int end = after ? __ffsll(after) - 1 : 64;
+    if (end > (int)nvalid) end = (int)nvalid;
+    int base = 0;
+    if (head) base = atomicAdd(&bd.cell_count[cell], end - lane);
+    base = __shfl(base, leader);
+    if (valid) bd.slot[i] = base + (lane - leader);
 }
 
-// Exclusive scan of the per-cell counts (one workgroup of 1024 threads).
-__global__ __launch_bounds__(1024) void k_scan(const unsigned *gate, int C,
-                                               const int *__restrict__ cnt, int *__restrict__ start)
+// Exclusive scan of the per-cell counts in three passes: per-block scans
+// of kScanCells cells, a scan of the block totals, and the block offsets.
+constexpr int kScanCells = 4096;  // cells per scan block (1024 threads x 4)
+
+// Exclusive scan of one value per thread over a 1024-thread block; returns
+// the block total in *total.
+__device__ __forceinline__ int block_scan_1024(int v, int *total)
+{
+    __shared__ int wsum[16];
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int incl = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        int u = __shfl_up(incl, off);
+        if (lane >= off) incl += u;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int k = 0; k < 16; ++k) {
+            int t = wsum[k];
+            wsum[k] = run;
+            run += t;
+        }
+        *total = run;
+    }
+    __syncthreads();
+    return wsum[w] + incl - v;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_local(const unsigned *gate, int C,
+                                                     const int *__restrict__ cnt,
+                                                     int *__restrict__ start, int *__restrict__ bsum)
 {
     if (skip(gate)) return;
-    __shared__ int part[1024];
-    int t = threadIdx.x;
-    int per = (C + 1023) / 1024;
-    int lo = t * per, hi = min(C, lo + per);
-    int s = 0;
-    for (int c = lo; c < hi; ++c) s += cnt[c];
-    part[t] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        int v = t >= off ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
+    __shared__ int tot;
+    int c0 = blockIdx.x * kScanCells + threadIdx.x * 4;
+    int v[4], s = 0;
+    for (int k = 0; k < 4; ++k) {
+        v[k] = (c0 + k < C) ? cnt[c0 + k] : 0;
+        s += v[k];
     }
-    int run = part[t] - s;
-    for (int c = lo; c < hi; ++c) {
-        start[c] = run;
-        run += cnt[c];
+    int run = block_scan_1024(s, &tot);
+    for (int k = 0; k < 4; ++k) {
+        if (c0 + k < C) start[c0 + k] = run;
+        run += v[k];
     }
-    if (t == 1023) start[C] = part[1023];
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-// a2 (first half): place every atom in its cell's segment (order inside a
+__global__ __launch_bounds__(1024) void k_scan_top(const unsigned *gate, int nb, int *bsum)
+{
+    if (skip(gate)) return;
+    __shared__ int tot;
+    int per = (nb + 1023) / 1024;
+    int lo = threadIdx.x * per, hi = min(nb, lo + per);
+    int s = 0;
+    for (int k = lo; k < hi; ++k) s += bsum[k];
+    int run = block_scan_1024(s, &tot);
+    for (int k = lo; k < hi; ++k) {
+        int t = bsum[k];
+        bsum[k] = run;
+        run += t;
+    }
+    if (threadIdx.x == 0) bsum[nb] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_add(const unsigned *gate, int C, int nb,
+                                                     int *__restrict__ start,
+                                                     const int *__restrict__ bsum)
+{
+    if (skip(gate)) return;
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < C) start[c] += bsum[c / kScanCells];
+    if (c == 0) start[C] = bsum[nb];
+}
+
+// Counting sort, first half: place every atom in its cell's segment (order inside a
 // cell is not yet deterministic).
 __global__ void k_scatter(const unsigned *gate, int N, Build bd)
 {
@@ -298,7 +506,7 @@ __global__ void k_scatter(const unsigned *gate, int N, Build bd)
     bd.tmp[bd.cell_start[bd.cell_of[i]] + bd.slot[i]] = i;
 }
 
-// a2 (second half): order each cell by original index.  The rank of an atom
+// Counting sort, second half: order each cell by original index.  The rank of an atom
 // is the number of atoms of its cell with a smaller original index.
 __global__ void k_rank(const unsigned *gate, int N, State st, Build bd)
 {
@@ -338,6 +546,8 @@ __global__ void k_commit(const unsigned *gate, int N, State st, Build bd)
     st.x[q] = x;
     st.y[q] = y;
     st.z[q] = z;
+    reinterpret_cast<double2 *>(st.pk)[2 * (size_t)q] = make_double2(x, y);
+    st.pk[4 * (size_t)q + 2] = z;
     st.xr[q] = x;
     st.yr[q] = y;
     st.zr[q] = z;
@@ -365,8 +575,26 @@ __device__ __forceinline__ int stencil_1d(int c, int nc, int out[3])
     return 3;
 }
 
-// a3: full list of slot i.  r^2 = (dx*dx + dy*dy) + dz*dz with separate
-// roundings (no contraction) so that membership is reproducible exactly.
+// Distinct neighbour cells along one axis for three or more cells, with
+// the periodic shift that brings x_j - x_i to the minimum image: +L for the
+// cell past the upper end (wrapped to 0), -L for the cell past the lower end.
+__device__ __forceinline__ void stencil_shift(int c, int nc, double L, int cell[3], double sh[3])
+{
+    cell[0] = c == 0 ? nc - 1 : c - 1;
+    sh[0] = c == 0 ? -L : 0.0;
+    cell[1] = c;
+    sh[1] = 0.0;
+    cell[2] = c == nc - 1 ? 0 : c + 1;
+    sh[2] = c == nc - 1 ? L : 0.0;
+}
+
+// Full list of slot i.  r^2 = (dx*dx + dy*dy) + dz*dz with separate
+// roundings (no contraction) so that membership is reproducible exactly; the
+// periodic correction is one exact addition of +-L, as in the minimum image.
+// With three or more cells per axis the correction is known per stencil cell;
+// with one or two cells every cell is in the stencil and the minimum image is
+// taken per pair.  Pairs without correction go to the front of the row, the
+// others to its back.
 __global__ __launch_bounds__(kBlock) void k_nlist(const unsigned *gate, int N, State st, Boxes bx,
                                                   Build bd, NList nl, unsigned *flags)
 {
@@ -377,42 +605,104 @@ __global__ __launch_bounds__(kBlock) void k_nlist(const unsigned *gate, int N, S
     int b = bx.box_of[i];
     double L = bx.L[b], invL = bx.invL[b], rl2 = bx.rl2[b];
     int nc = bx.nc[b], coff = bx.cell_off[b];
-    double xi = st.x[i], yi = st.y[i], zi = st.z[i];
+    const double *__restrict__ X = st.x;
+    const double *__restrict__ Y = st.y;
+    const double *__restrict__ Z = st.z;
+    double xi = X[i], yi = Y[i], zi = Z[i];
     double ncL = nc * invL;
-    int sx[3], sy[3], sz[3];
-    int kx = stencil_1d(cell_coord(xi, ncL, nc), nc, sx);
-    int ky = stencil_1d(cell_coord(yi, ncL, nc), nc, sy);
-    int kz = stencil_1d(cell_coord(zi, ncL, nc), nc, sz);
-    int n = 0;
+    int cx = cell_coord(xi, ncL, nc), cy = cell_coord(yi, ncL, nc), cz = cell_coord(zi, ncL, nc);
     const int mn = nl.mn;
-    int *out = nl.idx + i;
-    for (int a = 0; a < kz; ++a)
-        for (int bb = 0; bb < ky; ++bb)
-            for (int c = 0; c < kx; ++c) {
-                int cell = coff + (sz[a] * nc + sy[bb]) * nc + sx[c];
-                int s = bd.cell_start[cell], e = bd.cell_start[cell + 1];
+    int *col = nl.idx + i;
+    int np = 0, ni = 0, total = 0;
+    auto add = [&](int j, bool plain) {
+        if (np + ni < mn) {
+            if (plain)
+                col[(size_t)(np++) * N] = j;
+            else
+                col[(size_t)(mn - 1 - (ni++)) * N] = j;
+        }
+        ++total;
+    };
+    if (nc >= 3) {
+        // the 27 cells in ascending Morton order: rows come out ascending in
+        // the neighbour's slot, so the lanes of a wavefront gather nearby
+        // records at the same row
+        int ux[3], uy[3], uz[3];
+        double hx[3], hy[3], hz[3];
+        stencil_shift(cx, nc, L, ux, hx);
+        stencil_shift(cy, nc, L, uy, hy);
+        stencil_shift(cz, nc, L, uz, hz);
+        int key[27];
+        for (int a = 0; a < 3; ++a)
+            for (int bb = 0; bb < 3; ++bb)
+                for (int c = 0; c < 3; ++c)
+                    key[(a * 3 + bb) * 3 + c] = (morton3(ux[c], uy[bb], uz[a]) << 5) | ((a * 3 + bb) * 3 + c);
+        for (int k = 1; k < 27; ++k) {
+            int v = key[k], m = k - 1;
+            while (m >= 0 && key[m] > v) {
+                key[m + 1] = key[m];
+                --m;
+            }
+            key[m + 1] = v;
+        }
+        for (int k = 0; k < 27; ++k) {
+            int t = key[k] & 31;
+            int a = t / 9, bb = (t / 3) % 3, c = t % 3;
+            int cell = coff + (key[k] >> 5);
+            int s = bd.cell_start[cell], e = bd.cell_start[cell + 1];
+            double sx = hx[c], sy = hy[bb], sz = hz[a];
+            if (sx == 0.0 && sy == 0.0 && sz == 0.0) {
                 for (int j = s; j < e; ++j) {
-                    if (j == i) continue;
-                    double dx = st.x[j] - xi;
-                    double dy = st.y[j] - yi;
-                    double dz = st.z[j] - zi;
-                    dx = dx - rint(dx * invL) * L;
-                    dy = dy - rint(dy * invL) * L;
-                    dz = dz - rint(dz * invL) * L;
+                    double2 p2 = ldpk(st.pk, (unsigned)j, 0);
+                    double dx = p2.x - xi;
+                    double dy = p2.y - yi;
+                    double dz = ldpk_z(st.pk, (unsigned)j) - zi;
                     double r2 = (dx * dx + dy * dy) + dz * dz;
-                    if (r2 < rl2) {
-                        if (n < mn) out[(size_t)n * N] = j;
-                        ++n;
-                    }
+                    if (r2 < rl2 && j != i) add(j, true);
+                }
+            } else {
+                for (int j = s; j < e; ++j) {
+                    double2 p2 = ldpk(st.pk, (unsigned)j, 0);
+                    double dx = (p2.x - xi) + sx;
+                    double dy = (p2.y - yi) + sy;
+                    double dz = (ldpk_z(st.pk, (unsigned)j) - zi) + sz;
+                    double r2 = (dx * dx + dy * dy) + dz * dz;
+                    if (r2 < rl2) add(j, false);
                 }
             }
-    nl.count[i] = n;
-    if (n > mn) atomicOr(flags, (unsigned)MD_FLAG_NLIST_OVERFLOW);
+        }
+    } else {
+        int ux[3], uy[3], uz[3];
+        int kx = stencil_1d(cx, nc, ux), ky = stencil_1d(cy, nc, uy), kz = stencil_1d(cz, nc, uz);
+        for (int a = 0; a < kz; ++a)
+            for (int bb = 0; bb < ky; ++bb)
+                for (int c = 0; c < kx; ++c) {
+                    int cell = coff + morton3(ux[c], uy[bb], uz[a]);
+                    int s = bd.cell_start[cell], e = bd.cell_start[cell + 1];
+                    for (int j = s; j < e; ++j) {
+                        if (j == i) continue;
+                        double2 p2 = ldpk(st.pk, (unsigned)j, 0);
+                        double dx = p2.x - xi;
+                        double dy = p2.y - yi;
+                        double dz = ldpk_z(st.pk, (unsigned)j) - zi;
+                        double kx_ = rint(dx * invL), ky_ = rint(dy * invL), kz_ = rint(dz * invL);
+                        dx = dx - kx_ * L;
+                        dy = dy - ky_ * L;
+                        dz = dz - kz_ * L;
+                        double r2 = (dx * dx + dy * dy) + dz * dz;
+                        if (r2 < rl2) add(j, kx_ == 0.0 && ky_ == 0.0 && kz_ == 0.0);
+                    }
+                }
+    }
+    nl.count[i] = np | (ni << 16);
+    nl.total[i] = total;
+    if (total > mn) atomicOr(flags, (unsigned)MD_FLAG_NLIST_OVERFLOW);
 }
 
 // ---------------------------------------------------------------- passes
 
-// a5 + a6: rho_i over listed neighbours with r < rc, then F and F'.
+// Density pass with the embedding fused: rho_i over listed neighbours with
+// r < rc, then F(rho_i) and F'(rho_i).
 template <int KIND, bool MULTI>
 __global__ __launch_bounds__(kBlock) void k_density(int N, State st, Boxes bx, NList nl, Pot pot,
                                                     double L1, double invL1, unsigned *flags)
@@ -421,27 +711,24 @@ __global__ __launch_bounds__(kBlock) void k_density(int N, State st, Boxes bx, N
     if (i >= N) return;
     double L, invL;
     box_geom<MULTI>(bx, i, L1, invL1, L, invL);
-    const double *__restrict__ X = st.x;
-    const double *__restrict__ Y = st.y;
-    const double *__restrict__ Z = st.z;
-    double xi = X[i], yi = Y[i], zi = Z[i];
-    int cnt = min(nl.count[i], nl.mn);
-    const int *__restrict__ lp = nl.idx + i;
+    const double *__restrict__ pk = st.pk;
+    double xi = st.x[i], yi = st.y[i], zi = st.z[i];
+    Row rw = row_of(nl, i);
+    const int *col = nl.idx + i;
     unsigned bad = 0;
     double rho = 0.0;
-    for (int n = 0; n < cnt; ++n, lp += N) {
-        int j = *lp;
-        double dx = min_image(X[j] - xi, L, invL);
-        double dy = min_image(Y[j] - yi, L, invL);
-        double dz = min_image(Z[j] - zi, L, invL);
+    auto body = [&](double dx, double dy, double dz, double) {
         double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-        if (r2 < pot.rc2) rho += dens<KIND>(pot, sqrt(r2), bad);
-    }
+        if (r2 < pot.rc2) rho += dens<KIND>(pot, r2 * rsqrt_nr(r2), bad);
+    };
+    for_pairs<false, false>(col, N, 0, rw.np, pk, xi, yi, zi, L, invL, body);
+    for_pairs<true, false>(col, N, nl.mn - rw.ni, nl.mn, pk, xi, yi, zi, L, invL, body);
     double F, Fp;
     embed<KIND>(pot, rho, F, Fp, bad);
     st.rho[i] = rho;
     st.Femb[i] = F;
     st.Fp[i] = Fp;
+    st.pk[4 * (size_t)i + 3] = Fp;
     raise_flags(flags, bad);
 }
 
@@ -458,7 +745,8 @@ __global__ void k_embed(int N, State st, Pot pot, unsigned *flags)
     raise_flags(flags, bad);
 }
 
-// a7 (+ second half kick of a8): eq. 3 gathered per atom.
+// Force pass (eq. 3) gathered per atom, optionally fused with the second
+// half kick of velocity Verlet.
 template <int KIND, bool MULTI, bool ENERGY, bool KICK>
 __global__ __launch_bounds__(kBlock) void k_force(int N, State st, Boxes bx, NList nl, Pot pot,
                                                   double L1, double invL1, double kick,
@@ -468,34 +756,29 @@ __global__ __launch_bounds__(kBlock) void k_force(int N, State st, Boxes bx, NLi
     if (i >= N) return;
     double L, invL;
     box_geom<MULTI>(bx, i, L1, invL1, L, invL);
-    const double *__restrict__ X = st.x;
-    const double *__restrict__ Y = st.y;
-    const double *__restrict__ Z = st.z;
-    const double *__restrict__ FP = st.Fp;
-    double xi = X[i], yi = Y[i], zi = Z[i];
-    double fpi = FP[i];
-    int cnt = min(nl.count[i], nl.mn);
-    const int *__restrict__ lp = nl.idx + i;
+    const double *__restrict__ pk = st.pk;
+    double xi = st.x[i], yi = st.y[i], zi = st.z[i];
+    double fpi = st.Fp[i];
+    Row rw = row_of(nl, i);
+    const int *col = nl.idx + i;
     unsigned bad = 0;
     double ax = 0.0, ay = 0.0, az = 0.0, ep = 0.0;
-    for (int n = 0; n < cnt; ++n, lp += N) {
-        int j = *lp;
-        double dx = min_image(X[j] - xi, L, invL);
-        double dy = min_image(Y[j] - yi, L, invL);
-        double dz = min_image(Z[j] - zi, L, invL);
+    auto body = [&](double dx, double dy, double dz, double fpj) {
         double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
         if (r2 < pot.rc2) {
-            double r = sqrt(r2);
+            double inv_r = rsqrt_nr(r2);
             double dfr, v, dv;
-            pair_terms<KIND>(pot, r, dfr, v, dv, bad);
+            pair_terms<KIND>(pot, r2 * inv_r, dfr, v, dv, bad);
             // f_i += [(F'_i + F'_j) rho'(r) + V'(r)] (x_j - x_i) / r
-            double coef = fma(fpi + FP[j], dfr, dv) / r;
+            double coef = fma(fpi + fpj, dfr, dv) * inv_r;
             ax = fma(coef, dx, ax);
             ay = fma(coef, dy, ay);
             az = fma(coef, dz, az);
             if constexpr (ENERGY) ep += v;
         }
-    }
+    };
+    for_pairs<false, true>(col, N, 0, rw.np, pk, xi, yi, zi, L, invL, body);
+    for_pairs<true, true>(col, N, nl.mn - rw.ni, nl.mn, pk, xi, yi, zi, L, invL, body);
     st.fx[i] = ax;
     st.fy[i] = ay;
     st.fz[i] = az;
@@ -508,8 +791,9 @@ __global__ __launch_bounds__(kBlock) void k_force(int N, State st, Boxes bx, NLi
     raise_flags(flags, bad);
 }
 
-// a8 first half: v += (dt/2) a; x += dt v; request a rebuild when an atom has
-// moved more than half the skin since the last build (a4).
+// First half of a velocity-Verlet step: v += (dt/2) a; x += dt v; request a
+// list rebuild when an atom has moved more than half the skin since the last
+// build.
 template <bool MULTI>
 __global__ __launch_bounds__(kBlock) void k_kick_drift(int N, State st, Boxes bx, double kick,
                                                        double dt, double thr2_1, unsigned *flags)
@@ -529,6 +813,8 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(int N, State st, Boxes bx
         st.x[i] = x;
         st.y[i] = y;
         st.z[i] = z;
+        reinterpret_cast<double2 *>(st.pk)[2 * (size_t)i] = make_double2(x, y);
+        st.pk[4 * (size_t)i + 2] = z;
         double ddx = x - st.xr[i], ddy = y - st.yr[i], ddz = z - st.zr[i];
         double d2 = fma(ddz, ddz, fma(ddy, ddy, ddx * ddx));
         double thr2 = MULTI ? bx.thr2[bx.box_of[i]] : thr2_1;
@@ -606,10 +892,13 @@ __global__ void k_get_neighbors(int N, State st, NList nl, int32_t *counts, int3
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     int o = st.id[i];
-    int cnt = nl.count[i];
-    counts[o] = cnt;
-    int m = min(min(cnt, nl.mn), cols);
-    for (int n = 0; n < m; ++n) ids[(size_t)o * cols + n] = st.id[nl.idx[(size_t)n * N + i]];
+    Row rw = row_of(nl, i);
+    counts[o] = nl.total[i];
+    int m = 0;
+    for (int n = 0; n < rw.np && m < cols; ++n)
+        ids[(size_t)o * cols + (m++)] = st.id[nl.idx[(size_t)n * N + i]];
+    for (int n = nl.mn - rw.ni; n < nl.mn && m < cols; ++n)
+        ids[(size_t)o * cols + (m++)] = st.id[nl.idx[(size_t)n * N + i]];
 }
 
 // ---------------------------------------------------------------- B-spline
@@ -668,6 +957,11 @@ void launch_fill_u32(unsigned *p, int n, unsigned v, hipStream_t s)
     k_fill_u32<<<grid_for(n), kBlock, 0, s>>>(p, n, v);
 }
 
+void launch_pack_positions(Ctx &c, hipStream_t s)
+{
+    k_pack_positions<<<grid_for(c.N), kBlock, 0, s>>>((int)c.N, c.st);
+}
+
 void launch_set_state(Ctx &c, const double *pos, const double *vel, hipStream_t s)
 {
     k_set_state<<<grid_for(c.N), kBlock, 0, s>>>((int)c.N, pos, vel, c.st);
@@ -685,7 +979,10 @@ void launch_build(Ctx &c, bool gated, hipStream_t s)
     int C = c.bd.n_cells;
     k_clear_cells<<<grid_for(C), kBlock, 0, s>>>(gate, C, c.bd.cell_count);
     k_bin<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.st, c.bx, c.bd, c.dev.flags);
-    k_scan<<<1, 1024, 0, s>>>(gate, C, c.bd.cell_count, c.bd.cell_start);
+    int nb = (C + kScanCells - 1) / kScanCells;
+    k_scan_local<<<nb, 1024, 0, s>>>(gate, C, c.bd.cell_count, c.bd.cell_start, c.bd.bsum);
+    k_scan_top<<<1, 1024, 0, s>>>(gate, nb, c.bd.bsum);
+    k_scan_add<<<grid_for(C), kBlock, 0, s>>>(gate, C, nb, c.bd.cell_start, c.bd.bsum);
     k_scatter<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.bd);
     k_rank<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.st, c.bd);
     k_gather<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.st, c.bd);

@@ -22,6 +22,7 @@ MD_ERR_NONFINITE, MD_ERR_DEVICE, MD_ERR_STATE, MD_ERR_NOMEM = -5, -6, -7, -8
 MD_FLAG_NLIST_OVERFLOW, MD_FLAG_TABLE_RANGE, MD_FLAG_NONFINITE = 1, 2, 4
 MD_POT_FS, MD_POT_SMTB, MD_POT_SPLINE, MD_POT_BSPLINE = 1, 2, 3, 4
 MD_OPT_BATCHED, MD_OPT_BATCH_BLOCK, MD_OPT_USE_GRAPH, MD_OPT_GRAPH_STEPS = 1, 2, 3, 4
+MD_PASS_BUILD, MD_PASS_DENSITY, MD_PASS_FORCE, MD_PASS_KICK_DRIFT = 0, 1, 2, 3
 
 
 class MDError(RuntimeError):
@@ -64,6 +65,8 @@ _SIGS = {
     "md_adjoint": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "md_set_option": ([C.c_void_p, C.c_int32, C.c_int64], C.c_int),
     "md_get_option": ([C.c_void_p, C.c_int32, C.POINTER(C.c_int64)], C.c_int),
+    "md_time_pass": ([C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_double)],
+                     C.c_int),
 }
 
 
@@ -250,6 +253,13 @@ class System:
         out = self._f64(3 * K)
         _check(lib().md_adjoint(self._h, _ptr(g), _ptr(e), _ptr(out), _stream()), "md_adjoint")
         return out
+
+    def time_pass(self, which, reps):
+        """Mean duration (ms) of one launch of a pass, from HIP events on the stream."""
+        ms = C.c_double()
+        _check(lib().md_time_pass(self._h, int(which), int(reps), _stream(), C.byref(ms)),
+               "md_time_pass")
+        return ms.value
 
     def set_option(self, key, value):
         _check(lib().md_set_option(self._h, int(key), int(value)), "md_set_option")
