@@ -59,7 +59,8 @@ enum {
 enum {
     MD_FLAG_NLIST_OVERFLOW = 1u,
     MD_FLAG_TABLE_RANGE = 2u,
-    MD_FLAG_NONFINITE = 4u
+    MD_FLAG_NONFINITE = 4u,
+    MD_FLAG_TILE_OVERFLOW = 8u   /* a tile's halo exceeded its LDS capacity        */
 };
 
 /* Potential kinds. */
@@ -201,7 +202,10 @@ enum {
                                (default when B > 1), 0 the merged-box kernels     */
     MD_OPT_BATCH_BLOCK = 2, /* workgroup size of the persistent kernel (256/512/1024) */
     MD_OPT_USE_GRAPH = 3,   /* md_step replays a captured HIP graph (default 1)     */
-    MD_OPT_GRAPH_STEPS = 4  /* steps per captured graph (default 8)                 */
+    MD_OPT_GRAPH_STEPS = 4, /* steps per captured graph (default 8)                 */
+    MD_OPT_TILED = 5        /* 1: list build, density and force stage each tile's
+                               neighbour records in LDS (default where the tiles
+                               fit); 0: per-atom kernels gathering from HBM       */
 };
 int md_set_option(md_ctx *ctx, int32_t key, int64_t value);
 int md_get_option(const md_ctx *ctx, int32_t key, int64_t *value);

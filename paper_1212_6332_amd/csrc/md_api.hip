@@ -215,6 +215,69 @@ int capture_steps(Ctx &c, int nsteps)
     return MD_OK;
 }
 
+// Tile geometry.  Tiles of tx x ty x tz cells are chosen so that a tile
+// holds about one 1024-thread workgroup of atoms and its halo (the tile grown
+// by one cell) fits the LDS of one workgroup with a 30% margin.  Boxes with at
+// least max(t)+2 cells per axis are cut into such tiles (halo mode A); a
+// smaller box is one tile holding the whole box (mode B).  Without tiling,
+// every box is one tile numbered row-major and the per-atom kernels run.
+int plan_tiles(Ctx &c, double per_cell, bool allow)
+{
+    int max_lds = 0;
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c.device) !=
+        hipSuccess)
+        return MD_ERR_DEVICE;
+    size_t fixed = 8192;  // halo table and scan scratch (static LDS)
+    c.hmax = max_lds > (int)fixed ? (int)((max_lds - fixed) / 32) : 0;
+    c.tile_lds = (size_t)c.hmax * 32;
+    int best[3] = {0, 0, 0};
+    double best_atoms = 0.0;
+    for (int tz = 1; tz <= 6; ++tz)
+        for (int ty = tz; ty <= 6; ++ty)
+            for (int tx = ty; tx <= 6; ++tx) {
+                double atoms = tx * ty * tz * per_cell;
+                int halo_cells = (tx + 2) * (ty + 2) * (tz + 2);
+                double halo = halo_cells * per_cell;
+                if (atoms > 1100.0 || 1.3 * halo > c.hmax || halo_cells > kHaloCells) continue;
+                if (atoms > best_atoms) {
+                    best_atoms = atoms;
+                    best[0] = tx;
+                    best[1] = ty;
+                    best[2] = tz;
+                }
+            }
+    bool feasible = allow && best[0] > 0;
+    int tmax = std::max(best[0], std::max(best[1], best[2]));
+    for (int b = 0; b < c.B && feasible; ++b) {
+        int nc = c.box_nc[b];
+        if (nc >= tmax + 2) continue;
+        double nb = (double)(c.box_off[b + 1] - c.box_off[b]);
+        if (1.3 * nb > c.hmax || nc * nc * nc > kHaloCells) feasible = false;
+    }
+    c.tile_feasible = feasible;
+    c.tiled = feasible;
+    c.box_tile.assign(8 * (size_t)c.B, 0);
+    c.ntiles = 0;
+    for (int b = 0; b < c.B; ++b) {
+        int nc = c.box_nc[b];
+        int *t = &c.box_tile[8 * b];
+        if (feasible && nc >= tmax + 2) {
+            for (int d = 0; d < 3; ++d) {
+                t[d] = best[d];
+                t[3 + d] = (nc + best[d] - 1) / best[d];
+            }
+            t[7] = kTileA;
+        } else {
+            t[0] = t[1] = t[2] = nc;
+            t[3] = t[4] = t[5] = 1;
+            t[7] = feasible ? kTileB : kTileGlobal;
+        }
+        t[6] = t[0] * t[1] * t[2];
+        c.ntiles += t[3] * t[4] * t[5];
+    }
+    return MD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -273,25 +336,28 @@ int md_create(const md_system *sys, const md_potential *pot, md_ctx **out)
     c.box_rlist.resize(B);
     c.box_nc.resize(B);
     c.box_cell_off.resize(B + 1);
-    int64_t cells = 0;
-    double mn_est = 0.0;
+    double mn_est = 0.0, per_cell = 0.0;
     for (int b = 0; b < B; ++b) {
         double L = c.box_len[b];
         double rl = list_radius(pot->rc, sys->skin, L);
         c.box_rlist[b] = rl;
         int nc = cells_per_dim(L, rl);
-        if (nc > 1024) nc = 1024;  // Morton cell indices use 10 bits per axis
         c.box_nc[b] = nc;
-        c.box_cell_off[b] = (int)cells;
-        int64_t pw = 1;
-        while (pw < nc) pw <<= 1;  // Morton indices of a box span the next power of two
-        cells += pw * pw * pw;
         double nb = (double)(c.box_off[b + 1] - c.box_off[b]);
+        per_cell = std::max(per_cell, nb / ((double)nc * nc * nc));
         double expect = nb / (L * L * L) * 4.0 / 3.0 * M_PI * rl * rl * rl;
         double est = std::min(nb - 1.0, std::ceil(1.4 * expect + 16.0));
         mn_est = std::max(mn_est, est);
     }
-    if (cells >= (int64_t)1 << 30) return fail(MD_ERR_ARG);
+    int rc_t = plan_tiles(c, per_cell, pot->kind != MD_POT_BSPLINE);
+    if (rc_t != MD_OK) return fail(rc_t);
+    int64_t cells = 0;
+    for (int b = 0; b < B; ++b) {
+        const int *t = &c.box_tile[8 * b];
+        c.box_cell_off[b] = (int)cells;
+        cells += (int64_t)t[3] * t[4] * t[5] * t[6];
+        if (cells >= (int64_t)1 << 30) return fail(MD_ERR_ARG);
+    }
     c.box_cell_off[B] = (int)cells;
     c.bd.n_cells = (int)cells;
     int mn = sys->max_neighbors > 0 ? sys->max_neighbors : ((int)mn_est + 7) / 8 * 8;
@@ -334,6 +400,28 @@ int md_create(const md_system *sys, const md_potential *pot, md_ctx **out)
         c.bx.cell_off = c.d_boxi + B;
         c.bx.atom_off = c.d_boxi + 2 * B;
         c.bx.box_of = c.d_boxi + 3 * B + 1;
+    }
+
+    // tile descriptors
+    {
+        std::vector<int> ht(8 * (size_t)B + B + 1 + c.ntiles);
+        std::copy(c.box_tile.begin(), c.box_tile.end(), ht.begin());
+        int g = 0;
+        for (int b = 0; b < B; ++b) {
+            ht[8 * B + b] = g;
+            const int *t = &c.box_tile[8 * b];
+            for (int k = 0; k < t[3] * t[4] * t[5]; ++k) ht[9 * B + 1 + g + k] = b;
+            g += t[3] * t[4] * t[5];
+        }
+        ht[9 * B] = g;
+        if ((rc = dev_alloc(c, &c.d_tiles, ht.size())) != MD_OK) return fail(rc);
+        if (hipMemcpy(c.d_tiles, ht.data(), ht.size() * sizeof(int), hipMemcpyHostToDevice) !=
+            hipSuccess)
+            return fail(MD_ERR_DEVICE);
+        c.bx.tile = c.d_tiles;
+        c.bx.tile_off = c.d_tiles + 8 * B;
+        c.bx.tile_box = c.d_tiles + 9 * B + 1;
+        if (c.tile_feasible) tiled_prepare(c);
     }
 
     // atom state and build scratch
@@ -699,6 +787,14 @@ int md_set_option(md_ctx *h, int32_t key, int64_t v)
         c.graph_steps = (int)v;
         graph_reset(c);
         return MD_OK;
+    case MD_OPT_TILED:
+        if (v && !c.tile_feasible) return MD_ERR_ARG;
+        if ((v != 0) != c.tiled) {
+            c.tiled = v != 0;
+            graph_reset(c);
+            c.list_valid = c.density_valid = c.forces_valid = false;
+        }
+        return MD_OK;
     }
     return MD_ERR_ARG;
 }
@@ -712,6 +808,7 @@ int md_get_option(const md_ctx *h, int32_t key, int64_t *v)
     case MD_OPT_BATCH_BLOCK: *v = c.batch_block; return MD_OK;
     case MD_OPT_USE_GRAPH: *v = c.use_graph; return MD_OK;
     case MD_OPT_GRAPH_STEPS: *v = c.graph_steps; return MD_OK;
+    case MD_OPT_TILED: *v = c.tiled; return MD_OK;
     }
     return MD_ERR_ARG;
 }

@@ -1,0 +1,211 @@
+// Device helpers shared by the kernel files of libmd.so: potential
+// evaluation (eq. 1 forms and lookup tables), distance arithmetic, cell and
+// tile geometry.  All functions are inline device code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "md_internal.h"
+
+namespace mdk {
+namespace dev {
+
+// ---------------------------------------------------------------- arithmetic
+
+// Minimum image of a separation component: d - L * rint(d / L).  For the
+// separations that can be listed (|d| < L/2 after the correction) this
+// equals subtracting or adding L once, exactly.
+__device__ __forceinline__ double min_image(double d, double L, double invL)
+{
+    return fma(-L, rint(d * invL), d);
+}
+
+// 1/sqrt(a), a > 0: hardware estimate refined by two Newton steps
+// y <- y + y (1/2 - a y^2 / 2).
+__device__ __forceinline__ double rsqrt_nr(double a)
+{
+    double y = __builtin_amdgcn_rsq(a);
+    double h = 0.5 * a;
+    double e = fma(-h * y, y, 0.5);
+    y = fma(y, e, y);
+    e = fma(-h * y, y, 0.5);
+    return fma(y, e, y);
+}
+
+// exp(x) on the vector ALU alone: x = k ln2 + r with |r| <= ln2/2 (ln 2 split
+// in a 32-bit head and a tail so k ln2 is exact), exp(r) by its Taylor
+// polynomial of degree 13 (truncation < 5e-18 relative), then exp(x) =
+// 2^k exp(r).  Arguments are clamped to the range where exp is finite and
+// normal or gradually underflows.
+__device__ __forceinline__ double exp_fast(double x, const Pot &p)
+{
+    x = fmin(fmax(x, -745.0), 709.0);
+    double k = rint(x * 1.4426950408889634074);
+    double r = fma(-k, p.l2hi, x);
+    r = fma(-k, p.l2lo, r);
+    double q = 1.0 / 6227020800.0;  // 1/13!
+    q = fma(q, r, 1.0 / 479001600.0);
+    q = fma(q, r, 1.0 / 39916800.0);
+    q = fma(q, r, 1.0 / 3628800.0);
+    q = fma(q, r, 1.0 / 362880.0);
+    q = fma(q, r, 1.0 / 40320.0);
+    q = fma(q, r, 1.0 / 5040.0);
+    q = fma(q, r, 1.0 / 720.0);
+    q = fma(q, r, 1.0 / 120.0);
+    q = fma(q, r, 1.0 / 24.0);
+    q = fma(q, r, 1.0 / 6.0);
+    q = fma(q, r, 0.5);
+    q = fma(q, r, 1.0);
+    q = fma(q, r, 1.0);
+    return ldexp(q, (int)k);
+}
+
+// ---------------------------------------------------------------- potential
+
+__device__ __forceinline__ void table_eval(const Table &t, double x, double &s, double &ds,
+                                           unsigned &bad)
+{
+    double u = (x - t.lo) * t.inv_h;
+    int m = (int)floor(u);
+    if (!(x >= t.lo && x <= t.hi)) bad |= MD_FLAG_TABLE_RANGE;
+    m = m < 0 ? 0 : (m > t.n - 1 ? t.n - 1 : m);
+    double tt = u - (double)m;
+    const double2 *p = reinterpret_cast<const double2 *>(t.c + 4 * m);
+    double2 ab = p[0], cd = p[1];
+    s = fma(tt, fma(tt, fma(tt, cd.y, cd.x), ab.y), ab.x);
+    ds = fma(tt, fma(tt, 3.0 * cd.y, 2.0 * cd.x), ab.y) * t.inv_h;
+}
+
+// Density contribution rho(r).
+template <int KIND>
+__device__ __forceinline__ double dens(const Pot &p, double r, unsigned &bad)
+{
+    if constexpr (KIND == MD_POT_FS) {
+        double u = r - p.d;
+        return r < p.d ? u * u : 0.0;
+    } else if constexpr (KIND == MD_POT_SMTB) {
+        return exp_fast(fma(p.af, r, p.bf), p);
+    } else {
+        double s, ds;
+        table_eval(p.tab[1], r, s, ds, bad);
+        return s;
+    }
+}
+
+// rho'(r), V(r), V'(r).
+template <int KIND>
+__device__ __forceinline__ void pair_terms(const Pot &p, double r, double &dfr, double &v,
+                                           double &dv, unsigned &bad)
+{
+    if constexpr (KIND == MD_POT_FS) {
+        double u = r - p.d;
+        dfr = r < p.d ? 2.0 * u : 0.0;
+        double w = r - p.c;
+        double poly = fma(r, fma(r, p.c2, p.c1), p.c0);
+        double dpoly = fma(2.0 * p.c2, r, p.c1);
+        bool in = r < p.c;
+        v = in ? w * w * poly : 0.0;
+        dv = in ? w * fma(w, dpoly, 2.0 * poly) : 0.0;
+    } else if constexpr (KIND == MD_POT_SMTB) {
+        double ef = exp_fast(fma(p.af, r, p.bf), p);
+        double ev = exp_fast(fma(p.av, r, p.bv), p);
+        dfr = p.af * ef;
+        v = ev;
+        dv = p.av * ev;
+    } else {
+        double s;
+        table_eval(p.tab[1], r, s, dfr, bad);
+        table_eval(p.tab[0], r, v, dv, bad);
+    }
+}
+
+// F(rho), F'(rho).
+template <int KIND>
+__device__ __forceinline__ void embed(const Pot &p, double rho, double &F, double &Fp,
+                                      unsigned &bad)
+{
+    if constexpr (KIND == MD_POT_FS || KIND == MD_POT_SMTB) {
+        double A = (KIND == MD_POT_FS) ? p.A : 1.0;
+        if (rho > 0.0) {
+            double s = sqrt(rho);
+            F = -A * s;
+            Fp = -0.5 * A / s;
+        } else {
+            F = 0.0;
+            Fp = 0.0;
+        }
+    } else {
+        table_eval(p.tab[2], rho, F, Fp, bad);
+    }
+}
+
+// ---------------------------------------------------------------- cells
+
+__device__ __forceinline__ double wrap1(double x, double L)
+{
+    while (x < 0.0) x += L;
+    while (x >= L) x -= L;
+    return x;
+}
+
+// Cell of a wrapped coordinate along one axis.
+__device__ __forceinline__ int cell_coord(double x, double ncL, int nc)
+{
+    int c = (int)(x * ncL);
+    return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
+// Distinct cells {c-1, c, c+1} modulo nc along one axis.
+__device__ __forceinline__ int stencil_1d(int c, int nc, int out[3])
+{
+    if (nc == 1) {
+        out[0] = 0;
+        return 1;
+    }
+    if (nc == 2) {
+        out[0] = 0;
+        out[1] = 1;
+        return 2;
+    }
+    out[0] = c == 0 ? nc - 1 : c - 1;
+    out[1] = c;
+    out[2] = c == nc - 1 ? 0 : c + 1;
+    return 3;
+}
+
+// Neighbour cells along one axis for three or more cells, with the periodic
+// shift that brings x_j - x_i to the minimum image: +L for the cell past the
+// upper end (wrapped to 0), -L for the cell past the lower end.
+__device__ __forceinline__ void stencil_shift(int c, int nc, double L, int cell[3], double sh[3])
+{
+    cell[0] = c == 0 ? nc - 1 : c - 1;
+    sh[0] = c == 0 ? -L : 0.0;
+    cell[1] = c;
+    sh[1] = 0.0;
+    cell[2] = c == nc - 1 ? 0 : c + 1;
+    sh[2] = c == nc - 1 ? L : 0.0;
+}
+
+// Cells are numbered tile by tile: a box's cells are grouped in tiles of
+// tx x ty x tz cells (row-major over the tile grid, row-major inside a tile),
+// so the atoms of one tile are contiguous once sorted by cell.
+__device__ __forceinline__ int cell_id(const Boxes &bx, int b, int cx, int cy, int cz)
+{
+    const int *g = bx.tile + 8 * b;  // tx ty tz gx gy gz tile_cells mode
+    int tx = g[0], ty = g[1], tz = g[2], gx = g[3], gy = g[4], tc = g[6];
+    int Tx = cx / tx, Ty = cy / ty, Tz = cz / tz;
+    int lx = cx - Tx * tx, ly = cy - Ty * ty, lz = cz - Tz * tz;
+    return bx.cell_off[b] + ((Tz * gy + Ty) * gx + Tx) * tc + (lz * ty + ly) * tx + lx;
+}
+
+// Build kernels run unconditionally (gate == nullptr) or only when the device
+// rebuild request is set (inside replayed steps).
+__device__ __forceinline__ bool skip(const unsigned *gate) { return gate && gate[1] == 0u; }
+
+__device__ __forceinline__ void raise_flags(unsigned *flags, unsigned bad)
+{
+    if (bad) atomicOr(flags, bad);
+}
+
+}  // namespace dev
+}  // namespace mdk

@@ -13,6 +13,9 @@ namespace mdk {
 
 constexpr int kBlock = 256;        // threads per workgroup of the per-atom kernels
 constexpr int kChunk = 4096;       // atoms per partial sum of the energy reductions
+constexpr int kTileThreads = 1024; // threads of a tiled-pass workgroup (one tile)
+constexpr int kHaloCells = 512;    // halo cells a tile may have
+constexpr int kTileGlobal = 0, kTileA = 1, kTileB = 2;  // halo modes of a box
 
 // Per-interval cubic table on a uniform grid: c[4*m + {0,1,2,3}] = a, b, c, d.
 struct Table {
@@ -44,6 +47,9 @@ struct State {
 struct Boxes {
     const double *L, *invL, *rl2, *thr2;
     const int *nc, *cell_off, *atom_off, *box_of;
+    const int *tile;                   // per box: tx ty tz gx gy gz tile_cells mode
+    const int *tile_off;               // per box: first global tile index [B+1]
+    const int *tile_box;               // per global tile: its box
 };
 
 // Scratch of the list build.
@@ -87,6 +93,12 @@ void launch_get_neighbors(Ctx &c, int32_t *counts, int32_t *ids, int32_t max_col
                           hipStream_t s);
 void launch_bspline_tables(Ctx &c, const double *theta, hipStream_t s);
 void launch_fill_u32(unsigned *p, int n, unsigned v, hipStream_t s);
+// Tiled passes (md_tiled.hip).
+void tiled_prepare(Ctx &c);
+void launch_tile_nlist(Ctx &c, const unsigned *gate, hipStream_t s);
+void launch_tile_density(Ctx &c, hipStream_t s);
+void launch_tile_force(Ctx &c, bool energy, bool kick, hipStream_t s);
+void launch_tile_get_neighbors(Ctx &c, int32_t *counts, int32_t *ids, int32_t cols, hipStream_t s);
 void launch_pack_positions(Ctx &c, hipStream_t s);
 
 // Form (2), md_batched.hip.
@@ -116,6 +128,12 @@ struct Ctx {
     std::vector<int64_t> box_off;
     std::vector<double> box_len, box_rlist;
     std::vector<int> box_nc, box_cell_off;
+    std::vector<int> box_tile;         // per box: tx ty tz gx gy gz tile_cells mode
+    int ntiles = 0;
+    bool tiled = false, tile_feasible = false;
+    int hmax = 0;                      // LDS records per tile
+    size_t tile_lds = 0;               // dynamic LDS bytes of a tiled-pass workgroup
+    int *d_tiles = nullptr;            // tile(8B) | tile_off(B+1) | tile_box(ntiles)
     double *d_boxd = nullptr;          // L | invL | rl2 | thr2, each [B]
     int *d_boxi = nullptr;             // nc | cell_off | atom_off(B+1) | box_of(N)
     Boxes bx{};

@@ -20,11 +20,14 @@
 
 #include <cmath>
 
+#include "md_device.h"
 #include "md_internal.h"
 
 namespace mdk {
 
 namespace {
+
+using namespace dev;
 
 constexpr int kXcds = 8;
 
@@ -40,14 +43,6 @@ __device__ __forceinline__ int xcd_block(int b, int G)
 __device__ __forceinline__ int atom_index()
 {
     return xcd_block((int)blockIdx.x, (int)gridDim.x) * (int)blockDim.x + (int)threadIdx.x;
-}
-
-// Minimum image of a separation component: d - L * rint(d / L).  For the
-// separations that can be listed (|d| < L/2 after the correction) this
-// equals subtracting or adding L once, exactly.
-__device__ __forceinline__ double min_image(double d, double L, double invL)
-{
-    return fma(-L, rint(d * invL), d);
 }
 
 // Gather with a 32-bit byte offset from a uniform base pointer (the compiler
@@ -68,46 +63,6 @@ __device__ __forceinline__ double2 ldpk(const double *__restrict__ pk, unsigned 
 __device__ __forceinline__ double ldpk_z(const double *__restrict__ pk, unsigned j)
 {
     return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(pk) + (j << 5) + 16);
-}
-
-// 1/sqrt(a), a > 0: hardware estimate refined by two Newton steps
-// y <- y + y (1/2 - a y^2 / 2).
-__device__ __forceinline__ double rsqrt_nr(double a)
-{
-    double y = __builtin_amdgcn_rsq(a);
-    double h = 0.5 * a;
-    double e = fma(-h * y, y, 0.5);
-    y = fma(y, e, y);
-    e = fma(-h * y, y, 0.5);
-    return fma(y, e, y);
-}
-
-// exp(x) on the vector ALU alone: x = k ln2 + r with |r| <= ln2/2 (ln 2 split
-// in a 32-bit head and a tail so k ln2 is exact), exp(r) by its Taylor
-// polynomial of degree 13 (truncation < 5e-18 relative), then exp(x) =
-// 2^k exp(r).  Arguments are clamped to the range where exp is finite and
-// normal or gradually underflows.
-__device__ __forceinline__ double exp_fast(double x, const Pot &p)
-{
-    x = fmin(fmax(x, -745.0), 709.0);
-    double k = rint(x * 1.4426950408889634074);
-    double r = fma(-k, p.l2hi, x);
-    r = fma(-k, p.l2lo, r);
-    double q = 1.0 / 6227020800.0;          // 1/13!
-    q = fma(q, r, 1.0 / 479001600.0);       // 1/12!
-    q = fma(q, r, 1.0 / 39916800.0);
-    q = fma(q, r, 1.0 / 3628800.0);
-    q = fma(q, r, 1.0 / 362880.0);
-    q = fma(q, r, 1.0 / 40320.0);
-    q = fma(q, r, 1.0 / 5040.0);
-    q = fma(q, r, 1.0 / 720.0);
-    q = fma(q, r, 1.0 / 120.0);
-    q = fma(q, r, 1.0 / 24.0);
-    q = fma(q, r, 1.0 / 6.0);
-    q = fma(q, r, 0.5);
-    q = fma(q, r, 1.0);
-    q = fma(q, r, 1.0);
-    return ldexp(q, (int)k);
 }
 
 // Neighbour row of slot i: `np` pairs that need no periodic correction at
@@ -160,105 +115,6 @@ __device__ __forceinline__ void for_pairs(const int *__restrict__ col, int N, in
     }
 }
 
-// Morton (Z-order) index of a cell: interleaved bits of its three
-// coordinates (each below 1024).  Cells that are close in space get close
-// indices, so the atoms a group of workgroups touches stay in one L2.
-__device__ __forceinline__ unsigned spread3(unsigned v)
-{
-    v &= 0x3ffu;
-    v = (v | (v << 16)) & 0x030000ffu;
-    v = (v | (v << 8)) & 0x0300f00fu;
-    v = (v | (v << 4)) & 0x030c30c3u;
-    v = (v | (v << 2)) & 0x09249249u;
-    return v;
-}
-
-__device__ __forceinline__ int morton3(int cx, int cy, int cz)
-{
-    return (int)(spread3((unsigned)cx) | (spread3((unsigned)cy) << 1) |
-                 (spread3((unsigned)cz) << 2));
-}
-
-// ---------------------------------------------------------------- potential
-
-__device__ __forceinline__ void table_eval(const Table &t, double x, double &s, double &ds,
-                                           unsigned &bad)
-{
-    double u = (x - t.lo) * t.inv_h;
-    double fm = floor(u);
-    int m = (int)fm;
-    if (!(x >= t.lo && x <= t.hi)) bad |= MD_FLAG_TABLE_RANGE;
-    m = m < 0 ? 0 : (m > t.n - 1 ? t.n - 1 : m);
-    double tt = u - (double)m;
-    const double2 *p = reinterpret_cast<const double2 *>(t.c + 4 * m);
-    double2 ab = p[0], cd = p[1];
-    s = fma(tt, fma(tt, fma(tt, cd.y, cd.x), ab.y), ab.x);
-    ds = fma(tt, fma(tt, 3.0 * cd.y, 2.0 * cd.x), ab.y) * t.inv_h;
-}
-
-// Density contribution rho(r).
-template <int KIND>
-__device__ __forceinline__ double dens(const Pot &p, double r, unsigned &bad)
-{
-    if constexpr (KIND == MD_POT_FS) {
-        double u = r - p.d;
-        return r < p.d ? u * u : 0.0;
-    } else if constexpr (KIND == MD_POT_SMTB) {
-        return exp_fast(fma(p.af, r, p.bf), p);
-    } else {
-        double s, ds;
-        table_eval(p.tab[1], r, s, ds, bad);
-        return s;
-    }
-}
-
-// rho'(r), V(r), V'(r).
-template <int KIND>
-__device__ __forceinline__ void pair_terms(const Pot &p, double r, double &dfr, double &v,
-                                           double &dv, unsigned &bad)
-{
-    if constexpr (KIND == MD_POT_FS) {
-        double u = r - p.d;
-        dfr = r < p.d ? 2.0 * u : 0.0;
-        double w = r - p.c;
-        double poly = fma(r, fma(r, p.c2, p.c1), p.c0);
-        double dpoly = fma(2.0 * p.c2, r, p.c1);
-        bool in = r < p.c;
-        v = in ? w * w * poly : 0.0;
-        dv = in ? w * fma(w, dpoly, 2.0 * poly) : 0.0;
-    } else if constexpr (KIND == MD_POT_SMTB) {
-        double ef = exp_fast(fma(p.af, r, p.bf), p);
-        double ev = exp_fast(fma(p.av, r, p.bv), p);
-        dfr = p.af * ef;
-        v = ev;
-        dv = p.av * ev;
-    } else {
-        double s;
-        table_eval(p.tab[1], r, s, dfr, bad);
-        table_eval(p.tab[0], r, v, dv, bad);
-    }
-}
-
-// F(rho), F'(rho), F''(rho).
-template <int KIND>
-__device__ __forceinline__ void embed(const Pot &p, double rho, double &F, double &Fp,
-                                      unsigned &bad)
-{
-    if constexpr (KIND == MD_POT_FS || KIND == MD_POT_SMTB) {
-        double A = (KIND == MD_POT_FS) ? p.A : 1.0;
-        if (rho > 0.0) {
-            double s = sqrt(rho);
-            F = -A * s;
-            Fp = -0.5 * A / s;
-        } else {
-            F = 0.0;
-            Fp = 0.0;
-        }
-    } else {
-        table_eval(p.tab[2], rho, F, Fp, bad);
-    }
-}
-
 template <bool MULTI>
 __device__ __forceinline__ void box_geom(const Boxes &bx, int i, double L1, double invL1,
                                          double &L, double &invL)
@@ -271,11 +127,6 @@ __device__ __forceinline__ void box_geom(const Boxes &bx, int i, double L1, doub
         L = L1;
         invL = invL1;
     }
-}
-
-__device__ __forceinline__ void raise_flags(unsigned *flags, unsigned bad)
-{
-    if (bad) atomicOr(flags, bad);
 }
 
 // ---------------------------------------------------------------- state I/O
@@ -346,10 +197,6 @@ __global__ void k_fill_u32(unsigned *p, int n, unsigned v)
 
 // ---------------------------------------------------------------- list build
 
-// Build kernels run unconditionally (gate == nullptr) or only when the device
-// rebuild request is set (inside replayed steps).
-__device__ __forceinline__ bool skip(const unsigned *gate) { return gate && gate[1] == 0u; }
-
 __global__ void k_clear_cells(const unsigned *gate, int C, int *cell_count)
 {
     if (skip(gate)) return;
@@ -357,21 +204,7 @@ __global__ void k_clear_cells(const unsigned *gate, int C, int *cell_count)
     if (c < C) cell_count[c] = 0;
 }
 
-// Cell of a wrapped coordinate along one axis.
-__device__ __forceinline__ int cell_coord(double x, double ncL, int nc)
-{
-    int c = (int)(x * ncL);
-    return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
-}
-
-__device__ __forceinline__ double wrap1(double x, double L)
-{
-    while (x < 0.0) x += L;
-    while (x >= L) x -= L;
-    return x;
-}
-
-// Binning: wrap into the box, find the cell (Morton index within the box),
+// Binning: wrap into the box, find the cell (numbered tile by tile),
 // count atoms per cell.  Consecutive slots mostly share a cell (the state is
 // sorted from the previous build), so each run of equal cells in a
 // wavefront takes its slots with one atomic add.
@@ -398,8 +231,8 @@ __global__ __launch_bounds__(kBlock) void k_bin(const unsigned *gate, int N, Sta
         st.y[i] = y;
         st.z[i] = z;
         double ncL = nc * bx.invL[b];
-        cell = bx.cell_off[b] +
-               morton3(cell_coord(x, ncL, nc), cell_coord(y, ncL, nc), cell_coord(z, ncL, nc));
+        cell = cell_id(bx, b, cell_coord(x, ncL, nc), cell_coord(y, ncL, nc),
+                       cell_coord(z, ncL, nc));
         bd.cell_of[i] = cell;
     }
     int lane = threadIdx.x & 63;
@@ -557,37 +390,6 @@ __global__ void k_commit(const unsigned *gate, int N, State st, Build bd)
     st.id[q] = bd.sid[q];
 }
 
-// Distinct cells {c-1, c, c+1} modulo nc along one axis.
-__device__ __forceinline__ int stencil_1d(int c, int nc, int out[3])
-{
-    if (nc == 1) {
-        out[0] = 0;
-        return 1;
-    }
-    if (nc == 2) {
-        out[0] = 0;
-        out[1] = 1;
-        return 2;
-    }
-    out[0] = c == 0 ? nc - 1 : c - 1;
-    out[1] = c;
-    out[2] = c == nc - 1 ? 0 : c + 1;
-    return 3;
-}
-
-// Distinct neighbour cells along one axis for three or more cells, with
-// the periodic shift that brings x_j - x_i to the minimum image: +L for the
-// cell past the upper end (wrapped to 0), -L for the cell past the lower end.
-__device__ __forceinline__ void stencil_shift(int c, int nc, double L, int cell[3], double sh[3])
-{
-    cell[0] = c == 0 ? nc - 1 : c - 1;
-    sh[0] = c == 0 ? -L : 0.0;
-    cell[1] = c;
-    sh[1] = 0.0;
-    cell[2] = c == nc - 1 ? 0 : c + 1;
-    sh[2] = c == nc - 1 ? L : 0.0;
-}
-
 // Full list of slot i.  r^2 = (dx*dx + dy*dy) + dz*dz with separate
 // roundings (no contraction) so that membership is reproducible exactly; the
 // periodic correction is one exact addition of +-L, as in the minimum image.
@@ -624,7 +426,7 @@ __global__ __launch_bounds__(kBlock) void k_nlist(const unsigned *gate, int N, S
         ++total;
     };
     if (nc >= 3) {
-        // the 27 cells in ascending Morton order: rows come out ascending in
+        // the 27 cells in ascending cell order: rows come out ascending in
         // the neighbour's slot, so the lanes of a wavefront gather nearby
         // records at the same row
         int ux[3], uy[3], uz[3];
@@ -636,7 +438,8 @@ __global__ __launch_bounds__(kBlock) void k_nlist(const unsigned *gate, int N, S
         for (int a = 0; a < 3; ++a)
             for (int bb = 0; bb < 3; ++bb)
                 for (int c = 0; c < 3; ++c)
-                    key[(a * 3 + bb) * 3 + c] = (morton3(ux[c], uy[bb], uz[a]) << 5) | ((a * 3 + bb) * 3 + c);
+                    key[(a * 3 + bb) * 3 + c] = ((cell_id(bx, b, ux[c], uy[bb], uz[a]) - coff) << 5) |
+                                                ((a * 3 + bb) * 3 + c);
         for (int k = 1; k < 27; ++k) {
             int v = key[k], m = k - 1;
             while (m >= 0 && key[m] > v) {
@@ -677,7 +480,7 @@ __global__ __launch_bounds__(kBlock) void k_nlist(const unsigned *gate, int N, S
         for (int a = 0; a < kz; ++a)
             for (int bb = 0; bb < ky; ++bb)
                 for (int c = 0; c < kx; ++c) {
-                    int cell = coff + morton3(ux[c], uy[bb], uz[a]);
+                    int cell = cell_id(bx, b, ux[c], uy[bb], uz[a]);
                     int s = bd.cell_start[cell], e = bd.cell_start[cell + 1];
                     for (int j = s; j < e; ++j) {
                         if (j == i) continue;
@@ -987,12 +790,19 @@ void launch_build(Ctx &c, bool gated, hipStream_t s)
     k_rank<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.st, c.bd);
     k_gather<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.st, c.bd);
     k_commit<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.st, c.bd);
-    k_nlist<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.st, c.bx, c.bd, c.nl, c.dev.flags);
+    if (c.tiled)
+        launch_tile_nlist(c, gate, s);
+    else
+        k_nlist<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.st, c.bx, c.bd, c.nl, c.dev.flags);
     if (!gated) k_count_build<<<1, 1, 0, s>>>(c.dev.flags);
 }
 
 void launch_density(Ctx &c, hipStream_t s)
 {
+    if (c.tiled) {
+        launch_tile_density(c, s);
+        return;
+    }
     bool multi = c.B > 1;
     switch (c.pot.kind) {
     case MD_POT_FS: multi ? density_t<MD_POT_FS, true>(c, s) : density_t<MD_POT_FS, false>(c, s); break;
@@ -1013,6 +823,10 @@ void launch_embed(Ctx &c, hipStream_t s)
 
 void launch_force(Ctx &c, bool energy, bool kick, hipStream_t s)
 {
+    if (c.tiled) {
+        launch_tile_force(c, energy, kick, s);
+        return;
+    }
     bool multi = c.B > 1;
     switch (c.pot.kind) {
     case MD_POT_FS: multi ? force_t<MD_POT_FS, true>(c, energy, kick, s) : force_t<MD_POT_FS, false>(c, energy, kick, s); break;
@@ -1053,6 +867,10 @@ void launch_box_sums(Ctx &c, int what, double *out, hipStream_t s)
 
 void launch_get_neighbors(Ctx &c, int32_t *counts, int32_t *ids, int32_t max_cols, hipStream_t s)
 {
+    if (c.tiled) {
+        launch_tile_get_neighbors(c, counts, ids, max_cols, s);
+        return;
+    }
     k_get_neighbors<<<grid_for(c.N), kBlock, 0, s>>>((int)c.N, c.st, c.nl, counts, ids, max_cols);
 }
 

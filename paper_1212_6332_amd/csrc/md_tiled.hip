@@ -1,0 +1,476 @@
+// Tiled passes: the neighbour records a workgroup needs are staged in LDS.
+//
+// Cells are numbered tile by tile, so the atoms of a tile of tx x ty x tz
+// cells are one contiguous range of sorted slots.  One 1024-thread
+// workgroup owns one tile.  It first stages the records of the tile's halo
+// -- the tile's cells plus one layer of cells around them (the union of the
+// 27-cell stencils of Fig. 3) -- from HBM/L2 into LDS, then every thread
+// evaluates its atoms' neighbour rows against LDS.  The paper stages list
+// candidates in shared memory the same way (Fig. 3, spos); here the density
+// and force passes do it too, which turns their scattered global gathers
+// (the limiting cost of the per-atom kernels) into LDS reads.
+//
+// Two halo modes, fixed per box:
+//  A  (boxes with at least max(t)+2 cells per axis): the halo is the tile
+//     grown by one cell, with cells that wrap around the box staged at the
+//     periodic image next to the tile.  The list build applies the image
+//     shift per halo cell as one exact addition, (x_j - x_i) + s, as the
+//     minimum image does; the passes stage pre-shifted coordinates and need
+//     no minimum image at all.
+//  B  (small boxes): one tile is the whole box, staged once without shifts;
+//     the list build and the passes take the minimum image per pair.
+// Rows hold LDS indices of the tile's halo.
+#include <hip/hip_runtime.h>
+
+#include "md_device.h"
+#include "md_internal.h"
+
+namespace mdk {
+
+namespace {
+
+using namespace dev;
+
+constexpr int kT = kTileThreads;
+
+struct Tile {
+    int b, nc, mode;
+    double L, invL;
+    int ox, oy, oz;   // first cell of the tile
+    int hx, hy, hz;   // halo extent in cells
+    int s0, s1;       // slot range of the tile
+    int nh;           // halo cells
+};
+
+// Shared halo table: per halo cell, LDS offset, first slot, image shift code.
+struct HaloLds {
+    int off[kHaloCells + 1];
+    int start[kHaloCells];
+    int shift[kHaloCells];   // (sx+1) | (sy+1) << 2 | (sz+1) << 4, s in {-1, 0, 1}
+    int wsum[16];
+    int total;
+};
+
+__device__ __forceinline__ int xcd_tile(int b, int G)
+{
+    const int X = 8;
+    int q = G / X, r = G % X, k = b % X, w = b / X;
+    return (k < r) ? k * (q + 1) + w : r * (q + 1) + (k - r) * q + w;
+}
+
+__device__ __forceinline__ void tile_setup(const Boxes &bx, const Build &bd, int g, Tile &t)
+{
+    int b = bx.tile_box[g];
+    const int *tg = bx.tile + 8 * b;
+    int tx = tg[0], ty = tg[1], tz = tg[2], gx = tg[3], gy = tg[4], tc = tg[6];
+    t.b = b;
+    t.mode = tg[7];
+    t.nc = bx.nc[b];
+    t.L = bx.L[b];
+    t.invL = bx.invL[b];
+    int lin = g - bx.tile_off[b];
+    int Tx = lin % gx, Ty = (lin / gx) % gy, Tz = lin / (gx * gy);
+    t.ox = Tx * tx;
+    t.oy = Ty * ty;
+    t.oz = Tz * tz;
+    if (t.mode == kTileA) {
+        t.hx = min(tx, t.nc - t.ox) + 2;
+        t.hy = min(ty, t.nc - t.oy) + 2;
+        t.hz = min(tz, t.nc - t.oz) + 2;
+    } else {
+        t.hx = t.hy = t.hz = t.nc;
+    }
+    t.nh = t.hx * t.hy * t.hz;
+    int first = bx.cell_off[b] + lin * tc;
+    t.s0 = bd.cell_start[first];
+    t.s1 = bd.cell_start[first + tc];
+}
+
+// Exclusive scan over the 1024 threads of the block (one value each).
+__device__ __forceinline__ int block_scan(int v, HaloLds &H)
+{
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int incl = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        int u = __shfl_up(incl, off);
+        if (lane >= off) incl += u;
+    }
+    if (lane == 63) H.wsum[w] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int k = 0; k < 16; ++k) {
+            int x = H.wsum[k];
+            H.wsum[k] = run;
+            run += x;
+        }
+        H.total = run;
+    }
+    __syncthreads();
+    return H.wsum[w] + incl - v;
+}
+
+// Halo table of a tile (all threads).
+__device__ __forceinline__ void halo_table(const Tile &t, const Boxes &bx, const Build &bd,
+                                           HaloLds &H)
+{
+    int h = threadIdx.x;
+    int cnt = 0;
+    if (h < t.nh) {
+        int ix = h % t.hx, iy = (h / t.hx) % t.hy, iz = h / (t.hx * t.hy);
+        int cx, cy, cz, code;
+        if (t.mode == kTileA) {
+            int ux = t.ox + ix - 1, uy = t.oy + iy - 1, uz = t.oz + iz - 1;
+            int sx = ux < 0 ? -1 : (ux >= t.nc ? 1 : 0);
+            int sy = uy < 0 ? -1 : (uy >= t.nc ? 1 : 0);
+            int sz = uz < 0 ? -1 : (uz >= t.nc ? 1 : 0);
+            cx = ux - sx * t.nc;
+            cy = uy - sy * t.nc;
+            cz = uz - sz * t.nc;
+            code = (sx + 1) | ((sy + 1) << 2) | ((sz + 1) << 4);
+        } else {
+            cx = ix;
+            cy = iy;
+            cz = iz;
+            code = 1 | (1 << 2) | (1 << 4);
+        }
+        int c = cell_id(bx, t.b, cx, cy, cz);
+        int s = bd.cell_start[c];
+        cnt = bd.cell_start[c + 1] - s;
+        H.start[h] = s;
+        H.shift[h] = code;
+    }
+    int off = block_scan(cnt, H);
+    if (h < t.nh) H.off[h] = off;
+    if (h == 0) H.off[t.nh] = H.total;
+    __syncthreads();
+}
+
+__device__ __forceinline__ double shift_of(int code, int axis, double L)
+{
+    return (double)(((code >> (2 * axis)) & 3) - 1) * L;
+}
+
+// Stage the halo records: x, y, z (+ F') at 32 bytes per record.  With
+// `shifted`, coordinates are moved to the periodic image next to the tile.
+template <bool WITH_FP>
+__device__ __forceinline__ void stage(const Tile &t, const State &st, const HaloLds &H,
+                                      double *rec, int hmax, bool shifted, unsigned *flags)
+{
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int h = w; h < t.nh; h += kT / 64) {
+        int o = H.off[h], n = H.off[h + 1] - o, s = H.start[h], code = H.shift[h];
+        double sx = shifted ? shift_of(code, 0, t.L) : 0.0;
+        double sy = shifted ? shift_of(code, 1, t.L) : 0.0;
+        double sz = shifted ? shift_of(code, 2, t.L) : 0.0;
+        for (int l = lane; l < n; l += 64) {
+            int k = o + l;
+            if (k >= hmax) break;
+            int j = s + l;
+            double *r = rec + 4 * (size_t)k;
+            r[0] = st.x[j] + sx;
+            r[1] = st.y[j] + sy;
+            r[2] = st.z[j] + sz;
+            if constexpr (WITH_FP) r[3] = st.Fp[j];
+        }
+    }
+    if (threadIdx.x == 0 && H.total > hmax) atomicOr(flags, (unsigned)MD_FLAG_TILE_OVERFLOW);
+    __syncthreads();
+}
+
+// Halo cell of a local cell coordinate (tile-relative, -1..extent).
+__device__ __forceinline__ int halo_index(const Tile &t, int ix, int iy, int iz)
+{
+    return ((iz + 1) * t.hy + (iy + 1)) * t.hx + (ix + 1);
+}
+
+// ---------------------------------------------------------------- list build
+
+__global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, State st, Boxes bx,
+                                                   Build bd, NList nl, int hmax, unsigned *flags)
+{
+#pragma clang fp contract(off)
+    if (skip(gate)) return;
+    extern __shared__ double rec[];
+    __shared__ HaloLds H;
+    Tile t;
+    tile_setup(bx, bd, xcd_tile(blockIdx.x, gridDim.x), t);
+    halo_table(t, bx, bd, H);
+    stage<false>(t, st, H, rec, hmax, false, flags);
+    const double L = t.L, invL = t.invL, rl2 = bx.rl2[t.b];
+    const int mn = nl.mn, nc = t.nc;
+    const double ncL = nc * invL;
+    unsigned bad = 0;
+    for (int i = t.s0 + threadIdx.x; i < t.s1; i += kT) {
+        double xi = st.x[i], yi = st.y[i], zi = st.z[i];
+        int cx = cell_coord(xi, ncL, nc), cy = cell_coord(yi, ncL, nc), cz = cell_coord(zi, ncL, nc);
+        int *col = nl.idx + i;
+        int n = 0, total = 0;
+        if (t.mode == kTileA) {
+            int lx = cx - t.ox, ly = cy - t.oy, lz = cz - t.oz;
+            int hs = halo_index(t, lx, ly, lz);
+            int kself = H.off[hs] + (i - H.start[hs]);
+            for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx_ = -1; dx_ <= 1; ++dx_) {
+                        int h = halo_index(t, lx + dx_, ly + dy, lz + dz);
+                        int code = H.shift[h];
+                        double sx = shift_of(code, 0, L), sy = shift_of(code, 1, L),
+                               sz = shift_of(code, 2, L);
+                        int k0 = H.off[h], k1 = min(H.off[h + 1], hmax);
+                        for (int k = k0; k < k1; ++k) {
+                            const double *r = rec + 4 * k;
+                            double dx = (r[0] - xi) + sx;
+                            double dy2 = (r[1] - yi) + sy;
+                            double dz2 = (r[2] - zi) + sz;
+                            double r2 = (dx * dx + dy2 * dy2) + dz2 * dz2;
+                            if (r2 < rl2 && k != kself) {
+                                if (n < mn) col[(size_t)(n++) * N] = k;
+                                ++total;
+                            }
+                        }
+                    }
+        } else {
+            int kself = H.off[(cz * nc + cy) * nc + cx] + (i - H.start[(cz * nc + cy) * nc + cx]);
+            int ux[3], uy[3], uz[3];
+            int kx = stencil_1d(cx, nc, ux), ky = stencil_1d(cy, nc, uy), kz = stencil_1d(cz, nc, uz);
+            for (int a = 0; a < kz; ++a)
+                for (int bb = 0; bb < ky; ++bb)
+                    for (int c = 0; c < kx; ++c) {
+                        int h = (uz[a] * nc + uy[bb]) * nc + ux[c];
+                        int k0 = H.off[h], k1 = min(H.off[h + 1], hmax);
+                        for (int k = k0; k < k1; ++k) {
+                            if (k == kself) continue;
+                            const double *r = rec + 4 * k;
+                            double dx = r[0] - xi, dy2 = r[1] - yi, dz2 = r[2] - zi;
+                            dx = dx - rint(dx * invL) * L;
+                            dy2 = dy2 - rint(dy2 * invL) * L;
+                            dz2 = dz2 - rint(dz2 * invL) * L;
+                            double r2 = (dx * dx + dy2 * dy2) + dz2 * dz2;
+                            if (r2 < rl2) {
+                                if (n < mn) col[(size_t)(n++) * N] = k;
+                                ++total;
+                            }
+                        }
+                    }
+        }
+        nl.count[i] = n;
+        nl.total[i] = total;
+        if (total > mn) bad |= MD_FLAG_NLIST_OVERFLOW;
+    }
+    raise_flags(flags, bad);
+}
+
+// ---------------------------------------------------------------- passes
+
+// Visit the row of slot i (LDS indices), next index prefetched.
+template <bool IMG, class Body>
+__device__ __forceinline__ void for_row(const int *__restrict__ col, int N, int n1,
+                                        const double *rec, double xi, double yi, double zi,
+                                        double L, double invL, Body &&body)
+{
+    if (n1 <= 0) return;
+    const int *p = col;
+    int k = *p;
+    for (int n = 0; n < n1; ++n) {
+        p += N;
+        int kn = (n + 1 < n1) ? *p : k;
+        const double2 *r = reinterpret_cast<const double2 *>(rec + 4 * k);
+        double2 a = r[0], b2 = r[1];
+        double dx = a.x - xi, dy = a.y - yi, dz = b2.x - zi;
+        if constexpr (IMG) {
+            dx = min_image(dx, L, invL);
+            dy = min_image(dy, L, invL);
+            dz = min_image(dz, L, invL);
+        }
+        body(dx, dy, dz, b2.y);
+        k = kn;
+    }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kT) void k_tile_density(int N, State st, Boxes bx, Build bd, NList nl,
+                                                     Pot pot, int hmax, unsigned *flags)
+{
+    extern __shared__ double rec[];
+    __shared__ HaloLds H;
+    Tile t;
+    tile_setup(bx, bd, xcd_tile(blockIdx.x, gridDim.x), t);
+    halo_table(t, bx, bd, H);
+    bool shifted = t.mode == kTileA;
+    stage<false>(t, st, H, rec, hmax, shifted, flags);
+    unsigned bad = 0;
+    for (int i = t.s0 + threadIdx.x; i < t.s1; i += kT) {
+        double xi = st.x[i], yi = st.y[i], zi = st.z[i];
+        int n1 = nl.count[i] & 0xffff;
+        double rho = 0.0;
+        auto body = [&](double dx, double dy, double dz, double) {
+            double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            if (r2 < pot.rc2) rho += dens<KIND>(pot, r2 * rsqrt_nr(r2), bad);
+        };
+        if (shifted)
+            for_row<false>(nl.idx + i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
+        else
+            for_row<true>(nl.idx + i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
+        double F, Fp;
+        embed<KIND>(pot, rho, F, Fp, bad);
+        st.rho[i] = rho;
+        st.Femb[i] = F;
+        st.Fp[i] = Fp;
+    }
+    raise_flags(flags, bad);
+}
+
+template <int KIND, bool ENERGY, bool KICK>
+__global__ __launch_bounds__(kT) void k_tile_force(int N, State st, Boxes bx, Build bd, NList nl,
+                                                   Pot pot, int hmax, double kick, unsigned *flags)
+{
+    extern __shared__ double rec[];
+    __shared__ HaloLds H;
+    Tile t;
+    tile_setup(bx, bd, xcd_tile(blockIdx.x, gridDim.x), t);
+    halo_table(t, bx, bd, H);
+    bool shifted = t.mode == kTileA;
+    stage<true>(t, st, H, rec, hmax, shifted, flags);
+    unsigned bad = 0;
+    for (int i = t.s0 + threadIdx.x; i < t.s1; i += kT) {
+        double xi = st.x[i], yi = st.y[i], zi = st.z[i];
+        double fpi = st.Fp[i];
+        int n1 = nl.count[i] & 0xffff;
+        double ax = 0.0, ay = 0.0, az = 0.0, ep = 0.0;
+        auto body = [&](double dx, double dy, double dz, double fpj) {
+            double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            if (r2 < pot.rc2) {
+                double inv_r = rsqrt_nr(r2);
+                double dfr, v, dv;
+                pair_terms<KIND>(pot, r2 * inv_r, dfr, v, dv, bad);
+                // f_i += [(F'_i + F'_j) rho'(r) + V'(r)] (x_j - x_i) / r
+                double coef = fma(fpi + fpj, dfr, dv) * inv_r;
+                ax = fma(coef, dx, ax);
+                ay = fma(coef, dy, ay);
+                az = fma(coef, dz, az);
+                if constexpr (ENERGY) ep += v;
+            }
+        };
+        if (shifted)
+            for_row<false>(nl.idx + i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
+        else
+            for_row<true>(nl.idx + i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
+        st.fx[i] = ax;
+        st.fy[i] = ay;
+        st.fz[i] = az;
+        if constexpr (ENERGY) st.eat[i] = fma(0.5, ep, st.Femb[i]);
+        if constexpr (KICK) {
+            st.vx[i] = fma(kick, ax, st.vx[i]);
+            st.vy[i] = fma(kick, ay, st.vy[i]);
+            st.vz[i] = fma(kick, az, st.vz[i]);
+        }
+    }
+    raise_flags(flags, bad);
+}
+
+// Rows in original indices: LDS index -> halo cell (binary search) -> slot.
+__global__ __launch_bounds__(kT) void k_tile_get_neighbors(int N, State st, Boxes bx, Build bd,
+                                                           NList nl, int32_t *counts, int32_t *ids,
+                                                           int cols)
+{
+    __shared__ HaloLds H;
+    Tile t;
+    tile_setup(bx, bd, blockIdx.x, t);
+    halo_table(t, bx, bd, H);
+    for (int i = t.s0 + threadIdx.x; i < t.s1; i += kT) {
+        int o = st.id[i];
+        counts[o] = nl.total[i];
+        int m = min(min(nl.count[i] & 0xffff, nl.mn), cols);
+        for (int n = 0; n < m; ++n) {
+            int k = nl.idx[(size_t)n * N + i];
+            int lo = 0, hi = t.nh - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (H.off[mid] <= k) lo = mid;
+                else hi = mid - 1;
+            }
+            int j = H.start[lo] + (k - H.off[lo]);
+            ids[(size_t)o * cols + n] = st.id[j];
+        }
+    }
+}
+
+template <int KIND>
+void force_launch(Ctx &c, bool energy, bool kick, double k, hipStream_t s)
+{
+    int N = (int)c.N, G = c.ntiles;
+    size_t lds = c.tile_lds;
+    if (energy && kick)
+        k_tile_force<KIND, true, true><<<G, kT, lds, s>>>(N, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, k, c.dev.flags);
+    else if (energy)
+        k_tile_force<KIND, true, false><<<G, kT, lds, s>>>(N, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, k, c.dev.flags);
+    else if (kick)
+        k_tile_force<KIND, false, true><<<G, kT, lds, s>>>(N, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, k, c.dev.flags);
+    else
+        k_tile_force<KIND, false, false><<<G, kT, lds, s>>>(N, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, k, c.dev.flags);
+}
+
+template <class F>
+void allow(F *f, size_t lds)
+{
+    (void)hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+}  // namespace
+
+static constexpr double kKappaT = 1.602176634e-19 / 1.66053906660e-27 * 1e-10;
+
+void tiled_prepare(Ctx &c)
+{
+    size_t lds = c.tile_lds;
+    allow(k_tile_nlist, lds);
+    allow(k_tile_density<MD_POT_FS>, lds);
+    allow(k_tile_density<MD_POT_SMTB>, lds);
+    allow(k_tile_density<MD_POT_SPLINE>, lds);
+    allow(k_tile_force<MD_POT_FS, true, true>, lds);
+    allow(k_tile_force<MD_POT_FS, true, false>, lds);
+    allow(k_tile_force<MD_POT_FS, false, true>, lds);
+    allow(k_tile_force<MD_POT_FS, false, false>, lds);
+    allow(k_tile_force<MD_POT_SMTB, true, true>, lds);
+    allow(k_tile_force<MD_POT_SMTB, true, false>, lds);
+    allow(k_tile_force<MD_POT_SMTB, false, true>, lds);
+    allow(k_tile_force<MD_POT_SMTB, false, false>, lds);
+    allow(k_tile_force<MD_POT_SPLINE, true, true>, lds);
+    allow(k_tile_force<MD_POT_SPLINE, true, false>, lds);
+    allow(k_tile_force<MD_POT_SPLINE, false, true>, lds);
+    allow(k_tile_force<MD_POT_SPLINE, false, false>, lds);
+}
+
+void launch_tile_nlist(Ctx &c, const unsigned *gate, hipStream_t s)
+{
+    k_tile_nlist<<<c.ntiles, kT, c.tile_lds, s>>>(gate, (int)c.N, c.st, c.bx, c.bd, c.nl, c.hmax,
+                                                  c.dev.flags);
+}
+
+void launch_tile_density(Ctx &c, hipStream_t s)
+{
+    int N = (int)c.N;
+    switch (c.pot.kind) {
+    case MD_POT_FS: k_tile_density<MD_POT_FS><<<c.ntiles, kT, c.tile_lds, s>>>(N, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
+    case MD_POT_SMTB: k_tile_density<MD_POT_SMTB><<<c.ntiles, kT, c.tile_lds, s>>>(N, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
+    default: k_tile_density<MD_POT_SPLINE><<<c.ntiles, kT, c.tile_lds, s>>>(N, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
+    }
+}
+
+void launch_tile_force(Ctx &c, bool energy, bool kick, hipStream_t s)
+{
+    double k = 0.5 * c.dt * kKappaT / c.mass;
+    switch (c.pot.kind) {
+    case MD_POT_FS: force_launch<MD_POT_FS>(c, energy, kick, k, s); break;
+    case MD_POT_SMTB: force_launch<MD_POT_SMTB>(c, energy, kick, k, s); break;
+    default: force_launch<MD_POT_SPLINE>(c, energy, kick, k, s); break;
+    }
+}
+
+void launch_tile_get_neighbors(Ctx &c, int32_t *counts, int32_t *ids, int32_t cols, hipStream_t s)
+{
+    k_tile_get_neighbors<<<c.ntiles, kT, 0, s>>>((int)c.N, c.st, c.bx, c.bd, c.nl, counts, ids, cols);
+}
+
+}  // namespace mdk

@@ -22,8 +22,10 @@ def rel(a, b):
     return float(np.abs(a - b).max() / (scale if scale > 0 else 1.0))
 
 
-def gpu_eval(wl, pot=None, **kw):
+def gpu_eval(wl, pot=None, tiled=None, **kw):
     S = md.System.from_workload(wl, pot, **kw)
+    if tiled is not None:
+        S.set_option(md.MD_OPT_TILED, tiled)
     S.set_state(wl.pos, wl.vel)
     S.build_neighbors()
     rho = S.density()
@@ -72,6 +74,8 @@ CASES = {
     "smtb1372": lambda: W.fcc4m(ncell=7),          # ragged: not a multiple of the workgroup
     "spline1024": lambda: W.bcc128k(ncell=8),
     "spline2662": lambda: W.bcc128k(ncell=11),
+    "smtb5324": lambda: W.fcc4m(ncell=11),         # 6 cells per axis: edge tiles, halo mode A
+    "spline4394": lambda: W.bcc128k(ncell=13),     # 6 cells per axis, halo mode A
 }
 
 
@@ -81,10 +85,30 @@ def test_single_box_parity(name):
     compare(gpu_eval(wl), oracle_eval(wl))
 
 
+@pytest.mark.parametrize("name", ["smtb1372", "spline2662", "fs256", "smtb5324"])
+def test_single_box_parity_per_atom_kernels(name):
+    """The per-atom kernels (no LDS tiles) against the oracle."""
+    wl = CASES[name]()
+    compare(gpu_eval(wl, tiled=0), oracle_eval(wl))
+
+
+def test_tiled_and_per_atom_paths_agree():
+    wl = W.fcc4m(ncell=12)          # 6,912 atoms: several tiles per axis, halo mode A
+    a, b = gpu_eval(wl, tiled=1), gpu_eval(wl, tiled=0)
+    for k in ("rho", "f", "e_atom"):
+        assert rel(a[k], b[k]) <= 1e-13
+    assert np.array_equal(a["counts"], b["counts"])
+    for i in range(0, wl.n_atoms, 97):
+        assert sorted(a["ids"][i, :a["counts"][i]]) == sorted(b["ids"][i, :b["counts"][i]])
+    compare(a, oracle_eval(wl))
+
+
 def test_multibox_merged_parity():
     """Boxes of different sizes in one context (the merged-box scheme)."""
     wl = W.batch2048(n_boxes=24)
-    compare(gpu_eval(wl), oracle_eval(wl))
+    o = oracle_eval(wl)
+    compare(gpu_eval(wl), o)
+    compare(gpu_eval(wl, tiled=0), o)
     wa = W.adjoint64(n_boxes=5)
     tp = wa.extra["target_pot"]
     compare(gpu_eval(wa, tp), oracle_eval(wa, tp))
