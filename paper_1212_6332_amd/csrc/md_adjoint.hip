@@ -20,6 +20,7 @@
 
 #include <cmath>
 
+#include "md_device.h"
 #include "md_internal.h"
 
 namespace mdk {
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_s(int N, State st, Boxes bx, NLi
     for (int n = 0; n < nl.mn; ++n) {
         if (n == np) n = n1;  // skip to the boundary-crossing part of the row
         if (n >= nl.mn) break;
-        int j = nl.idx[(size_t)n * N + i];
+        int j = nl.idx[dev::nl_off(n, i, N)];
         double dx = min_image(st.x[j] - xi, L, invL);
         double dy = min_image(st.y[j] - yi, L, invL);
         double dz = min_image(st.z[j] - zi, L, invL);
@@ -146,7 +147,7 @@ __global__ __launch_bounds__(W) void k_adj_theta(int N, int K, State st, Boxes b
         for (int n = 0; n < nl.mn; ++n) {
             if (n == np) n = n1;  // skip to the boundary-crossing part of the row
             if (n >= nl.mn) break;
-            int j = nl.idx[(size_t)n * N + i];
+            int j = nl.idx[dev::nl_off(n, i, N)];
             double dx = min_image(st.x[j] - xi, L, invL);
             double dy = min_image(st.y[j] - yi, L, invL);
             double dz = min_image(st.z[j] - zi, L, invL);

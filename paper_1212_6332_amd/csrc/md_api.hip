@@ -165,7 +165,8 @@ int upload_potential(Ctx &c, const md_potential *p, hipStream_t s, bool first)
 
 int alloc_list(Ctx &c, int mn)
 {
-    if (mn > 65535) return MD_ERR_ARG;
+    mn = (mn + 3) / 4 * 4;  // rows are stored in groups of four
+    if (mn > 65532) return MD_ERR_ARG;
     c.nl.mn = mn;
     ALLOC(c.nl.idx, (size_t)mn * c.N);
     HIP_TRY(hipMemset(c.nl.idx, 0, sizeof(int) * (size_t)mn * c.N));

@@ -198,6 +198,15 @@ __device__ __forceinline__ int cell_id(const Boxes &bx, int b, int cx, int cy, i
     return bx.cell_off[b] + ((Tz * gy + Ty) * gx + Tx) * tc + (lz * ty + ly) * tx + lx;
 }
 
+// Neighbour-list layout: rows come in groups of four per slot, group-major
+// and slot-fastest, so that one 16-byte load returns four neighbours of an
+// atom and 64 consecutive slots read 1 KiB contiguously.  The capacity is a
+// multiple of four.
+__device__ __forceinline__ size_t nl_off(int r, int i, int N)
+{
+    return (((size_t)(r >> 2) * N + i) << 2) + (r & 3);
+}
+
 // Build kernels run unconditionally (gate == nullptr) or only when the device
 // rebuild request is set (inside replayed steps).
 __device__ __forceinline__ bool skip(const unsigned *gate) { return gate && gate[1] == 0u; }

@@ -82,22 +82,19 @@ __device__ __forceinline__ Row row_of(const NList &nl, int i)
 // already in flight.  Each pair costs one coalesced index load and two
 // 16-byte loads from one 32-byte record.
 template <bool IMG, bool FPJ, class Body>
-__device__ __forceinline__ void for_pairs(const int *__restrict__ col, int N, int n0, int n1,
+__device__ __forceinline__ void for_pairs(const int *__restrict__ idx, int i, int N, int n0, int n1,
                                           const double *__restrict__ pk, double xi, double yi,
                                           double zi, double L, double invL, Body &&body)
 {
     if (n0 >= n1) return;
-    const int *p = col + (size_t)n0 * N;
-    unsigned j = (unsigned)p[0];
-    unsigned jn = (n0 + 1 < n1) ? (unsigned)p[N] : j;
-    p += 2 * (size_t)N;
+    unsigned j = (unsigned)idx[nl_off(n0, i, N)];
+    unsigned jn = (n0 + 1 < n1) ? (unsigned)idx[nl_off(n0 + 1, i, N)] : j;
     double2 a = ldpk(pk, j, 0);
     double2 b;
     if constexpr (FPJ) b = ldpk(pk, j, 1);
     else b.x = ldpk_z(pk, j);
     for (int n = n0; n < n1; ++n) {
-        unsigned jnn = (n + 2 < n1) ? (unsigned)*p : jn;
-        p += N;
+        unsigned jnn = (n + 2 < n1) ? (unsigned)idx[nl_off(n + 2, i, N)] : jn;
         double2 an = ldpk(pk, jn, 0);
         double2 bn;
         if constexpr (FPJ) bn = ldpk(pk, jn, 1);
@@ -414,14 +411,13 @@ __global__ __launch_bounds__(kBlock) void k_nlist(const unsigned *gate, int N, S
     double ncL = nc * invL;
     int cx = cell_coord(xi, ncL, nc), cy = cell_coord(yi, ncL, nc), cz = cell_coord(zi, ncL, nc);
     const int mn = nl.mn;
-    int *col = nl.idx + i;
     int np = 0, ni = 0, total = 0;
     auto add = [&](int j, bool plain) {
         if (np + ni < mn) {
             if (plain)
-                col[(size_t)(np++) * N] = j;
+                nl.idx[nl_off(np++, i, N)] = j;
             else
-                col[(size_t)(mn - 1 - (ni++)) * N] = j;
+                nl.idx[nl_off(mn - 1 - (ni++), i, N)] = j;
         }
         ++total;
     };
@@ -517,15 +513,14 @@ __global__ __launch_bounds__(kBlock) void k_density(int N, State st, Boxes bx, N
     const double *__restrict__ pk = st.pk;
     double xi = st.x[i], yi = st.y[i], zi = st.z[i];
     Row rw = row_of(nl, i);
-    const int *col = nl.idx + i;
     unsigned bad = 0;
     double rho = 0.0;
     auto body = [&](double dx, double dy, double dz, double) {
         double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
         if (r2 < pot.rc2) rho += dens<KIND>(pot, r2 * rsqrt_nr(r2), bad);
     };
-    for_pairs<false, false>(col, N, 0, rw.np, pk, xi, yi, zi, L, invL, body);
-    for_pairs<true, false>(col, N, nl.mn - rw.ni, nl.mn, pk, xi, yi, zi, L, invL, body);
+    for_pairs<false, false>(nl.idx, i, N, 0, rw.np, pk, xi, yi, zi, L, invL, body);
+    for_pairs<true, false>(nl.idx, i, N, nl.mn - rw.ni, nl.mn, pk, xi, yi, zi, L, invL, body);
     double F, Fp;
     embed<KIND>(pot, rho, F, Fp, bad);
     st.rho[i] = rho;
@@ -563,7 +558,6 @@ __global__ __launch_bounds__(kBlock) void k_force(int N, State st, Boxes bx, NLi
     double xi = st.x[i], yi = st.y[i], zi = st.z[i];
     double fpi = st.Fp[i];
     Row rw = row_of(nl, i);
-    const int *col = nl.idx + i;
     unsigned bad = 0;
     double ax = 0.0, ay = 0.0, az = 0.0, ep = 0.0;
     auto body = [&](double dx, double dy, double dz, double fpj) {
@@ -580,8 +574,8 @@ __global__ __launch_bounds__(kBlock) void k_force(int N, State st, Boxes bx, NLi
             if constexpr (ENERGY) ep += v;
         }
     };
-    for_pairs<false, true>(col, N, 0, rw.np, pk, xi, yi, zi, L, invL, body);
-    for_pairs<true, true>(col, N, nl.mn - rw.ni, nl.mn, pk, xi, yi, zi, L, invL, body);
+    for_pairs<false, true>(nl.idx, i, N, 0, rw.np, pk, xi, yi, zi, L, invL, body);
+    for_pairs<true, true>(nl.idx, i, N, nl.mn - rw.ni, nl.mn, pk, xi, yi, zi, L, invL, body);
     st.fx[i] = ax;
     st.fy[i] = ay;
     st.fz[i] = az;
@@ -597,7 +591,7 @@ __global__ __launch_bounds__(kBlock) void k_force(int N, State st, Boxes bx, NLi
 // First half of a velocity-Verlet step: v += (dt/2) a; x += dt v; request a
 // list rebuild when an atom has moved more than half the skin since the last
 // build.
-template <bool MULTI>
+template <bool MULTI, bool PACK>
 __global__ __launch_bounds__(kBlock) void k_kick_drift(int N, State st, Boxes bx, double kick,
                                                        double dt, double thr2_1, unsigned *flags)
 {
@@ -616,15 +610,20 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(int N, State st, Boxes bx
         st.x[i] = x;
         st.y[i] = y;
         st.z[i] = z;
-        reinterpret_cast<double2 *>(st.pk)[2 * (size_t)i] = make_double2(x, y);
-        st.pk[4 * (size_t)i + 2] = z;
+        if constexpr (PACK) {
+            reinterpret_cast<double2 *>(st.pk)[2 * (size_t)i] = make_double2(x, y);
+            st.pk[4 * (size_t)i + 2] = z;
+        }
         double ddx = x - st.xr[i], ddy = y - st.yr[i], ddz = z - st.zr[i];
         double d2 = fma(ddz, ddz, fma(ddy, ddy, ddx * ddx));
         double thr2 = MULTI ? bx.thr2[bx.box_of[i]] : thr2_1;
         need = d2 > thr2;
         bad = !isfinite(d2);
     }
-    if (__any(need) && (threadIdx.x & 63) == 0) atomicOr(flags + 1, 1u);
+    // one request per wavefront, and none once the flag is already raised
+    if (__any(need) && (threadIdx.x & 63) == 0 &&
+        __atomic_load_n(flags + 1, __ATOMIC_RELAXED) == 0u)
+        atomicOr(flags + 1, 1u);
     if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flags, (unsigned)MD_FLAG_NONFINITE);
 }
 
@@ -699,9 +698,9 @@ __global__ void k_get_neighbors(int N, State st, NList nl, int32_t *counts, int3
     counts[o] = nl.total[i];
     int m = 0;
     for (int n = 0; n < rw.np && m < cols; ++n)
-        ids[(size_t)o * cols + (m++)] = st.id[nl.idx[(size_t)n * N + i]];
+        ids[(size_t)o * cols + (m++)] = st.id[nl.idx[nl_off(n, i, N)]];
     for (int n = nl.mn - rw.ni; n < nl.mn && m < cols; ++n)
-        ids[(size_t)o * cols + (m++)] = st.id[nl.idx[(size_t)n * N + i]];
+        ids[(size_t)o * cols + (m++)] = st.id[nl.idx[nl_off(n, i, N)]];
 }
 
 // ---------------------------------------------------------------- B-spline
@@ -839,10 +838,16 @@ void launch_kick_drift(Ctx &c, hipStream_t s)
 {
     double k = 0.5 * c.dt * kKappa / c.mass;
     double h = 0.5 * (c.box_rlist[0] - c.pot.rc);
-    if (c.B > 1)
-        k_kick_drift<true><<<grid_for(c.N), kBlock, 0, s>>>((int)c.N, c.st, c.bx, k, c.dt, 0.0, c.dev.flags);
+    // the packed neighbour records feed only the per-atom kernels
+    int g = grid_for(c.N), N = (int)c.N;
+    if (c.B > 1 && c.tiled)
+        k_kick_drift<true, false><<<g, kBlock, 0, s>>>(N, c.st, c.bx, k, c.dt, 0.0, c.dev.flags);
+    else if (c.B > 1)
+        k_kick_drift<true, true><<<g, kBlock, 0, s>>>(N, c.st, c.bx, k, c.dt, 0.0, c.dev.flags);
+    else if (c.tiled)
+        k_kick_drift<false, false><<<g, kBlock, 0, s>>>(N, c.st, c.bx, k, c.dt, h * h, c.dev.flags);
     else
-        k_kick_drift<false><<<grid_for(c.N), kBlock, 0, s>>>((int)c.N, c.st, c.bx, k, c.dt, h * h, c.dev.flags);
+        k_kick_drift<false, true><<<g, kBlock, 0, s>>>(N, c.st, c.bx, k, c.dt, h * h, c.dev.flags);
 }
 
 void launch_step_end(Ctx &c, hipStream_t s) { k_step_end<<<1, 1, 0, s>>>(c.dev.flags); }

@@ -42,6 +42,8 @@ struct Tile {
     int nh;           // halo cells
 };
 
+constexpr int kNoShift = 1 | (1 << 2) | (1 << 4);  // shift code of an unshifted cell
+
 // Shared halo table: per halo cell, LDS offset, first slot, image shift code.
 struct HaloLds {
     int off[kHaloCells + 1];
@@ -153,25 +155,46 @@ __device__ __forceinline__ double shift_of(int code, int axis, double L)
 
 // Stage the halo records: x, y, z (+ F') at 32 bytes per record.  With
 // `shifted`, coordinates are moved to the periodic image next to the tile.
+// Every thread copies records k = tid, tid + 1024, ...; its loads are all
+// issued before the first LDS store, so a tile pays about one memory round
+// trip for its whole halo.
 template <bool WITH_FP>
 __device__ __forceinline__ void stage(const Tile &t, const State &st, const HaloLds &H,
                                       double *rec, int hmax, bool shifted, unsigned *flags)
 {
-    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int h = w; h < t.nh; h += kT / 64) {
-        int o = H.off[h], n = H.off[h + 1] - o, s = H.start[h], code = H.shift[h];
-        double sx = shifted ? shift_of(code, 0, t.L) : 0.0;
-        double sy = shifted ? shift_of(code, 1, t.L) : 0.0;
-        double sz = shifted ? shift_of(code, 2, t.L) : 0.0;
-        for (int l = lane; l < n; l += 64) {
-            int k = o + l;
-            if (k >= hmax) break;
-            int j = s + l;
-            double *r = rec + 4 * (size_t)k;
-            r[0] = st.x[j] + sx;
-            r[1] = st.y[j] + sy;
-            r[2] = st.z[j] + sz;
-            if constexpr (WITH_FP) r[3] = st.Fp[j];
+    constexpr int R = 6;  // records per thread per round (hmax <= R * 1024 per round)
+    int total = min(H.total, hmax);
+    for (int base = 0; base < total; base += R * kT) {
+        double vx[R], vy[R], vz[R], vf[R];
+        int kk[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            int k = base + u * kT + (int)threadIdx.x;
+            kk[u] = k;
+            if (k < total) {
+                int lo = 0, hi = t.nh - 1;  // halo cell holding record k
+                while (lo < hi) {
+                    int mid = (lo + hi + 1) >> 1;
+                    if (H.off[mid] <= k) lo = mid;
+                    else hi = mid - 1;
+                }
+                int j = H.start[lo] + (k - H.off[lo]);
+                int code = H.shift[lo];
+                vx[u] = st.x[j] + (shifted ? shift_of(code, 0, t.L) : 0.0);
+                vy[u] = st.y[j] + (shifted ? shift_of(code, 1, t.L) : 0.0);
+                vz[u] = st.z[j] + (shifted ? shift_of(code, 2, t.L) : 0.0);
+                if constexpr (WITH_FP) vf[u] = st.Fp[j];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            if (kk[u] < total) {
+                double *r = rec + 4 * (size_t)kk[u];
+                r[0] = vx[u];
+                r[1] = vy[u];
+                r[2] = vz[u];
+                if constexpr (WITH_FP) r[3] = vf[u];
+            }
         }
     }
     if (threadIdx.x == 0 && H.total > hmax) atomicOr(flags, (unsigned)MD_FLAG_TILE_OVERFLOW);
@@ -204,29 +227,53 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
     for (int i = t.s0 + threadIdx.x; i < t.s1; i += kT) {
         double xi = st.x[i], yi = st.y[i], zi = st.z[i];
         int cx = cell_coord(xi, ncL, nc), cy = cell_coord(yi, ncL, nc), cz = cell_coord(zi, ncL, nc);
-        int *col = nl.idx + i;
         int n = 0, total = 0;
         if (t.mode == kTileA) {
             int lx = cx - t.ox, ly = cy - t.oy, lz = cz - t.oz;
             int hs = halo_index(t, lx, ly, lz);
             int kself = H.off[hs] + (i - H.start[hs]);
+            // squared distance from the atom to the lower and upper faces of
+            // its cell along each axis; a stencil cell whose box is farther
+            // than the list radius cannot hold a neighbour (tested with a
+            // relative margin so that rounding never drops a pair)
+            double w = L / nc;
+            double gx0 = xi - cx * w, gy0 = yi - cy * w, gz0 = zi - cz * w;
+            double ex[3] = {gx0 * gx0, 0.0, (w - gx0) * (w - gx0)};
+            double ey[3] = {gy0 * gy0, 0.0, (w - gy0) * (w - gy0)};
+            double ez[3] = {gz0 * gz0, 0.0, (w - gz0) * (w - gz0)};
+            double reach = rl2 * (1.0 + 1e-6);
             for (int dz = -1; dz <= 1; ++dz)
                 for (int dy = -1; dy <= 1; ++dy)
                     for (int dx_ = -1; dx_ <= 1; ++dx_) {
+                        if (ex[dx_ + 1] + ey[dy + 1] + ez[dz + 1] > reach) continue;
                         int h = halo_index(t, lx + dx_, ly + dy, lz + dz);
                         int code = H.shift[h];
-                        double sx = shift_of(code, 0, L), sy = shift_of(code, 1, L),
-                               sz = shift_of(code, 2, L);
                         int k0 = H.off[h], k1 = min(H.off[h + 1], hmax);
-                        for (int k = k0; k < k1; ++k) {
-                            const double *r = rec + 4 * k;
-                            double dx = (r[0] - xi) + sx;
-                            double dy2 = (r[1] - yi) + sy;
-                            double dz2 = (r[2] - zi) + sz;
-                            double r2 = (dx * dx + dy2 * dy2) + dz2 * dz2;
-                            if (r2 < rl2 && k != kself) {
-                                if (n < mn) col[(size_t)(n++) * N] = k;
-                                ++total;
+                        if (code == kNoShift) {
+                            for (int k = k0; k < k1; ++k) {
+                                const double *r = rec + 4 * k;
+                                double dx = r[0] - xi;
+                                double dy2 = r[1] - yi;
+                                double dz2 = r[2] - zi;
+                                double r2 = (dx * dx + dy2 * dy2) + dz2 * dz2;
+                                if (r2 < rl2 && k != kself) {
+                                    if (n < mn) nl.idx[nl_off(n++, i, N)] = k;
+                                    ++total;
+                                }
+                            }
+                        } else {
+                            double sx = shift_of(code, 0, L), sy = shift_of(code, 1, L),
+                                   sz = shift_of(code, 2, L);
+                            for (int k = k0; k < k1; ++k) {
+                                const double *r = rec + 4 * k;
+                                double dx = (r[0] - xi) + sx;
+                                double dy2 = (r[1] - yi) + sy;
+                                double dz2 = (r[2] - zi) + sz;
+                                double r2 = (dx * dx + dy2 * dy2) + dz2 * dz2;
+                                if (r2 < rl2) {
+                                    if (n < mn) nl.idx[nl_off(n++, i, N)] = k;
+                                    ++total;
+                                }
                             }
                         }
                     }
@@ -248,7 +295,7 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
                             dz2 = dz2 - rint(dz2 * invL) * L;
                             double r2 = (dx * dx + dy2 * dy2) + dz2 * dz2;
                             if (r2 < rl2) {
-                                if (n < mn) col[(size_t)(n++) * N] = k;
+                                if (n < mn) nl.idx[nl_off(n++, i, N)] = k;
                                 ++total;
                             }
                         }
@@ -263,28 +310,36 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
 
 // ---------------------------------------------------------------- passes
 
-// Visit the row of slot i (LDS indices), next index prefetched.
+// Visit the row of slot i (LDS indices) four entries at a time: one 16-byte
+// load per group, the next group prefetched while the current one runs.
 template <bool IMG, class Body>
-__device__ __forceinline__ void for_row(const int *__restrict__ col, int N, int n1,
+__device__ __forceinline__ void for_row(const int *__restrict__ idx, int i, int N, int n1,
                                         const double *rec, double xi, double yi, double zi,
                                         double L, double invL, Body &&body)
 {
     if (n1 <= 0) return;
-    const int *p = col;
-    int k = *p;
-    for (int n = 0; n < n1; ++n) {
-        p += N;
-        int kn = (n + 1 < n1) ? *p : k;
-        const double2 *r = reinterpret_cast<const double2 *>(rec + 4 * k);
-        double2 a = r[0], b2 = r[1];
-        double dx = a.x - xi, dy = a.y - yi, dz = b2.x - zi;
-        if constexpr (IMG) {
-            dx = min_image(dx, L, invL);
-            dy = min_image(dy, L, invL);
-            dz = min_image(dz, L, invL);
+    const int4 *g = reinterpret_cast<const int4 *>(idx) + i;
+    int ng = (n1 + 3) >> 2;
+    int4 cur = g[0];
+    for (int q = 0; q < ng; ++q) {
+        int4 nxt = (q + 1 < ng) ? g[(size_t)(q + 1) * N] : cur;
+        int kk[4] = {cur.x, cur.y, cur.z, cur.w};
+        int m = n1 - 4 * q;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (u < m) {
+                const double2 *r = reinterpret_cast<const double2 *>(rec + 4 * kk[u]);
+                double2 a = r[0], b2 = r[1];
+                double dx = a.x - xi, dy = a.y - yi, dz = b2.x - zi;
+                if constexpr (IMG) {
+                    dx = min_image(dx, L, invL);
+                    dy = min_image(dy, L, invL);
+                    dz = min_image(dz, L, invL);
+                }
+                body(dx, dy, dz, b2.y);
+            }
         }
-        body(dx, dy, dz, b2.y);
-        k = kn;
+        cur = nxt;
     }
 }
 
@@ -309,9 +364,9 @@ __global__ __launch_bounds__(kT) void k_tile_density(int N, State st, Boxes bx, 
             if (r2 < pot.rc2) rho += dens<KIND>(pot, r2 * rsqrt_nr(r2), bad);
         };
         if (shifted)
-            for_row<false>(nl.idx + i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
+            for_row<false>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
         else
-            for_row<true>(nl.idx + i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
+            for_row<true>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
         double F, Fp;
         embed<KIND>(pot, rho, F, Fp, bad);
         st.rho[i] = rho;
@@ -353,9 +408,9 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, State st, Boxes bx, Bu
             }
         };
         if (shifted)
-            for_row<false>(nl.idx + i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
+            for_row<false>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
         else
-            for_row<true>(nl.idx + i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
+            for_row<true>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
         st.fx[i] = ax;
         st.fy[i] = ay;
         st.fz[i] = az;
@@ -383,7 +438,7 @@ __global__ __launch_bounds__(kT) void k_tile_get_neighbors(int N, State st, Boxe
         counts[o] = nl.total[i];
         int m = min(min(nl.count[i] & 0xffff, nl.mn), cols);
         for (int n = 0; n < m; ++n) {
-            int k = nl.idx[(size_t)n * N + i];
+            int k = nl.idx[nl_off(n, i, N)];
             int lo = 0, hi = t.nh - 1;
             while (lo < hi) {
                 int mid = (lo + hi + 1) >> 1;
