@@ -211,8 +211,9 @@ def cpu_baseline(ncell=50, steps=10):
 
 
 def pmc_probe(reps):
-    """Short run for hardware-counter collection: force passes of the 4M-atom
-    workload, then one plain 2 GiB device copy used to scale the counters."""
+    """Short run for hardware-counter collection: force and density passes of
+    the 4M-atom workload, then one plain 2 GiB device copy used to scale the
+    counters."""
     import torch
     from paper_1212_6332_amd import md, workloads as W
 
@@ -224,6 +225,7 @@ def pmc_probe(reps):
     print(json.dumps({"mean_list_len": float(counts.double().mean()), "n_atoms": wl.n_atoms,
                       "force_bytes": force_pass_bytes(wl.n_atoms, float(counts.double().mean()))}))
     S.time_pass(md.MD_PASS_FORCE, reps)
+    S.time_pass(md.MD_PASS_DENSITY, reps)
     torch.cuda.synchronize()
     src = torch.ones(2 ** 28, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)

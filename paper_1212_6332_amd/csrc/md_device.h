@@ -32,35 +32,49 @@ __device__ __forceinline__ double rsqrt_nr(double a)
     return fma(y, e, y);
 }
 
-// exp(x) on the vector ALU alone: x = k ln2 + r with |r| <= ln2/2 (ln 2 split
-// in a 32-bit head and a tail so k ln2 is exact), exp(r) by its Taylor
-// polynomial of degree 13 (truncation < 5e-18 relative), then exp(x) =
-// 2^k exp(r).  Arguments are clamped to the range where exp is finite and
-// normal or gradually underflows.
+// exp(x) on the vector ALU alone, for |x| <= 700 (the host checks that the
+// arguments of a potential stay in that range): x = k ln2 + r with |r| <=
+// ln2/2 (ln 2 split in a 32-bit head and a tail so k ln2 is exact), exp(r) by
+// the polynomial kExpPoly, then exp(x) = 2^k exp(r).  k comes from adding
+// 1.5 * 2^52 to x / ln2: the fma rounds the exact sum to an integer, which
+// the low 32 bits of the result then hold in two's complement.
 __device__ __forceinline__ double exp_fast(double x, const Pot &p)
 {
-    x = fmin(fmax(x, -745.0), 709.0);
-    double k = rint(x * 1.4426950408889634074);
-    double r = fma(-k, p.l2hi, x);
-    r = fma(-k, p.l2lo, r);
-    double q = 1.0 / 6227020800.0;  // 1/13!
-    q = fma(q, r, 1.0 / 479001600.0);
-    q = fma(q, r, 1.0 / 39916800.0);
-    q = fma(q, r, 1.0 / 3628800.0);
-    q = fma(q, r, 1.0 / 362880.0);
-    q = fma(q, r, 1.0 / 40320.0);
-    q = fma(q, r, 1.0 / 5040.0);
-    q = fma(q, r, 1.0 / 720.0);
-    q = fma(q, r, 1.0 / 120.0);
-    q = fma(q, r, 1.0 / 24.0);
-    q = fma(q, r, 1.0 / 6.0);
-    q = fma(q, r, 0.5);
+    const double shifter = 6755399441055744.0;  // 1.5 * 2^52
+    double s = fma(x, 1.4426950408889634074, shifter);
+    int k = __double2loint(s);
+    double kd = s - shifter;
+    double r = fma(-kd, p.l2hi, x);
+    r = fma(-kd, p.l2lo, r);
+    double q = fma(p.ec[11], r, p.ec[10]);
+#pragma unroll
+    for (int m = 9; m >= 2; --m) q = fma(q, r, p.ec[m]);
     q = fma(q, r, 1.0);
     q = fma(q, r, 1.0);
-    return ldexp(q, (int)k);
+    return ldexp(q, k);
 }
 
 // ---------------------------------------------------------------- potential
+
+// The vector ALU takes at most one scalar-register operand per instruction,
+// so fma(a, r, b) with a and b both uniform needs one of them copied into a
+// vector register.  Pinning the additive constants of the pair terms in
+// vector registers once, before a loop over pairs, keeps that copy out of
+// the loop.  (The empty asm only forces the value into a vector register.)
+__device__ __forceinline__ void pin_vector(double &v) { asm volatile("" : "+v"(v)); }
+
+__device__ __forceinline__ Pot pinned(const Pot &p)
+{
+    Pot q = p;
+    if (q.kind == MD_POT_SMTB) {
+        pin_vector(q.bv);
+        pin_vector(q.bf);
+        pin_vector(q.bvd);
+        pin_vector(q.bfd);
+        pin_vector(q.ec[10]);
+    }
+    return q;
+}
 
 __device__ __forceinline__ void table_eval(const Table &t, double x, double &s, double &ds,
                                            unsigned &bad)
@@ -116,6 +130,27 @@ __device__ __forceinline__ void pair_terms(const Pot &p, double r, double &dfr, 
         double s;
         table_eval(p.tab[1], r, s, dfr, bad);
         table_eval(p.tab[0], r, v, dv, bad);
+    }
+}
+
+// Force coefficient of one pair without the energy, up to a sign fixed per
+// kind: (F'_i + F'_j) rho'(r) + V'(r) = kSign * returned value.  For SMTB
+// both derivatives are negative single exponentials, so the kernel takes
+// exp(af r + bfd) and exp(av r + bvd) and negates the sum once per atom.
+template <int KIND>
+constexpr double kForceSign = KIND == MD_POT_SMTB ? -1.0 : 1.0;
+
+template <int KIND>
+__device__ __forceinline__ double pair_coef(const Pot &p, double r, double fpij, unsigned &bad)
+{
+    if constexpr (KIND == MD_POT_SMTB) {
+        double e1 = exp_fast(fma(p.af, r, p.bfd), p);
+        double e2 = exp_fast(fma(p.av, r, p.bvd), p);
+        return fma(fpij, e1, e2);
+    } else {
+        double dfr, v, dv;
+        pair_terms<KIND>(p, r, dfr, v, dv, bad);
+        return fma(fpij, dfr, dv);
     }
 }
 

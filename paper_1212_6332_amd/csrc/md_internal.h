@@ -24,6 +24,17 @@ struct Table {
     double lo, hi, inv_h;
 };
 
+// exp(r) ~ sum_k kExpPoly[k] r^k on |r| <= 0.3466 (just above ln(2)/2): the
+// degree-11 polynomial interpolating exp at the 12 Chebyshev nodes of that
+// interval, computed in extended precision; with its coefficients rounded to
+// double its relative error is below 3e-17.  The two leading coefficients
+// round to exactly 1.
+constexpr double kExpPoly[12] = {
+    1.0, 1.0, 0.50000000000000189, 0.16666666666666452, 0.041666666666488585,
+    0.008333333333392973, 0.0013888888952158077, 0.0001984126979465664,
+    2.480148565207557e-05, 2.7557294295755615e-06, 2.7632581262081151e-07,
+    2.5099509922947443e-08};
+
 // Potential as the kernels see it.  B-spline potentials are converted to
 // per-interval tables on the device and evaluated as kind MD_POT_SPLINE.
 struct Pot {
@@ -31,7 +42,9 @@ struct Pot {
     double rc, rc2;
     double c, d, c0, c1, c2, A;        // Finnis-Sinclair
     double av, bv, af, bf;             // SMTB: V = exp(av r + bv), rho = exp(af r + bf)
+    double bvd, bfd;                   // SMTB: -V' = exp(av r + bvd), -rho' = exp(af r + bfd)
     double l2hi, l2lo;                 // ln 2 = l2hi + l2lo, l2hi with 32 significant bits
+    double ec[12];                     // kExpPoly, passed as kernel arguments (scalar registers)
     Table tab[3];                      // V(r), rho(r), F(rho)
 };
 

@@ -45,7 +45,9 @@ struct Tile {
 constexpr int kNoShift = 1 | (1 << 2) | (1 << 4);  // shift code of an unshifted cell
 
 // Shared halo table: per halo cell, LDS offset, first slot, image shift code.
-struct HaloLds {
+// Its 256-byte alignment (and size) keeps the record array behind it aligned,
+// so each record's 16-byte halves are aligned for 128-bit LDS reads.
+struct alignas(256) HaloLds {
     int off[kHaloCells + 1];
     int start[kHaloCells];
     int shift[kHaloCells];   // (sx+1) | (sy+1) << 2 | (sz+1) << 4, s in {-1, 0, 1}
@@ -214,7 +216,7 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
 {
 #pragma clang fp contract(off)
     if (skip(gate)) return;
-    extern __shared__ double rec[];
+    extern __shared__ __attribute__((aligned(256))) double rec[];
     __shared__ HaloLds H;
     Tile t;
     tile_setup(bx, bd, xcd_tile(blockIdx.x, gridDim.x), t);
@@ -310,8 +312,10 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
 
 // ---------------------------------------------------------------- passes
 
-// Visit the row of slot i (LDS indices) four entries at a time: one 16-byte
-// load per group, the next group prefetched while the current one runs.
+// Visit the row of slot i (LDS indices) four entries at a time, one 16-byte
+// load per group.  While group q is evaluated, group q + 1 is already in
+// flight; the two registers alternate roles (the loop body is unrolled by
+// two) so that no register copy at the back edge waits for a load.
 template <bool IMG, class Body>
 __device__ __forceinline__ void for_row(const int *__restrict__ idx, int i, int N, int n1,
                                         const double *rec, double xi, double yi, double zi,
@@ -319,12 +323,9 @@ __device__ __forceinline__ void for_row(const int *__restrict__ idx, int i, int 
 {
     if (n1 <= 0) return;
     const int4 *g = reinterpret_cast<const int4 *>(idx) + i;
-    int ng = (n1 + 3) >> 2;
-    int4 cur = g[0];
-    for (int q = 0; q < ng; ++q) {
-        int4 nxt = (q + 1 < ng) ? g[(size_t)(q + 1) * N] : cur;
-        int kk[4] = {cur.x, cur.y, cur.z, cur.w};
-        int m = n1 - 4 * q;
+    const int ng = (n1 + 3) >> 2;
+    auto group = [&](const int4 &c, int m) {
+        int kk[4] = {c.x, c.y, c.z, c.w};
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             if (u < m) {
@@ -339,21 +340,33 @@ __device__ __forceinline__ void for_row(const int *__restrict__ idx, int i, int 
                 body(dx, dy, dz, b2.y);
             }
         }
-        cur = nxt;
+    };
+    // Every load is unconditional (past the end of the row it re-reads the
+    // row's last group, already in cache): with a fixed number of loads per
+    // iteration the wait before a group can leave the later load in flight.
+    auto load = [&](int q) { return g[(size_t)min(q, ng - 1) * N]; };
+    int4 a = load(0);
+    int4 b = load(1);
+    for (int q = 0; q < ng; q += 2) {
+        group(a, n1 - 4 * q);
+        a = load(q + 2);
+        group(b, n1 - 4 * (q + 1));
+        b = load(q + 3);
     }
 }
 
 template <int KIND>
 __global__ __launch_bounds__(kT) void k_tile_density(int N, State st, Boxes bx, Build bd, NList nl,
-                                                     Pot pot, int hmax, unsigned *flags)
+                                                     Pot pot_arg, int hmax, unsigned *flags)
 {
-    extern __shared__ double rec[];
+    extern __shared__ __attribute__((aligned(256))) double rec[];
     __shared__ HaloLds H;
     Tile t;
     tile_setup(bx, bd, xcd_tile(blockIdx.x, gridDim.x), t);
     halo_table(t, bx, bd, H);
     bool shifted = t.mode == kTileA;
     stage<false>(t, st, H, rec, hmax, shifted, flags);
+    const Pot pot = pinned(pot_arg);
     unsigned bad = 0;
     for (int i = t.s0 + threadIdx.x; i < t.s1; i += kT) {
         double xi = st.x[i], yi = st.y[i], zi = st.z[i];
@@ -378,15 +391,19 @@ __global__ __launch_bounds__(kT) void k_tile_density(int N, State st, Boxes bx, 
 
 template <int KIND, bool ENERGY, bool KICK>
 __global__ __launch_bounds__(kT) void k_tile_force(int N, State st, Boxes bx, Build bd, NList nl,
-                                                   Pot pot, int hmax, double kick, unsigned *flags)
+                                                   Pot pot_arg, int hmax, double kick,
+                                                   unsigned *flags)
 {
-    extern __shared__ double rec[];
+    extern __shared__ __attribute__((aligned(256))) double rec[];
     __shared__ HaloLds H;
     Tile t;
     tile_setup(bx, bd, xcd_tile(blockIdx.x, gridDim.x), t);
     halo_table(t, bx, bd, H);
     bool shifted = t.mode == kTileA;
     stage<true>(t, st, H, rec, hmax, shifted, flags);
+    const Pot pot = pinned(pot_arg);
+    // without the energy, SMTB accumulates the negated force (see pair_coef)
+    constexpr double sg = ENERGY ? 1.0 : kForceSign<KIND>;
     unsigned bad = 0;
     for (int i = t.s0 + threadIdx.x; i < t.s1; i += kT) {
         double xi = st.x[i], yi = st.y[i], zi = st.z[i];
@@ -397,20 +414,28 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, State st, Boxes bx, Bu
             double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
             if (r2 < pot.rc2) {
                 double inv_r = rsqrt_nr(r2);
-                double dfr, v, dv;
-                pair_terms<KIND>(pot, r2 * inv_r, dfr, v, dv, bad);
                 // f_i += [(F'_i + F'_j) rho'(r) + V'(r)] (x_j - x_i) / r
-                double coef = fma(fpi + fpj, dfr, dv) * inv_r;
+                double coef;
+                if constexpr (ENERGY) {
+                    double dfr, v, dv;
+                    pair_terms<KIND>(pot, r2 * inv_r, dfr, v, dv, bad);
+                    coef = fma(fpi + fpj, dfr, dv) * inv_r;
+                    ep += v;
+                } else {
+                    coef = pair_coef<KIND>(pot, r2 * inv_r, fpi + fpj, bad) * inv_r;
+                }
                 ax = fma(coef, dx, ax);
                 ay = fma(coef, dy, ay);
                 az = fma(coef, dz, az);
-                if constexpr (ENERGY) ep += v;
             }
         };
         if (shifted)
             for_row<false>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
         else
             for_row<true>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
+        ax *= sg;
+        ay *= sg;
+        az *= sg;
         st.fx[i] = ax;
         st.fy[i] = ay;
         st.fz[i] = az;
