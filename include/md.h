@@ -72,8 +72,8 @@ enum {
                            V(r) = 2A exp(-p (r/r0 - 1)),
                            rho(r) = xi^2 exp(-2q (r/r0 - 1)), F(rho) = -sqrt(rho)
                            (the SETB form of Section 4); A, xi, p, q, r0 > 0
-                           and the exponents of V, rho, V', rho' within
-                           [-700, 700] on [0, rc], else MD_ERR_ARG              */
+                           and V, rho, |V'|, |rho'| within 2^-1000 .. 2^1000
+                           on [0, rc], else MD_ERR_ARG                          */
     MD_POT_SPLINE = 3,  /* lookup tables (Section 3.3): for V(r), rho(r), F(rho)
                            each a uniform grid [lo, hi] of n intervals with cubic
                            coefficients (a, b, c, d): S = a + b t + c t^2 + d t^3,

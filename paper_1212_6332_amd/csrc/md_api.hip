@@ -101,27 +101,30 @@ int upload_potential(Ctx &c, const md_potential *p, hipStream_t s, bool first)
         double A = p->params[0], xi = p->params[1], pp = p->params[2], qq = p->params[3],
                r0 = p->params[4];
         if (!(A > 0.0 && xi > 0.0 && r0 > 0.0 && pp > 0.0 && qq > 0.0)) return MD_ERR_ARG;
-        // V = 2A exp(-p (r/r0 - 1)) = exp(av r + bv); rho = xi^2 exp(-2q (r/r0 - 1)) = exp(af r + bf)
-        q.av = -pp / r0;
-        q.bv = pp + std::log(2.0 * A);
-        q.af = -2.0 * qq / r0;
-        q.bf = 2.0 * qq + 2.0 * std::log(xi);
-        // derivatives as single exponentials: V' = av V = -exp(av r + bv + ln|av|)
-        q.bvd = q.bv + std::log(-q.av);
-        q.bfd = q.bf + std::log(-q.af);
-        // the device exponential assumes arguments within [-700, 700] for
-        // every r in [0, rc]; the arguments are linear in r
-        for (double b : {q.bv, q.bf, q.bvd, q.bfd})
-            for (double x : {b, (b == q.bv || b == q.bvd ? q.av : q.af) * q.rc + b})
-                if (!(std::fabs(x) <= 700.0)) return MD_ERR_ARG;
-        // ln 2 split for the exponential's argument reduction: a 32-bit head
-        // (exact products with the reduction multiple) and the remainder
-        long double ln2 = 0.693147180559945309417232121458176568L;
-        double hi = (double)std::ldexp(std::floor(std::ldexp(ln2, 32)), -32);
-        q.l2hi = hi;
-        q.l2lo = (double)(ln2 - (long double)hi);
-        static_assert(kExpPoly[0] == 1.0 && kExpPoly[1] == 1.0, "leading exp coefficients");
-        for (int m = 0; m < 12; ++m) q.ec[m] = kExpPoly[m];
+        // V = 2A exp(-p (r/r0 - 1)) = exp(av r + bv), rho = xi^2 exp(-2q (r/r0 - 1)) =
+        // exp(af r + bf); the derivatives as single exponentials, V' = av V =
+        // -exp(av r + bv + ln|av|); all four stored in base 2 (times log2 e)
+        const long double log2e = 1.442695040888963407359924681001892137L;
+        const long double ln2 = 0.693147180559945309417232121458176568L;
+        long double av = -(long double)pp / r0, bv = pp + std::log(2.0L * A);
+        long double af = -2.0L * qq / r0, bf = 2.0L * qq + 2.0L * std::log((long double)xi);
+        long double bvd = bv + std::log(-av), bfd = bf + std::log(-af);
+        q.avn = (double)av;
+        q.afn = (double)af;
+        q.av = (double)(av * log2e);
+        q.bv = (double)(bv * log2e);
+        q.af = (double)(af * log2e);
+        q.bf = (double)(bf * log2e);
+        q.bvd = (double)(bvd * log2e);
+        q.bfd = (double)(bfd * log2e);
+        // the device 2^t assumes |t| <= 1000 for every r in [0, rc]; t is linear in r
+        const double slope_offset[4][2] = {{q.av, q.bv}, {q.av, q.bvd}, {q.af, q.bf}, {q.af, q.bfd}};
+        for (const auto &so : slope_offset)
+            for (double t : {so[1], so[0] * q.rc + so[1]})
+                if (!(std::fabs(t) <= 1000.0)) return MD_ERR_ARG;
+        static_assert(kExpPoly[0] == 1.0, "leading exp coefficient");
+        long double w = 1.0L;
+        for (int m = 0; m < 12; ++m, w *= ln2) q.ec[m] = (double)(kExpPoly[m] * w);
     } else {
         q.kind = MD_POT_SPLINE;
         if (first) {

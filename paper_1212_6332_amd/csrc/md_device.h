@@ -20,37 +20,34 @@ __device__ __forceinline__ double min_image(double d, double L, double invL)
     return fma(-L, rint(d * invL), d);
 }
 
-// 1/sqrt(a), a > 0: hardware estimate refined by two Newton steps
-// y <- y + y (1/2 - a y^2 / 2).
+// 1/sqrt(a), a > 0: the hardware estimate y (relative error about 5e-8)
+// refined by one third-order step: with e = 1 - a y^2,
+// 1/sqrt(a) = y (1 - e)^(-1/2) = y (1 + e/2 + 3 e^2/8 + O(e^3)).
 __device__ __forceinline__ double rsqrt_nr(double a)
 {
     double y = __builtin_amdgcn_rsq(a);
-    double h = 0.5 * a;
-    double e = fma(-h * y, y, 0.5);
-    y = fma(y, e, y);
-    e = fma(-h * y, y, 0.5);
-    return fma(y, e, y);
+    double e = fma(-a * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 
-// exp(x) on the vector ALU alone, for |x| <= 700 (the host checks that the
-// arguments of a potential stay in that range): x = k ln2 + r with |r| <=
-// ln2/2 (ln 2 split in a 32-bit head and a tail so k ln2 is exact), exp(r) by
-// the polynomial kExpPoly, then exp(x) = 2^k exp(r).  k comes from adding
-// 1.5 * 2^52 to x / ln2: the fma rounds the exact sum to an integer, which
-// the low 32 bits of the result then hold in two's complement.
-__device__ __forceinline__ double exp_fast(double x, const Pot &p)
+// 2^t on the vector ALU alone, for |t| <= 1000 (the host checks that the
+// arguments of a potential stay in that range): t = k + f with k the nearest
+// integer and |f| <= 1/2, 2^f = exp(f ln2) by the polynomial kExpPoly in
+// f ln2 (its coefficients are stored premultiplied by powers of ln 2), then
+// 2^t = 2^k 2^f.  k comes from adding 1.5 * 2^52 to t: the sum rounds t to an
+// integer, which the low 32 bits of the result then hold in two's complement;
+// f = t - k is exact.  Exponentials exp(a r + b) of the pair terms are taken
+// as 2^(a' r + b') with a' = a log2(e), b' = b log2(e) folded on the host.
+__device__ __forceinline__ double exp2_fast(double t, const Pot &p)
 {
     const double shifter = 6755399441055744.0;  // 1.5 * 2^52
-    double s = fma(x, 1.4426950408889634074, shifter);
+    double s = t + shifter;
     int k = __double2loint(s);
-    double kd = s - shifter;
-    double r = fma(-kd, p.l2hi, x);
-    r = fma(-kd, p.l2lo, r);
-    double q = fma(p.ec[11], r, p.ec[10]);
+    double f = t - (s - shifter);
+    double q = fma(p.ec[11], f, p.ec[10]);
 #pragma unroll
-    for (int m = 9; m >= 2; --m) q = fma(q, r, p.ec[m]);
-    q = fma(q, r, 1.0);
-    q = fma(q, r, 1.0);
+    for (int m = 9; m >= 1; --m) q = fma(q, f, p.ec[m]);
+    q = fma(q, f, 1.0);
     return ldexp(q, k);
 }
 
@@ -98,7 +95,7 @@ __device__ __forceinline__ double dens(const Pot &p, double r, unsigned &bad)
         double u = r - p.d;
         return r < p.d ? u * u : 0.0;
     } else if constexpr (KIND == MD_POT_SMTB) {
-        return exp_fast(fma(p.af, r, p.bf), p);
+        return exp2_fast(fma(p.af, r, p.bf), p);
     } else {
         double s, ds;
         table_eval(p.tab[1], r, s, ds, bad);
@@ -121,11 +118,11 @@ __device__ __forceinline__ void pair_terms(const Pot &p, double r, double &dfr, 
         v = in ? w * w * poly : 0.0;
         dv = in ? w * fma(w, dpoly, 2.0 * poly) : 0.0;
     } else if constexpr (KIND == MD_POT_SMTB) {
-        double ef = exp_fast(fma(p.af, r, p.bf), p);
-        double ev = exp_fast(fma(p.av, r, p.bv), p);
-        dfr = p.af * ef;
+        double ef = exp2_fast(fma(p.af, r, p.bf), p);
+        double ev = exp2_fast(fma(p.av, r, p.bv), p);
+        dfr = p.afn * ef;
         v = ev;
-        dv = p.av * ev;
+        dv = p.avn * ev;
     } else {
         double s;
         table_eval(p.tab[1], r, s, dfr, bad);
@@ -144,8 +141,8 @@ template <int KIND>
 __device__ __forceinline__ double pair_coef(const Pot &p, double r, double fpij, unsigned &bad)
 {
     if constexpr (KIND == MD_POT_SMTB) {
-        double e1 = exp_fast(fma(p.af, r, p.bfd), p);
-        double e2 = exp_fast(fma(p.av, r, p.bvd), p);
+        double e1 = exp2_fast(fma(p.af, r, p.bfd), p);
+        double e2 = exp2_fast(fma(p.av, r, p.bvd), p);
         return fma(fpij, e1, e2);
     } else {
         double dfr, v, dv;

@@ -24,7 +24,8 @@ struct Table {
     double lo, hi, inv_h;
 };
 
-// exp(r) ~ sum_k kExpPoly[k] r^k on |r| <= 0.3466 (just above ln(2)/2): the
+// exp(r) ~ sum_k kExpPoly[k] r^k on |r| <= 0.3466 (just above ln(2)/2, so
+// 2^f = exp(f ln 2) for |f| <= 1/2): the
 // degree-11 polynomial interpolating exp at the 12 Chebyshev nodes of that
 // interval, computed in extended precision; with its coefficients rounded to
 // double its relative error is below 3e-17.  The two leading coefficients
@@ -41,10 +42,10 @@ struct Pot {
     int kind;
     double rc, rc2;
     double c, d, c0, c1, c2, A;        // Finnis-Sinclair
-    double av, bv, af, bf;             // SMTB: V = exp(av r + bv), rho = exp(af r + bf)
-    double bvd, bfd;                   // SMTB: -V' = exp(av r + bvd), -rho' = exp(af r + bfd)
-    double l2hi, l2lo;                 // ln 2 = l2hi + l2lo, l2hi with 32 significant bits
-    double ec[12];                     // kExpPoly, passed as kernel arguments (scalar registers)
+    // SMTB in base 2: V = 2^(av r + bv), rho = 2^(af r + bf), -V' = 2^(av r + bvd),
+    // -rho' = 2^(af r + bfd); avn, afn are the slopes of ln V and ln rho
+    double av, bv, af, bf, bvd, bfd, avn, afn;
+    double ec[12];                     // kExpPoly[m] ln(2)^m, kernel arguments (scalar registers)
     Table tab[3];                      // V(r), rho(r), F(rho)
 };
 

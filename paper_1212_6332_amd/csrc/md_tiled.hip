@@ -19,7 +19,9 @@
 //     no minimum image at all.
 //  B  (small boxes): one tile is the whole box, staged once without shifts;
 //     the list build and the passes take the minimum image per pair.
-// Rows hold LDS indices of the tile's halo.
+// Rows hold the byte offsets of halo records in the LDS record array
+// (record index times 32), so the passes address a record with no
+// arithmetic.
 #include <hip/hip_runtime.h>
 
 #include "md_device.h"
@@ -259,7 +261,7 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
                                 double dz2 = r[2] - zi;
                                 double r2 = (dx * dx + dy2 * dy2) + dz2 * dz2;
                                 if (r2 < rl2 && k != kself) {
-                                    if (n < mn) nl.idx[nl_off(n++, i, N)] = k;
+                                    if (n < mn) nl.idx[nl_off(n++, i, N)] = k << 5;
                                     ++total;
                                 }
                             }
@@ -273,7 +275,7 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
                                 double dz2 = (r[2] - zi) + sz;
                                 double r2 = (dx * dx + dy2 * dy2) + dz2 * dz2;
                                 if (r2 < rl2) {
-                                    if (n < mn) nl.idx[nl_off(n++, i, N)] = k;
+                                    if (n < mn) nl.idx[nl_off(n++, i, N)] = k << 5;
                                     ++total;
                                 }
                             }
@@ -297,7 +299,7 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
                             dz2 = dz2 - rint(dz2 * invL) * L;
                             double r2 = (dx * dx + dy2 * dy2) + dz2 * dz2;
                             if (r2 < rl2) {
-                                if (n < mn) nl.idx[nl_off(n++, i, N)] = k;
+                                if (n < mn) nl.idx[nl_off(n++, i, N)] = k << 5;
                                 ++total;
                             }
                         }
@@ -312,8 +314,8 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
 
 // ---------------------------------------------------------------- passes
 
-// Visit the row of slot i (LDS indices) four entries at a time, one 16-byte
-// load per group.  While group q is evaluated, group q + 1 is already in
+// Visit the row of slot i (record byte offsets) four entries at a time, one
+// 16-byte load per group.  While group q is evaluated, group q + 1 is already in
 // flight; the two registers alternate roles (the loop body is unrolled by
 // two) so that no register copy at the back edge waits for a load.
 template <bool IMG, class Body>
@@ -329,7 +331,8 @@ __device__ __forceinline__ void for_row(const int *__restrict__ idx, int i, int 
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             if (u < m) {
-                const double2 *r = reinterpret_cast<const double2 *>(rec + 4 * kk[u]);
+                const double2 *r = reinterpret_cast<const double2 *>(
+                    reinterpret_cast<const char *>(rec) + (unsigned)kk[u]);
                 double2 a = r[0], b2 = r[1];
                 double dx = a.x - xi, dy = a.y - yi, dz = b2.x - zi;
                 if constexpr (IMG) {
@@ -463,7 +466,7 @@ __global__ __launch_bounds__(kT) void k_tile_get_neighbors(int N, State st, Boxe
         counts[o] = nl.total[i];
         int m = min(min(nl.count[i] & 0xffff, nl.mn), cols);
         for (int n = 0; n < m; ++n) {
-            int k = nl.idx[nl_off(n, i, N)];
+            int k = nl.idx[nl_off(n, i, N)] >> 5;
             int lo = 0, hi = t.nh - 1;
             while (lo < hi) {
                 int mid = (lo + hi + 1) >> 1;
