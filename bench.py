@@ -23,17 +23,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
-FP64_VALU_PEAK = 256 * 64 * 2.4e9  # lane-instructions/s: 256 CUs x 64 lanes x 2.4 GHz
+HBM_PEAK_GBS = 8000.0                    # MI355X HBM3E
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # FP64 VALU lane-operations: 256 CUs x 64 lanes x 2.4 GHz
 METRIC = "atom-steps/s FP64 EAM step at 4M atoms; HBM GB/s fraction; batched box-steps/s"
 COUNTERS = os.path.join(ROOT, "profiles", "force_pass_fcc4m_counters.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_1212_6332_amd", "csrc", "md_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_1212_6332_amd", "csrc")
+# the sources the force kernel is compiled from
+KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("md_tiled.hip", "md_device.h", "md_internal.h")]
+FORCE_KERNEL = "k_tile_force<2, false, true>"
+
+# Algorithmic FP64 work, in lane-operations (one VALU operation on one lane):
+# every list entry costs the separation (3 differences), r^2 (1 multiply,
+# 2 fma) and the cutoff compare; every pair inside the cutoff costs 1/r and r
+# (estimate, one third-order correction, one multiply: 7) and, per
+# exponential 2^t, its argument (1), reduction (3), degree-11 polynomial (11)
+# and scaling (1); the force pass takes two exponentials and assembles
+# (F'_i + F'_j) rho' + V' and the three force components (6), the density
+# pass takes one exponential and one accumulation.
+OPS_ENTRY = 7
+OPS_FORCE_PAIR = 7 + 2 * 16 + 6
+OPS_DENSITY_PAIR = 7 + 16 + 1
 
 
 def force_pass_bytes(n_atoms, mean_list):
     """Algorithmic HBM bytes of one force pass with the fused half kick:
     per atom x,y,z (24) + F' (8) + count (4) + list (4 per entry) + force
-    out (24) + velocity in/out (48); neighbour gathers counted once."""
+    out (24) + velocity in/out (48); neighbour records counted once."""
     return n_atoms * (108.0 + 4.0 * mean_list)
 
 
@@ -42,9 +57,16 @@ def density_pass_bytes(n_atoms, mean_list):
     return n_atoms * (52.0 + 4.0 * mean_list)
 
 
+def kernel_source_sha256():
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
 def read_counters():
-    """Traffic of the force pass from the committed rocprofv3 counter summary,
-    or None if it is missing or was taken from a different kernel source."""
+    """HBM bytes per force-pass launch from the committed rocprofv3 counter
+    summary, or None if it is missing or was taken from other kernel sources."""
     if not os.path.exists(COUNTERS):
         return None
     kv = {}
@@ -52,13 +74,31 @@ def read_counters():
         if ":" in line and not line.lstrip().startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-    if kv.get("kernel_source_sha256") != sha:
+    if kv.get("kernel_source_sha256") != kernel_source_sha256():
         return None
     try:
         return float(kv["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def list_stats(S, rc):
+    """Entries of the neighbour list and pairs inside the cutoff, counted on
+    the device from the list the passes use (measurement only)."""
+    import torch
+    counts, ids = S.neighbors()
+    pos, _ = S.get_state()
+    L = float(S.box_len[0])
+    entries = int(counts.sum())
+    pairs = 0
+    for a in range(0, ids.shape[0], 1 << 19):
+        blk = ids[a:a + (1 << 19)].long()
+        ok = blk >= 0
+        d = pos[blk.clamp(min=0)] - pos[a:a + blk.shape[0], None, :]
+        d -= L * torch.round(d / L)
+        r2 = (d * d).sum(-1)
+        pairs += int(((r2 < rc * rc) & ok).sum())
+    return entries, pairs
 
 
 def timed_steps(S, steps, warmup):
@@ -88,27 +128,40 @@ def bench_main(steps, warmup, reps):
     S = md.System.from_workload(wl)
     S.set_state(wl.pos, wl.vel)
     S.forces(energy=False)
-    counts, _ = S.neighbors(1)
-    mean_list = float(counts.double().mean())
-    wall, gpu_s, rebuilds = timed_steps(S, steps, warmup)
+    entries, pairs = list_stats(S, wl.pot.rc)
     n = wl.n_atoms
+    mean_list = entries / n
+    wall, gpu_s, rebuilds = timed_steps(S, steps, warmup)
     ms = {name: S.time_pass(p, reps) for name, p in (
         ("force", md.MD_PASS_FORCE), ("density", md.MD_PASS_DENSITY),
         ("kick_drift", md.MD_PASS_KICK_DRIFT), ("build", md.MD_PASS_BUILD))}
+    f_ops = OPS_ENTRY * entries + OPS_FORCE_PAIR * pairs
+    d_ops = OPS_ENTRY * entries + OPS_DENSITY_PAIR * pairs
+    achieved = f_ops / (ms["force"] * 1e-3) / 1e12
     fbytes = force_pass_bytes(n, mean_list)
-    achieved = fbytes / (ms["force"] * 1e-3) / 1e9
+    traffic = read_counters()
     res = {
         "value": n * steps / wall,
         "ms_per_step": wall / steps * 1e3,
         "gpu_ms_per_step": gpu_s / steps * 1e3,
         "rebuilds": int(rebuilds),
         "mean_list_len": mean_list,
+        "pairs_per_atom": pairs / n,
         "pass_ms": ms,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": read_counters(),
-                     "kernel": "force pass (k_force, fused half kick)",
-                     "bytes_per_launch": fbytes, "ms_per_launch": ms["force"],
-                     "density_pass_gbs": density_pass_bytes(n, mean_list) / (ms["density"] * 1e-3) / 1e9},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                     "unit": "T FP64 lane-ops/s", "frac": achieved / VALU_PEAK_TOPS,
+                     "traffic": traffic,
+                     "kernel": f"{FORCE_KERNEL}: force pass with the fused half kick",
+                     "ops_per_launch": f_ops, "ms_per_launch": ms["force"],
+                     "hbm": {"algorithmic_bytes_per_launch": fbytes,
+                             "algorithmic_gbs": fbytes / (ms["force"] * 1e-3) / 1e9,
+                             "measured_gbs": (traffic / (ms["force"] * 1e-3) / 1e9
+                                              if traffic else None),
+                             "peak_gbs": HBM_PEAK_GBS},
+                     "density_pass": {"ops_per_launch": d_ops,
+                                      "achieved": d_ops / (ms["density"] * 1e-3) / 1e12,
+                                      "algorithmic_gbs": density_pass_bytes(n, mean_list)
+                                      / (ms["density"] * 1e-3) / 1e9}},
         "n_atoms": n,
     }
     S.close()
@@ -184,11 +237,11 @@ def bench_c2(steps=1000, warmup=20):
             "rebuilds": int(reb), "steps": steps}
 
 
-def cpu_baseline(ncell=50, steps=10):
+def cpu_baseline(ncell=50, steps=100):
     """The CPU oracle on a bounded sample: the same material (FCC SMTB, a =
     3.615, 300 K, sigma 0.05) in a 50^3-cell box (500,000 atoms, 1/8 of the
-    full system), 10 velocity-Verlet steps; list build and initial forces
-    timed separately and excluded."""
+    full system), 100 velocity-Verlet steps (about 10-20 s on the host's
+    cores); list build and initial forces timed separately and excluded."""
     import oracle as O
     from paper_1212_6332_amd import workloads as W
 
@@ -264,7 +317,8 @@ def main():
         "config": {"workload": "fcc4m: FCC 100^3 cells (4,000,000 atoms), second-moment "
                                "tight binding (Cu), rc 5.85 A, skin 0.3 A, 300 K, dt 1 fs",
                    "n_atoms": r["n_atoms"], "rebuilds_in_timed_steps": r["rebuilds"],
-                   "mean_list_len": r["mean_list_len"], "gpu_ms_per_step": r["gpu_ms_per_step"],
+                   "mean_list_len": r["mean_list_len"], "pairs_per_atom": r["pairs_per_atom"],
+                   "gpu_ms_per_step": r["gpu_ms_per_step"],
                    "pass_ms": r["pass_ms"]},
         "roofline": r["roofline"],
     }
