@@ -30,7 +30,7 @@ COUNTERS = os.path.join(ROOT, "profiles", "force_pass_fcc4m_counters.txt")
 CSRC = os.path.join(ROOT, "paper_1212_6332_amd", "csrc")
 # the sources the force kernel is compiled from
 KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("md_tiled.hip", "md_device.h", "md_internal.h")]
-FORCE_KERNEL = "k_tile_force<2, false, true>"
+FORCE_KERNEL = "k_tile_force<2, false, 1>"
 
 # Algorithmic FP64 work, in lane-operations (one VALU operation on one lane):
 # every list entry costs the separation (3 differences), r^2 (1 multiply,
@@ -133,8 +133,9 @@ def bench_main(steps, warmup, reps):
     mean_list = entries / n
     wall, gpu_s, rebuilds = timed_steps(S, steps, warmup)
     ms = {name: S.time_pass(p, reps) for name, p in (
-        ("force", md.MD_PASS_FORCE), ("density", md.MD_PASS_DENSITY),
-        ("kick_drift", md.MD_PASS_KICK_DRIFT), ("build", md.MD_PASS_BUILD))}
+        ("force", md.MD_PASS_FORCE), ("force_step", md.MD_PASS_FORCE_STEP),
+        ("density", md.MD_PASS_DENSITY), ("kick_drift", md.MD_PASS_KICK_DRIFT),
+        ("build", md.MD_PASS_BUILD))}
     f_ops = OPS_ENTRY * entries + OPS_FORCE_PAIR * pairs
     d_ops = OPS_ENTRY * entries + OPS_DENSITY_PAIR * pairs
     achieved = f_ops / (ms["force"] * 1e-3) / 1e12

@@ -192,10 +192,19 @@ int md_adjoint(md_ctx *ctx, const double *g, const double *e, double *gtheta, vo
 /* Benchmarking: launch one pass `reps` times on `stream`, bracketed by HIP
  * events recorded on that stream, and return the mean duration per launch in
  * *avg_ms (synchronises).  Passes: MD_PASS_BUILD (list build), MD_PASS_DENSITY
- * (density + embedding), MD_PASS_FORCE (force + half kick, the variant used by
- * md_step), MD_PASS_KICK_DRIFT.  Positions and velocities are restored
- * afterwards, so timing leaves the trajectory unchanged. */
-enum { MD_PASS_BUILD = 0, MD_PASS_DENSITY = 1, MD_PASS_FORCE = 2, MD_PASS_KICK_DRIFT = 3 };
+ * (density + embedding), MD_PASS_FORCE (force + half kick), MD_PASS_KICK_DRIFT,
+ * MD_PASS_FORCE_STEP (the force pass as most steps of md_step run it in tiled
+ * contexts: force, half kick, and the next step's half kick and drift into the
+ * second position buffer; elsewhere the same as MD_PASS_FORCE).  Positions and
+ * velocities are restored afterwards, so timing leaves the trajectory
+ * unchanged. */
+enum {
+    MD_PASS_BUILD = 0,
+    MD_PASS_DENSITY = 1,
+    MD_PASS_FORCE = 2,
+    MD_PASS_KICK_DRIFT = 3,
+    MD_PASS_FORCE_STEP = 4
+};
 int md_time_pass(md_ctx *ctx, int32_t pass, int32_t reps, void *stream, double *avg_ms);
 
 /* Options. */
@@ -204,7 +213,10 @@ enum {
                                (default when B > 1), 0 the merged-box kernels     */
     MD_OPT_BATCH_BLOCK = 2, /* workgroup size of the persistent kernel (256/512/1024) */
     MD_OPT_USE_GRAPH = 3,   /* md_step replays a captured HIP graph (default 1)     */
-    MD_OPT_GRAPH_STEPS = 4, /* steps per captured graph (default 8)                 */
+    MD_OPT_GRAPH_STEPS = 4, /* steps per captured graph (default 9; in tiled
+                               contexts all but the last one or two steps of a
+                               graph fuse the next kick and drift into the force
+                               pass, with bitwise the same trajectory)            */
     MD_OPT_TILED = 5        /* 1: list build, density and force stage each tile's
                                neighbour records in LDS (default where the tiles
                                fit); 0: per-atom kernels gathering from HBM       */

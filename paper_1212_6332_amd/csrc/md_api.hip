@@ -206,18 +206,35 @@ void ensure_density(Ctx &c, hipStream_t s)
     }
 }
 
+// One captured graph of nsteps velocity-Verlet steps.  In tiled contexts
+// the force pass of a step also performs the next step's half kick and drift
+// (the same operations, in the same order, as the separate kick-drift
+// kernel), writing the new positions to the other position buffer; the
+// steps then alternate between the two buffers.  The last one or two steps
+// are not fused, so that the state ends where it began: in the primary
+// buffer, with velocities at the full step.  The device's rebuild request
+// is counted and cleared right after the gated build, before a fused force
+// pass can raise the next one.
 int capture_steps(Ctx &c, int nsteps)
 {
     graph_reset(c);
     hipGraph_t g = nullptr;
+    const State prim = c.st;
+    State alt = prim;
+    std::swap(alt.x, alt.xo);
+    std::swap(alt.y, alt.yo);
+    std::swap(alt.z, alt.zo);
+    int fused = c.tiled ? (nsteps % 2 ? nsteps - 1 : nsteps - 2) : 0;
     HIP_TRY(hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeRelaxed));
     for (int k = 0; k < nsteps; ++k) {
-        launch_kick_drift(c, c.cap_stream);
+        c.st = (k < fused && k % 2) ? alt : prim;
+        if (k == 0 || k > fused) launch_kick_drift(c, c.cap_stream);
         launch_build(c, true, c.cap_stream);
-        launch_density(c, c.cap_stream);
-        launch_force(c, false, true, c.cap_stream);
         launch_step_end(c, c.cap_stream);
+        launch_density(c, c.cap_stream);
+        launch_force(c, false, k < fused ? 2 : 1, c.cap_stream);
     }
+    c.st = prim;
     HIP_TRY(hipStreamEndCapture(c.cap_stream, &g));
     hipError_t e = hipGraphInstantiate(&c.graph_exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
@@ -439,7 +456,8 @@ int md_create(const md_system *sys, const md_potential *pot, md_ctx **out)
     }
 
     // atom state and build scratch
-    double **dbl[] = {&c.st.x, &c.st.y, &c.st.z, &c.st.vx, &c.st.vy, &c.st.vz, &c.st.fx,
+    double **dbl[] = {&c.st.x, &c.st.y, &c.st.z, &c.st.xo, &c.st.yo, &c.st.zo, &c.st.vx,
+                      &c.st.vy, &c.st.vz, &c.st.fx,
                       &c.st.fy, &c.st.fz, &c.st.xr, &c.st.yr, &c.st.zr, &c.st.rho, &c.st.Fp,
                       &c.st.Femb, &c.st.eat, &c.bd.sx, &c.bd.sy, &c.bd.sz, &c.bd.svx,
                       &c.bd.svy, &c.bd.svz};
@@ -602,7 +620,7 @@ int md_forces(md_ctx *h, double *f_out, double *e_atom, double *e_box, void *str
     hipStream_t s = as_stream(stream);
     ensure_density(c, s);
     bool energy = e_atom || e_box;
-    launch_force(c, energy, false, s);
+    launch_force(c, energy, 0, s);
     c.forces_valid = true;
     if (f_out) launch_scatter_vec3(c, c.st.fx, c.st.fy, c.st.fz, f_out, s);
     if (e_atom) launch_scatter_scalar(c, c.st.eat, e_atom, s);
@@ -629,7 +647,7 @@ int md_step(md_ctx *h, int nsteps, void *stream)
     ensure_list(c, s);
     if (!c.forces_valid) {
         ensure_density(c, s);
-        launch_force(c, false, false, s);
+        launch_force(c, false, 0, s);
         c.forces_valid = true;
     }
     int done = 0;
@@ -644,9 +662,9 @@ int md_step(md_ctx *h, int nsteps, void *stream)
     for (; done < nsteps; ++done) {
         launch_kick_drift(c, s);
         launch_build(c, true, s);
-        launch_density(c, s);
-        launch_force(c, false, true, s);
         launch_step_end(c, s);
+        launch_density(c, s);
+        launch_force(c, false, 1, s);
     }
     c.list_valid = c.density_valid = c.forces_valid = true;
     batched_invalidate(c);
@@ -733,14 +751,14 @@ int md_adjoint(md_ctx *h, const double *g, const double *e, double *gtheta, void
 
 int md_time_pass(md_ctx *h, int32_t pass, int32_t reps, void *stream, double *avg_ms)
 {
-    if (!h || !avg_ms || reps < 1 || pass < MD_PASS_BUILD || pass > MD_PASS_KICK_DRIFT)
+    if (!h || !avg_ms || reps < 1 || pass < MD_PASS_BUILD || pass > MD_PASS_FORCE_STEP)
         return MD_ERR_ARG;
     Ctx &c = h->c;
     if (!c.state_set) return MD_ERR_STATE;
     hipStream_t s = as_stream(stream);
     ensure_density(c, s);
     if (!c.forces_valid) {
-        launch_force(c, false, false, s);
+        launch_force(c, false, 0, s);
         c.forces_valid = true;
     }
     size_t nb = sizeof(double) * (size_t)c.N;
@@ -755,7 +773,8 @@ int md_time_pass(md_ctx *h, int32_t pass, int32_t reps, void *stream, double *av
         switch (pass) {
         case MD_PASS_BUILD: launch_build(c, false, s); break;
         case MD_PASS_DENSITY: launch_density(c, s); break;
-        case MD_PASS_FORCE: launch_force(c, false, true, s); break;
+        case MD_PASS_FORCE: launch_force(c, false, 1, s); break;
+        case MD_PASS_FORCE_STEP: launch_force(c, false, c.tiled ? 2 : 1, s); break;
         case MD_PASS_KICK_DRIFT: launch_kick_drift(c, s); break;
         }
     }
@@ -775,7 +794,7 @@ int md_time_pass(md_ctx *h, int32_t pass, int32_t reps, void *stream, double *av
     for (int k = 0; k < 6; ++k) HIP_TRY(hipMemcpyAsync(live[k], save[k], nb, hipMemcpyDeviceToDevice, s));
     launch_pack_positions(c, s);
     launch_fill_u32(c.dev.flags + 1, 1, 0u, s);
-    if (pass == MD_PASS_KICK_DRIFT) launch_force(c, false, false, s);
+    if (pass == MD_PASS_KICK_DRIFT) launch_force(c, false, 0, s);
     HIP_TRY(hipStreamSynchronize(s));
     return MD_OK;
 }

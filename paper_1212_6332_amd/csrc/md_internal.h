@@ -52,6 +52,7 @@ struct Pot {
 // Atom state in sorted (cell) order, structure of arrays.
 struct State {
     double *x, *y, *z, *vx, *vy, *vz, *fx, *fy, *fz, *xr, *yr, *zr;
+    double *xo, *yo, *zo;              // the other position buffer: drift target of a fused force pass
     double *pk;                        // [N][4] packed x, y, z, F'(rho) for neighbour gathers
     int *id;                           // original index of each sorted slot
     double *rho, *Fp, *Femb, *eat;     // density, F'(rho), F(rho), per-atom energy
@@ -96,7 +97,9 @@ void launch_get_state(Ctx &c, double *pos, double *vel, hipStream_t s);
 void launch_build(Ctx &c, bool gated, hipStream_t s);
 void launch_density(Ctx &c, hipStream_t s);
 void launch_embed(Ctx &c, hipStream_t s);
-void launch_force(Ctx &c, bool energy, bool kick, hipStream_t s);
+// kick: 0 none, 1 half kick, 2 half kick and the next step's half kick and
+// drift into the other position buffer (tiled contexts only)
+void launch_force(Ctx &c, bool energy, int kick, hipStream_t s);
 void launch_kick_drift(Ctx &c, hipStream_t s);
 void launch_step_end(Ctx &c, hipStream_t s);
 void launch_scatter_scalar(Ctx &c, const double *src, double *dst, hipStream_t s);
@@ -111,7 +114,7 @@ void launch_fill_u32(unsigned *p, int n, unsigned v, hipStream_t s);
 void tiled_prepare(Ctx &c);
 void launch_tile_nlist(Ctx &c, const unsigned *gate, hipStream_t s);
 void launch_tile_density(Ctx &c, hipStream_t s);
-void launch_tile_force(Ctx &c, bool energy, bool kick, hipStream_t s);
+void launch_tile_force(Ctx &c, bool energy, int kick, hipStream_t s);
 void launch_tile_get_neighbors(Ctx &c, int32_t *counts, int32_t *ids, int32_t cols, hipStream_t s);
 void launch_pack_positions(Ctx &c, hipStream_t s);
 
@@ -178,7 +181,7 @@ struct Ctx {
 
     // graph replay of md_step
     bool use_graph = true;
-    int graph_steps = 8;
+    int graph_steps = 9;
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     int graph_len = 0;

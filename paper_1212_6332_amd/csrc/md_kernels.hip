@@ -820,12 +820,13 @@ void launch_embed(Ctx &c, hipStream_t s)
     }
 }
 
-void launch_force(Ctx &c, bool energy, bool kick, hipStream_t s)
+void launch_force(Ctx &c, bool energy, int kick_mode, hipStream_t s)
 {
     if (c.tiled) {
-        launch_tile_force(c, energy, kick, s);
+        launch_tile_force(c, energy, kick_mode, s);
         return;
     }
+    bool kick = kick_mode > 0;  // fused drifts are captured for tiled contexts only
     bool multi = c.B > 1;
     switch (c.pot.kind) {
     case MD_POT_FS: multi ? force_t<MD_POT_FS, true>(c, energy, kick, s) : force_t<MD_POT_FS, false>(c, energy, kick, s); break;

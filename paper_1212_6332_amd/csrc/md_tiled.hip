@@ -392,9 +392,12 @@ __global__ __launch_bounds__(kT) void k_tile_density(int N, State st, Boxes bx, 
     raise_flags(flags, bad);
 }
 
-template <int KIND, bool ENERGY, bool KICK>
+// MODE 0: forces only; 1: forces and the half kick v += kick f; 2: also the
+// next step's half kick and drift, x' = x + dt (v + kick f) into the other
+// position buffer, with the rebuild test of the kick-drift kernel.
+template <int KIND, bool ENERGY, int MODE>
 __global__ __launch_bounds__(kT) void k_tile_force(int N, State st, Boxes bx, Build bd, NList nl,
-                                                   Pot pot_arg, int hmax, double kick,
+                                                   Pot pot_arg, int hmax, double kick, double dt,
                                                    unsigned *flags)
 {
     extern __shared__ __attribute__((aligned(256))) double rec[];
@@ -408,6 +411,8 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, State st, Boxes bx, Bu
     // without the energy, SMTB accumulates the negated force (see pair_coef)
     constexpr double sg = ENERGY ? 1.0 : kForceSign<KIND>;
     unsigned bad = 0;
+    bool need = false;
+    const double thr2 = bx.thr2[t.b];
     for (int i = t.s0 + threadIdx.x; i < t.s1; i += kT) {
         double xi = st.x[i], yi = st.y[i], zi = st.z[i];
         double fpi = st.Fp[i];
@@ -443,11 +448,33 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, State st, Boxes bx, Bu
         st.fy[i] = ay;
         st.fz[i] = az;
         if constexpr (ENERGY) st.eat[i] = fma(0.5, ep, st.Femb[i]);
-        if constexpr (KICK) {
-            st.vx[i] = fma(kick, ax, st.vx[i]);
-            st.vy[i] = fma(kick, ay, st.vy[i]);
-            st.vz[i] = fma(kick, az, st.vz[i]);
+        if constexpr (MODE >= 1) {
+            double vx = fma(kick, ax, st.vx[i]);
+            double vy = fma(kick, ay, st.vy[i]);
+            double vz = fma(kick, az, st.vz[i]);
+            if constexpr (MODE == 2) {
+                vx = fma(kick, ax, vx);
+                vy = fma(kick, ay, vy);
+                vz = fma(kick, az, vz);
+                double x = fma(dt, vx, xi), y = fma(dt, vy, yi), z = fma(dt, vz, zi);
+                st.xo[i] = x;
+                st.yo[i] = y;
+                st.zo[i] = z;
+                double ddx = x - st.xr[i], ddy = y - st.yr[i], ddz = z - st.zr[i];
+                double d2 = fma(ddz, ddz, fma(ddy, ddy, ddx * ddx));
+                need = need || d2 > thr2;
+                if (!isfinite(d2)) bad |= MD_FLAG_NONFINITE;
+            }
+            st.vx[i] = vx;
+            st.vy[i] = vy;
+            st.vz[i] = vz;
         }
+    }
+    if constexpr (MODE == 2) {
+        // one request per wavefront, and none once the flag is already raised
+        if (__any(need) && (threadIdx.x & 63) == 0 &&
+            __atomic_load_n(flags + 1, __ATOMIC_RELAXED) == 0u)
+            atomicOr(flags + 1, 1u);
     }
     raise_flags(flags, bad);
 }
@@ -480,18 +507,24 @@ __global__ __launch_bounds__(kT) void k_tile_get_neighbors(int N, State st, Boxe
 }
 
 template <int KIND>
-void force_launch(Ctx &c, bool energy, bool kick, double k, hipStream_t s)
+void force_launch(Ctx &c, bool energy, int mode, double k, hipStream_t s)
 {
     int N = (int)c.N, G = c.ntiles;
     size_t lds = c.tile_lds;
-    if (energy && kick)
-        k_tile_force<KIND, true, true><<<G, kT, lds, s>>>(N, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, k, c.dev.flags);
+    double dt = c.dt;
+#define MDK_FORCE(E, M) \
+    k_tile_force<KIND, E, M><<<G, kT, lds, s>>>(N, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, k, dt, c.dev.flags)
+    if (energy && mode > 0)
+        MDK_FORCE(true, 1);
     else if (energy)
-        k_tile_force<KIND, true, false><<<G, kT, lds, s>>>(N, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, k, c.dev.flags);
-    else if (kick)
-        k_tile_force<KIND, false, true><<<G, kT, lds, s>>>(N, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, k, c.dev.flags);
+        MDK_FORCE(true, 0);
+    else if (mode == 2)
+        MDK_FORCE(false, 2);
+    else if (mode == 1)
+        MDK_FORCE(false, 1);
     else
-        k_tile_force<KIND, false, false><<<G, kT, lds, s>>>(N, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, k, c.dev.flags);
+        MDK_FORCE(false, 0);
+#undef MDK_FORCE
 }
 
 template <class F>
@@ -511,18 +544,21 @@ void tiled_prepare(Ctx &c)
     allow(k_tile_density<MD_POT_FS>, lds);
     allow(k_tile_density<MD_POT_SMTB>, lds);
     allow(k_tile_density<MD_POT_SPLINE>, lds);
-    allow(k_tile_force<MD_POT_FS, true, true>, lds);
-    allow(k_tile_force<MD_POT_FS, true, false>, lds);
-    allow(k_tile_force<MD_POT_FS, false, true>, lds);
-    allow(k_tile_force<MD_POT_FS, false, false>, lds);
-    allow(k_tile_force<MD_POT_SMTB, true, true>, lds);
-    allow(k_tile_force<MD_POT_SMTB, true, false>, lds);
-    allow(k_tile_force<MD_POT_SMTB, false, true>, lds);
-    allow(k_tile_force<MD_POT_SMTB, false, false>, lds);
-    allow(k_tile_force<MD_POT_SPLINE, true, true>, lds);
-    allow(k_tile_force<MD_POT_SPLINE, true, false>, lds);
-    allow(k_tile_force<MD_POT_SPLINE, false, true>, lds);
-    allow(k_tile_force<MD_POT_SPLINE, false, false>, lds);
+    allow(k_tile_force<MD_POT_FS, true, 1>, lds);
+    allow(k_tile_force<MD_POT_FS, true, 0>, lds);
+    allow(k_tile_force<MD_POT_FS, false, 1>, lds);
+    allow(k_tile_force<MD_POT_FS, false, 0>, lds);
+    allow(k_tile_force<MD_POT_FS, false, 2>, lds);
+    allow(k_tile_force<MD_POT_SMTB, true, 1>, lds);
+    allow(k_tile_force<MD_POT_SMTB, true, 0>, lds);
+    allow(k_tile_force<MD_POT_SMTB, false, 1>, lds);
+    allow(k_tile_force<MD_POT_SMTB, false, 0>, lds);
+    allow(k_tile_force<MD_POT_SMTB, false, 2>, lds);
+    allow(k_tile_force<MD_POT_SPLINE, true, 1>, lds);
+    allow(k_tile_force<MD_POT_SPLINE, true, 0>, lds);
+    allow(k_tile_force<MD_POT_SPLINE, false, 1>, lds);
+    allow(k_tile_force<MD_POT_SPLINE, false, 0>, lds);
+    allow(k_tile_force<MD_POT_SPLINE, false, 2>, lds);
 }
 
 void launch_tile_nlist(Ctx &c, const unsigned *gate, hipStream_t s)
@@ -541,13 +577,13 @@ void launch_tile_density(Ctx &c, hipStream_t s)
     }
 }
 
-void launch_tile_force(Ctx &c, bool energy, bool kick, hipStream_t s)
+void launch_tile_force(Ctx &c, bool energy, int mode, hipStream_t s)
 {
     double k = 0.5 * c.dt * kKappaT / c.mass;
     switch (c.pot.kind) {
-    case MD_POT_FS: force_launch<MD_POT_FS>(c, energy, kick, k, s); break;
-    case MD_POT_SMTB: force_launch<MD_POT_SMTB>(c, energy, kick, k, s); break;
-    default: force_launch<MD_POT_SPLINE>(c, energy, kick, k, s); break;
+    case MD_POT_FS: force_launch<MD_POT_FS>(c, energy, mode, k, s); break;
+    case MD_POT_SMTB: force_launch<MD_POT_SMTB>(c, energy, mode, k, s); break;
+    default: force_launch<MD_POT_SPLINE>(c, energy, mode, k, s); break;
     }
 }
 

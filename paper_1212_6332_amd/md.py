@@ -22,7 +22,7 @@ MD_ERR_NONFINITE, MD_ERR_DEVICE, MD_ERR_STATE, MD_ERR_NOMEM = -5, -6, -7, -8
 MD_FLAG_NLIST_OVERFLOW, MD_FLAG_TABLE_RANGE, MD_FLAG_NONFINITE, MD_FLAG_TILE_OVERFLOW = 1, 2, 4, 8
 MD_POT_FS, MD_POT_SMTB, MD_POT_SPLINE, MD_POT_BSPLINE = 1, 2, 3, 4
 MD_OPT_BATCHED, MD_OPT_BATCH_BLOCK, MD_OPT_USE_GRAPH, MD_OPT_GRAPH_STEPS, MD_OPT_TILED = 1, 2, 3, 4, 5
-MD_PASS_BUILD, MD_PASS_DENSITY, MD_PASS_FORCE, MD_PASS_KICK_DRIFT = 0, 1, 2, 3
+MD_PASS_BUILD, MD_PASS_DENSITY, MD_PASS_FORCE, MD_PASS_KICK_DRIFT, MD_PASS_FORCE_STEP = 0, 1, 2, 3, 4
 
 
 class MDError(RuntimeError):

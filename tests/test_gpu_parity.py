@@ -213,12 +213,20 @@ def test_step_energy_conservation():
     S.close()
 
 
-def test_graph_replay_equals_direct_launches():
-    wl = W.bcc128k(ncell=8)
+@pytest.mark.parametrize("name,graph_steps", [("spline1024", 9), ("spline1024", 8),
+                                               ("smtb5324", 9), ("smtb5324", 4)])
+def test_graph_replay_equals_direct_launches(name, graph_steps):
+    """Captured steps (whose force passes also perform the next half kick and
+    drift into the second position buffer, in tiled contexts) against one
+    launch per kernel: bitwise the same trajectory, rebuild count and flags.
+    spline1024 is one tile in halo mode B, smtb5324 is cut into tiles (mode A);
+    odd and even graph lengths end the fused chain differently."""
+    wl = CASES[name]()
     out = []
     for use_graph in (1, 0):
         S = md.System.from_workload(wl)
         S.set_option(md.MD_OPT_USE_GRAPH, use_graph)
+        S.set_option(md.MD_OPT_GRAPH_STEPS, graph_steps)
         S.set_state(wl.pos, wl.vel)
         S.step(37)
         p, v = S.get_state()
@@ -226,6 +234,7 @@ def test_graph_replay_equals_direct_launches():
         S.close()
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
     assert out[0][2] == out[1][2]
+    assert out[0][2][1] >= 2  # the initial build and at least one decided on the device
 
 
 def test_error_flags():
