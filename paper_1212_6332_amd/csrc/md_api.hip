@@ -452,7 +452,11 @@ int md_create(const md_system *sys, const md_potential *pot, md_ctx **out)
         c.bx.tile = c.d_tiles;
         c.bx.tile_off = c.d_tiles + 8 * B;
         c.bx.tile_box = c.d_tiles + 9 * B + 1;
-        if (c.tile_feasible) tiled_prepare(c);
+        if (c.tile_feasible) {
+            tiled_prepare(c);
+            if ((rc = dev_alloc(c, &c.nl.tsrc, (size_t)c.ntiles * c.hmax)) != MD_OK) return fail(rc);
+            if ((rc = dev_alloc(c, &c.nl.ttotal, (size_t)c.ntiles)) != MD_OK) return fail(rc);
+        }
     }
 
     // atom state and build scratch

@@ -81,6 +81,11 @@ struct NList {
     int *total;                        // [N]: neighbours found (may exceed mn)
     int *idx;                          // [MN][N], column major (slot-fastest)
     int mn;
+    // tiled contexts: the halo records of tile g, in LDS order, as
+    // tsrc[g * hmax + k] = slot | image << 27 (image = (sx+1) + 3 (sy+1) + 9 (sz+1)),
+    // and their number ttotal[g]; written by each list build
+    unsigned *tsrc;
+    int *ttotal;
 };
 
 // Device words: flags[0] status bits, flags[1] rebuild request,

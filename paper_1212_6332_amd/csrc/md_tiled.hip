@@ -162,9 +162,18 @@ __device__ __forceinline__ double shift_of(int code, int axis, double L)
 // Every thread copies records k = tid, tid + 1024, ...; its loads are all
 // issued before the first LDS store, so a tile pays about one memory round
 // trip for its whole halo.
+constexpr unsigned kSlotBits = 27;  // slots below 2^27 (the host caps N)
+constexpr unsigned kSlotMask = (1u << kSlotBits) - 1u;
+
+__device__ __forceinline__ unsigned image_code(int code)
+{
+    return (unsigned)((code & 3) + 3 * ((code >> 2) & 3) + 9 * ((code >> 4) & 3));
+}
+
 template <bool WITH_FP>
 __device__ __forceinline__ void stage(const Tile &t, const State &st, const HaloLds &H,
-                                      double *rec, int hmax, bool shifted, unsigned *flags)
+                                      double *rec, int hmax, bool shifted, unsigned *flags,
+                                      unsigned *src_out = nullptr)
 {
     constexpr int R = 6;  // records per thread per round (hmax <= R * 1024 per round)
     int total = min(H.total, hmax);
@@ -184,6 +193,7 @@ __device__ __forceinline__ void stage(const Tile &t, const State &st, const Halo
                 }
                 int j = H.start[lo] + (k - H.off[lo]);
                 int code = H.shift[lo];
+                if (src_out) src_out[k] = (unsigned)j | image_code(code) << kSlotBits;
                 vx[u] = st.x[j] + (shifted ? shift_of(code, 0, t.L) : 0.0);
                 vy[u] = st.y[j] + (shifted ? shift_of(code, 1, t.L) : 0.0);
                 vz[u] = st.z[j] + (shifted ? shift_of(code, 2, t.L) : 0.0);
@@ -205,6 +215,53 @@ __device__ __forceinline__ void stage(const Tile &t, const State &st, const Halo
     __syncthreads();
 }
 
+// Stage the halo records of tile g from its source list (written by the list
+// build): one coalesced load of the list, then the gathers.  With `shifted`,
+// coordinates are moved to the periodic image the list records.
+template <bool WITH_FP>
+__device__ __forceinline__ void stage_list(int g, const Tile &t, const State &st, const NList &nl,
+                                           double *rec, int hmax, bool shifted)
+{
+    constexpr int R = 6;  // records per thread per round (hmax <= R * 1024 per round)
+    const int total = min(nl.ttotal[g], hmax);
+    const unsigned *src = nl.tsrc + (size_t)g * hmax;
+    for (int base = 0; base < total; base += R * kT) {
+        double vx[R], vy[R], vz[R], vf[R];
+        int kk[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            int k = base + u * kT + (int)threadIdx.x;
+            kk[u] = k;
+            if (k < total) {
+                unsigned e = src[k];
+                int j = (int)(e & kSlotMask);
+                vx[u] = st.x[j];
+                vy[u] = st.y[j];
+                vz[u] = st.z[j];
+                if constexpr (WITH_FP) vf[u] = st.Fp[j];
+                if (shifted) {
+                    int c = (int)(e >> kSlotBits), cz = c / 9, cy = (c - 9 * cz) / 3;
+                    int cx = c - 9 * cz - 3 * cy;
+                    vx[u] += (double)(cx - 1) * t.L;
+                    vy[u] += (double)(cy - 1) * t.L;
+                    vz[u] += (double)(cz - 1) * t.L;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            if (kk[u] < total) {
+                double *r = rec + 4 * (size_t)kk[u];
+                r[0] = vx[u];
+                r[1] = vy[u];
+                r[2] = vz[u];
+                if constexpr (WITH_FP) r[3] = vf[u];
+            }
+        }
+    }
+    __syncthreads();
+}
+
 // Halo cell of a local cell coordinate (tile-relative, -1..extent).
 __device__ __forceinline__ int halo_index(const Tile &t, int ix, int iy, int iz)
 {
@@ -221,9 +278,11 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
     extern __shared__ __attribute__((aligned(256))) double rec[];
     __shared__ HaloLds H;
     Tile t;
-    tile_setup(bx, bd, xcd_tile(blockIdx.x, gridDim.x), t);
+    const int g = xcd_tile(blockIdx.x, gridDim.x);
+    tile_setup(bx, bd, g, t);
     halo_table(t, bx, bd, H);
-    stage<false>(t, st, H, rec, hmax, false, flags);
+    stage<false>(t, st, H, rec, hmax, false, flags, nl.tsrc + (size_t)g * hmax);
+    if (threadIdx.x == 0) nl.ttotal[g] = H.total;
     const double L = t.L, invL = t.invL, rl2 = bx.rl2[t.b];
     const int mn = nl.mn, nc = t.nc;
     const double ncL = nc * invL;
@@ -363,12 +422,11 @@ __global__ __launch_bounds__(kT) void k_tile_density(int N, State st, Boxes bx, 
                                                      Pot pot_arg, int hmax, unsigned *flags)
 {
     extern __shared__ __attribute__((aligned(256))) double rec[];
-    __shared__ HaloLds H;
     Tile t;
-    tile_setup(bx, bd, xcd_tile(blockIdx.x, gridDim.x), t);
-    halo_table(t, bx, bd, H);
+    const int g = xcd_tile(blockIdx.x, gridDim.x);
+    tile_setup(bx, bd, g, t);
     bool shifted = t.mode == kTileA;
-    stage<false>(t, st, H, rec, hmax, shifted, flags);
+    stage_list<false>(g, t, st, nl, rec, hmax, shifted);
     const Pot pot = pinned(pot_arg);
     unsigned bad = 0;
     for (int i = t.s0 + threadIdx.x; i < t.s1; i += kT) {
@@ -401,12 +459,11 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, State st, Boxes bx, Bu
                                                    unsigned *flags)
 {
     extern __shared__ __attribute__((aligned(256))) double rec[];
-    __shared__ HaloLds H;
     Tile t;
-    tile_setup(bx, bd, xcd_tile(blockIdx.x, gridDim.x), t);
-    halo_table(t, bx, bd, H);
+    const int g = xcd_tile(blockIdx.x, gridDim.x);
+    tile_setup(bx, bd, g, t);
     bool shifted = t.mode == kTileA;
-    stage<true>(t, st, H, rec, hmax, shifted, flags);
+    stage_list<true>(g, t, st, nl, rec, hmax, shifted);
     const Pot pot = pinned(pot_arg);
     // without the energy, SMTB accumulates the negated force (see pair_coef)
     constexpr double sg = ENERGY ? 1.0 : kForceSign<KIND>;
