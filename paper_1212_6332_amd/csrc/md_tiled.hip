@@ -24,6 +24,8 @@
 // arithmetic.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "md_device.h"
 #include "md_internal.h"
 
@@ -417,36 +419,120 @@ __device__ __forceinline__ void for_row(const int *__restrict__ idx, int i, int 
     }
 }
 
+// Tile m of persistent workgroup b (of P), or -1.  Workgroups are dispatched
+// round robin over the 8 XCDs; the workgroups of one XCD sweep one contiguous
+// eighth of the tiles together, so neighbouring tiles (which share halo
+// cells) are staged through the same L2 at about the same time.
+__device__ __forceinline__ int tile_at(int b, int m, int P, int G)
+{
+    if (P % 8 == 0) {
+        int x = b % 8, Q = P / 8;
+        int lo = (int)((long long)G * x / 8), hi = (int)((long long)G * (x + 1) / 8);
+        int g = lo + b / 8 + m * Q;
+        return g < hi ? g : -1;
+    }
+    int g = b + m * P;
+    return g < G ? g : -1;
+}
+
+// Persistent driver of the tiled passes: each workgroup takes its tiles in
+// turn.  Each wave fetches its share of the next tile's halo (source list,
+// then the gathers) as soon as its own rows of the current tile are done,
+// while slower waves of the workgroup are still evaluating; after a barrier
+// the records go to LDS.
+template <bool WITH_FP, class Rows>
+__device__ __forceinline__ void run_tiles(int G, const State &st, const Boxes &bx, const Build &bd,
+                                          const NList &nl, double *rec, int hmax, Rows &&rows)
+{
+    constexpr int R = 5;  // records per thread: hmax <= R * 1024
+    const int P = gridDim.x, tid = threadIdx.x;
+    int m = 0;
+    int g = tile_at(blockIdx.x, 0, P, G);
+    if (g < 0) return;
+    Tile t;
+    tile_setup(bx, bd, g, t);
+    stage_list<WITH_FP>(g, t, st, nl, rec, hmax, t.mode == kTileA);
+    while (true) {
+        const int gn = tile_at(blockIdx.x, m + 1, P, G);
+        Tile tn = t;
+        int totn = 0;
+        if (gn >= 0) {
+            tile_setup(bx, bd, gn, tn);
+            totn = min(nl.ttotal[gn], hmax);
+        }
+        rows(t);
+        const unsigned *src = nl.tsrc + (size_t)max(gn, 0) * hmax;
+        unsigned e[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) e[u] = src[min(u * kT + tid, hmax - 1)];
+        double px[R], py[R], pz[R], pf[R];
+        const bool shn = tn.mode == kTileA;
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            int k = u * kT + tid;
+            if (k < totn) {
+                int j = (int)(e[u] & kSlotMask);
+                px[u] = st.x[j];
+                py[u] = st.y[j];
+                pz[u] = st.z[j];
+                if constexpr (WITH_FP) pf[u] = st.Fp[j];
+                if (shn) {
+                    int c = (int)(e[u] >> kSlotBits), cz = c / 9, cy = (c - 9 * cz) / 3;
+                    int cx = c - 9 * cz - 3 * cy;
+                    px[u] += (double)(cx - 1) * tn.L;
+                    py[u] += (double)(cy - 1) * tn.L;
+                    pz[u] += (double)(cz - 1) * tn.L;
+                }
+            }
+        }
+        __syncthreads();
+        if (gn < 0) break;
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            int k = u * kT + tid;
+            if (k < totn) {
+                double *r = rec + 4 * (size_t)k;
+                r[0] = px[u];
+                r[1] = py[u];
+                r[2] = pz[u];
+                if constexpr (WITH_FP) r[3] = pf[u];
+            }
+        }
+        __syncthreads();
+        t = tn;
+        ++m;
+    }
+}
+
 template <int KIND>
-__global__ __launch_bounds__(kT) void k_tile_density(int N, State st, Boxes bx, Build bd, NList nl,
-                                                     Pot pot_arg, int hmax, unsigned *flags)
+__global__ __launch_bounds__(kT) void k_tile_density(int N, int G, State st, Boxes bx, Build bd,
+                                                     NList nl, Pot pot_arg, int hmax,
+                                                     unsigned *flags)
 {
     extern __shared__ __attribute__((aligned(256))) double rec[];
-    Tile t;
-    const int g = xcd_tile(blockIdx.x, gridDim.x);
-    tile_setup(bx, bd, g, t);
-    bool shifted = t.mode == kTileA;
-    stage_list<false>(g, t, st, nl, rec, hmax, shifted);
     const Pot pot = pinned(pot_arg);
     unsigned bad = 0;
-    for (int i = t.s0 + threadIdx.x; i < t.s1; i += kT) {
-        double xi = st.x[i], yi = st.y[i], zi = st.z[i];
-        int n1 = nl.count[i] & 0xffff;
-        double rho = 0.0;
-        auto body = [&](double dx, double dy, double dz, double) {
-            double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            if (r2 < pot.rc2) rho += dens<KIND>(pot, r2 * rsqrt_nr(r2), bad);
-        };
-        if (shifted)
-            for_row<false>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
-        else
-            for_row<true>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
-        double F, Fp;
-        embed<KIND>(pot, rho, F, Fp, bad);
-        st.rho[i] = rho;
-        st.Femb[i] = F;
-        st.Fp[i] = Fp;
-    }
+    run_tiles<false>(G, st, bx, bd, nl, rec, hmax, [&](const Tile &t) {
+        const bool shifted = t.mode == kTileA;
+        for (int i = t.s0 + threadIdx.x; i < t.s1; i += kT) {
+            double xi = st.x[i], yi = st.y[i], zi = st.z[i];
+            int n1 = nl.count[i] & 0xffff;
+            double rho = 0.0;
+            auto body = [&](double dx, double dy, double dz, double) {
+                double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                if (r2 < pot.rc2) rho += dens<KIND>(pot, r2 * rsqrt_nr(r2), bad);
+            };
+            if (shifted)
+                for_row<false>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
+            else
+                for_row<true>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
+            double F, Fp;
+            embed<KIND>(pot, rho, F, Fp, bad);
+            st.rho[i] = rho;
+            st.Femb[i] = F;
+            st.Fp[i] = Fp;
+        }
+    });
     raise_flags(flags, bad);
 }
 
@@ -454,79 +540,77 @@ __global__ __launch_bounds__(kT) void k_tile_density(int N, State st, Boxes bx, 
 // next step's half kick and drift, x' = x + dt (v + kick f) into the other
 // position buffer, with the rebuild test of the kick-drift kernel.
 template <int KIND, bool ENERGY, int MODE>
-__global__ __launch_bounds__(kT) void k_tile_force(int N, State st, Boxes bx, Build bd, NList nl,
-                                                   Pot pot_arg, int hmax, double kick, double dt,
-                                                   unsigned *flags)
+__global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes bx, Build bd,
+                                                   NList nl, Pot pot_arg, int hmax, double kick,
+                                                   double dt, unsigned *flags)
 {
     extern __shared__ __attribute__((aligned(256))) double rec[];
-    Tile t;
-    const int g = xcd_tile(blockIdx.x, gridDim.x);
-    tile_setup(bx, bd, g, t);
-    bool shifted = t.mode == kTileA;
-    stage_list<true>(g, t, st, nl, rec, hmax, shifted);
     const Pot pot = pinned(pot_arg);
     // without the energy, SMTB accumulates the negated force (see pair_coef)
     constexpr double sg = ENERGY ? 1.0 : kForceSign<KIND>;
     unsigned bad = 0;
     bool need = false;
-    const double thr2 = bx.thr2[t.b];
-    for (int i = t.s0 + threadIdx.x; i < t.s1; i += kT) {
-        double xi = st.x[i], yi = st.y[i], zi = st.z[i];
-        double fpi = st.Fp[i];
-        int n1 = nl.count[i] & 0xffff;
-        double ax = 0.0, ay = 0.0, az = 0.0, ep = 0.0;
-        auto body = [&](double dx, double dy, double dz, double fpj) {
-            double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            if (r2 < pot.rc2) {
-                double inv_r = rsqrt_nr(r2);
-                // f_i += [(F'_i + F'_j) rho'(r) + V'(r)] (x_j - x_i) / r
-                double coef;
-                if constexpr (ENERGY) {
-                    double dfr, v, dv;
-                    pair_terms<KIND>(pot, r2 * inv_r, dfr, v, dv, bad);
-                    coef = fma(fpi + fpj, dfr, dv) * inv_r;
-                    ep += v;
-                } else {
-                    coef = pair_coef<KIND>(pot, r2 * inv_r, fpi + fpj, bad) * inv_r;
+    run_tiles<true>(G, st, bx, bd, nl, rec, hmax, [&](const Tile &t) {
+        const bool shifted = t.mode == kTileA;
+        const double thr2 = bx.thr2[t.b];
+        for (int i = t.s0 + threadIdx.x; i < t.s1; i += kT) {
+            double xi = st.x[i], yi = st.y[i], zi = st.z[i];
+            double fpi = st.Fp[i];
+            int n1 = nl.count[i] & 0xffff;
+            double ax = 0.0, ay = 0.0, az = 0.0, ep = 0.0;
+            auto body = [&](double dx, double dy, double dz, double fpj) {
+                double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                if (r2 < pot.rc2) {
+                    double inv_r = rsqrt_nr(r2);
+                    // f_i += [(F'_i + F'_j) rho'(r) + V'(r)] (x_j - x_i) / r
+                    double coef;
+                    if constexpr (ENERGY) {
+                        double dfr, v, dv;
+                        pair_terms<KIND>(pot, r2 * inv_r, dfr, v, dv, bad);
+                        coef = fma(fpi + fpj, dfr, dv) * inv_r;
+                        ep += v;
+                    } else {
+                        coef = pair_coef<KIND>(pot, r2 * inv_r, fpi + fpj, bad) * inv_r;
+                    }
+                    ax = fma(coef, dx, ax);
+                    ay = fma(coef, dy, ay);
+                    az = fma(coef, dz, az);
                 }
-                ax = fma(coef, dx, ax);
-                ay = fma(coef, dy, ay);
-                az = fma(coef, dz, az);
+            };
+            if (shifted)
+                for_row<false>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
+            else
+                for_row<true>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
+            ax *= sg;
+            ay *= sg;
+            az *= sg;
+            st.fx[i] = ax;
+            st.fy[i] = ay;
+            st.fz[i] = az;
+            if constexpr (ENERGY) st.eat[i] = fma(0.5, ep, st.Femb[i]);
+            if constexpr (MODE >= 1) {
+                double vx = fma(kick, ax, st.vx[i]);
+                double vy = fma(kick, ay, st.vy[i]);
+                double vz = fma(kick, az, st.vz[i]);
+                if constexpr (MODE == 2) {
+                    vx = fma(kick, ax, vx);
+                    vy = fma(kick, ay, vy);
+                    vz = fma(kick, az, vz);
+                    double x = fma(dt, vx, xi), y = fma(dt, vy, yi), z = fma(dt, vz, zi);
+                    st.xo[i] = x;
+                    st.yo[i] = y;
+                    st.zo[i] = z;
+                    double ddx = x - st.xr[i], ddy = y - st.yr[i], ddz = z - st.zr[i];
+                    double d2 = fma(ddz, ddz, fma(ddy, ddy, ddx * ddx));
+                    need = need || d2 > thr2;
+                    if (!isfinite(d2)) bad |= MD_FLAG_NONFINITE;
+                }
+                st.vx[i] = vx;
+                st.vy[i] = vy;
+                st.vz[i] = vz;
             }
-        };
-        if (shifted)
-            for_row<false>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
-        else
-            for_row<true>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
-        ax *= sg;
-        ay *= sg;
-        az *= sg;
-        st.fx[i] = ax;
-        st.fy[i] = ay;
-        st.fz[i] = az;
-        if constexpr (ENERGY) st.eat[i] = fma(0.5, ep, st.Femb[i]);
-        if constexpr (MODE >= 1) {
-            double vx = fma(kick, ax, st.vx[i]);
-            double vy = fma(kick, ay, st.vy[i]);
-            double vz = fma(kick, az, st.vz[i]);
-            if constexpr (MODE == 2) {
-                vx = fma(kick, ax, vx);
-                vy = fma(kick, ay, vy);
-                vz = fma(kick, az, vz);
-                double x = fma(dt, vx, xi), y = fma(dt, vy, yi), z = fma(dt, vz, zi);
-                st.xo[i] = x;
-                st.yo[i] = y;
-                st.zo[i] = z;
-                double ddx = x - st.xr[i], ddy = y - st.yr[i], ddz = z - st.zr[i];
-                double d2 = fma(ddz, ddz, fma(ddy, ddy, ddx * ddx));
-                need = need || d2 > thr2;
-                if (!isfinite(d2)) bad |= MD_FLAG_NONFINITE;
-            }
-            st.vx[i] = vx;
-            st.vy[i] = vy;
-            st.vz[i] = vz;
         }
-    }
+    });
     if constexpr (MODE == 2) {
         // one request per wavefront, and none once the flag is already raised
         if (__any(need) && (threadIdx.x & 63) == 0 &&
@@ -566,11 +650,11 @@ __global__ __launch_bounds__(kT) void k_tile_get_neighbors(int N, State st, Boxe
 template <int KIND>
 void force_launch(Ctx &c, bool energy, int mode, double k, hipStream_t s)
 {
-    int N = (int)c.N, G = c.ntiles;
+    const int N = (int)c.N, G = c.ntiles, P = c.tile_grid;
     size_t lds = c.tile_lds;
     double dt = c.dt;
 #define MDK_FORCE(E, M) \
-    k_tile_force<KIND, E, M><<<G, kT, lds, s>>>(N, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, k, dt, c.dev.flags)
+    k_tile_force<KIND, E, M><<<P, kT, lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, k, dt, c.dev.flags)
     if (energy && mode > 0)
         MDK_FORCE(true, 1);
     else if (energy)
@@ -597,6 +681,15 @@ static constexpr double kKappaT = 1.602176634e-19 / 1.66053906660e-27 * 1e-10;
 void tiled_prepare(Ctx &c)
 {
     size_t lds = c.tile_lds;
+    // persistent grid of the passes: as many workgroups as can be resident
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_force<MD_POT_SMTB, false, 2>,
+                                                     kT, lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device) != hipSuccess ||
+        cus < 1)
+        cus = 1;
+    c.tile_grid = std::max(1, std::min(c.ntiles, per_cu * cus));
     allow(k_tile_nlist, lds);
     allow(k_tile_density<MD_POT_FS>, lds);
     allow(k_tile_density<MD_POT_SMTB>, lds);
@@ -626,11 +719,11 @@ void launch_tile_nlist(Ctx &c, const unsigned *gate, hipStream_t s)
 
 void launch_tile_density(Ctx &c, hipStream_t s)
 {
-    int N = (int)c.N;
+    const int N = (int)c.N, P = c.tile_grid, G = c.ntiles;
     switch (c.pot.kind) {
-    case MD_POT_FS: k_tile_density<MD_POT_FS><<<c.ntiles, kT, c.tile_lds, s>>>(N, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
-    case MD_POT_SMTB: k_tile_density<MD_POT_SMTB><<<c.ntiles, kT, c.tile_lds, s>>>(N, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
-    default: k_tile_density<MD_POT_SPLINE><<<c.ntiles, kT, c.tile_lds, s>>>(N, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
+    case MD_POT_FS: k_tile_density<MD_POT_FS><<<P, kT, c.tile_lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
+    case MD_POT_SMTB: k_tile_density<MD_POT_SMTB><<<P, kT, c.tile_lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
+    default: k_tile_density<MD_POT_SPLINE><<<P, kT, c.tile_lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
     }
 }
 
