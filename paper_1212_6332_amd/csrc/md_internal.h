@@ -152,7 +152,7 @@ struct Ctx {
     std::vector<int> box_nc, box_cell_off;
     std::vector<int> box_tile;         // per box: tx ty tz gx gy gz tile_cells mode
     int ntiles = 0;
-    int tile_grid = 1;                 // workgroups of the persistent tiled passes
+    int tile_grid = 1;                 // workgroups of the persistent tiled density pass
     bool tiled = false, tile_feasible = false;
     int hmax = 0;                      // LDS records per tile
     size_t tile_lds = 0;               // dynamic LDS bytes of a tiled-pass workgroup

@@ -550,8 +550,14 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
     constexpr double sg = ENERGY ? 1.0 : kForceSign<KIND>;
     unsigned bad = 0;
     bool need = false;
-    run_tiles<true>(G, st, bx, bd, nl, rec, hmax, [&](const Tile &t) {
+    // one workgroup per tile (with the persistent driver the fused variant
+    // needs more registers than it gains)
+    {
+        const int g = xcd_tile(blockIdx.x, gridDim.x);
+        Tile t;
+        tile_setup(bx, bd, g, t);
         const bool shifted = t.mode == kTileA;
+        stage_list<true>(g, t, st, nl, rec, hmax, shifted);
         const double thr2 = bx.thr2[t.b];
         for (int i = t.s0 + threadIdx.x; i < t.s1; i += kT) {
             double xi = st.x[i], yi = st.y[i], zi = st.z[i];
@@ -610,7 +616,7 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
                 st.vz[i] = vz;
             }
         }
-    });
+    }
     if constexpr (MODE == 2) {
         // one request per wavefront, and none once the flag is already raised
         if (__any(need) && (threadIdx.x & 63) == 0 &&
@@ -650,11 +656,11 @@ __global__ __launch_bounds__(kT) void k_tile_get_neighbors(int N, State st, Boxe
 template <int KIND>
 void force_launch(Ctx &c, bool energy, int mode, double k, hipStream_t s)
 {
-    const int N = (int)c.N, G = c.ntiles, P = c.tile_grid;
+    const int N = (int)c.N, G = c.ntiles;
     size_t lds = c.tile_lds;
     double dt = c.dt;
 #define MDK_FORCE(E, M) \
-    k_tile_force<KIND, E, M><<<P, kT, lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, k, dt, c.dev.flags)
+    k_tile_force<KIND, E, M><<<G, kT, lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, k, dt, c.dev.flags)
     if (energy && mode > 0)
         MDK_FORCE(true, 1);
     else if (energy)
@@ -681,10 +687,10 @@ static constexpr double kKappaT = 1.602176634e-19 / 1.66053906660e-27 * 1e-10;
 void tiled_prepare(Ctx &c)
 {
     size_t lds = c.tile_lds;
-    // persistent grid of the passes: as many workgroups as can be resident
+    // persistent grid of the density pass: as many workgroups as can be resident
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_force<MD_POT_SMTB, false, 2>,
-                                                     kT, lds) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_density<MD_POT_SMTB>, kT,
+                                                     lds) != hipSuccess || per_cu < 1)
         per_cu = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device) != hipSuccess ||
         cus < 1)
