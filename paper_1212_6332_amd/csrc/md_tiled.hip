@@ -563,6 +563,19 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
             double xi = st.x[i], yi = st.y[i], zi = st.z[i];
             double fpi = st.Fp[i];
             int n1 = nl.count[i] & 0xffff;
+            // the epilogue's inputs are loaded before the row, so their
+            // latency hides behind it
+            double v0x = 0.0, v0y = 0.0, v0z = 0.0, rx = 0.0, ry = 0.0, rz = 0.0;
+            if constexpr (MODE >= 1) {
+                v0x = st.vx[i];
+                v0y = st.vy[i];
+                v0z = st.vz[i];
+            }
+            if constexpr (MODE == 2) {
+                rx = st.xr[i];
+                ry = st.yr[i];
+                rz = st.zr[i];
+            }
             double ax = 0.0, ay = 0.0, az = 0.0, ep = 0.0;
             auto body = [&](double dx, double dy, double dz, double fpj) {
                 double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
@@ -595,9 +608,9 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
             st.fz[i] = az;
             if constexpr (ENERGY) st.eat[i] = fma(0.5, ep, st.Femb[i]);
             if constexpr (MODE >= 1) {
-                double vx = fma(kick, ax, st.vx[i]);
-                double vy = fma(kick, ay, st.vy[i]);
-                double vz = fma(kick, az, st.vz[i]);
+                double vx = fma(kick, ax, v0x);
+                double vy = fma(kick, ay, v0y);
+                double vz = fma(kick, az, v0z);
                 if constexpr (MODE == 2) {
                     vx = fma(kick, ax, vx);
                     vy = fma(kick, ay, vy);
@@ -606,7 +619,7 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
                     st.xo[i] = x;
                     st.yo[i] = y;
                     st.zo[i] = z;
-                    double ddx = x - st.xr[i], ddy = y - st.yr[i], ddz = z - st.zr[i];
+                    double ddx = x - rx, ddy = y - ry, ddz = z - rz;
                     double d2 = fma(ddz, ddz, fma(ddy, ddy, ddx * ddx));
                     need = need || d2 > thr2;
                     if (!isfinite(d2)) bad |= MD_FLAG_NONFINITE;
