@@ -79,6 +79,14 @@ def lib():
         L.orc_threads.restype = i32
         L.orc_adjoint.argtypes = [i64, _f64p, _f64p, _f64p, dbl, P, _i32p, _i32p, i32, _f64p,
                                   _f64p, _f64p, dbl, _f64p]
+        L.orc_virial.argtypes = [i64, _f64p, _f64p, _f64p, dbl, P, _i32p, _i32p, i32, _f64p]
+        L.orc_virial.restype = dbl
+        L.orc_virial_direct.argtypes = [i64, _f64p, _f64p, _f64p, dbl, P]
+        L.orc_virial_direct.restype = dbl
+        L.orc_vv_baro.argtypes = [i64, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p,
+                                  C.POINTER(dbl), P, dbl, dbl, dbl, i32, i32, dbl, dbl, dbl,
+                                  C.c_void_p]
+        L.orc_vv_baro.restype = i32
         _lib = L
     return _lib
 
@@ -249,6 +257,42 @@ def forces_multi(W, pos=None, pot=None):
         out["Fp"][s] = r["Fp"]
         out["E_box"][b] = r["E"]
     return out
+
+
+def virial(pos, L, pot: Pot, skin=0.3):
+    """Pair virial W = sum_{i<j} r_ij . f_ij (eq. 6 for a periodic box) over a
+    fresh list."""
+    x, y, z = _xyz(pos)
+    count, ids = neighbor_list(pos, L, rlist(pot.rc, skin, L))
+    r = forces(pos, L, pot, count, ids)
+    ids = np.ascontiguousarray(ids, dtype=np.int32)
+    return float(lib().orc_virial(x.size, x, y, z, float(L), pot.ref, count, ids, ids.shape[1],
+                                  r["Fp"]))
+
+
+def virial_direct(pos, L, pot: Pot):
+    x, y, z = _xyz(pos)
+    return float(lib().orc_virial_direct(x.size, x, y, z, float(L), pot.ref))
+
+
+def pressure(pos, vel, L, pot: Pot, mass, skin=0.3):
+    """Instantaneous pressure of eq. (6), P = (2 E_kin + W) / (3 V), in eV/Angstrom^3."""
+    return (2.0 * kinetic(vel, mass) + virial(pos, L, pot, skin)) / (3.0 * float(L) ** 3)
+
+
+def vv_baro(pos, vel, L, pot: Pot, mass, dt, skin, nsteps, p0, tau, beta, maxn=256):
+    """Velocity Verlet with the Berendsen barostat of eq. (5).
+    Returns (pos, vel, L, pressures[nsteps + 1], rebuilds)."""
+    x, y, z = _xyz(pos)
+    vx, vy, vz = _xyz(vel)
+    Lc = C.c_double(float(L))
+    pr = np.zeros(nsteps + 1)
+    nreb = lib().orc_vv_baro(x.size, x, y, z, vx, vy, vz, C.byref(Lc), pot.ref, float(mass),
+                             float(dt), float(skin), int(nsteps), int(maxn), float(p0),
+                             float(tau), float(beta), pr.ctypes.data)
+    if nreb < 0:
+        raise ValueError("neighbour row overflow in orc_vv_baro")
+    return (np.stack([x, y, z], axis=1), np.stack([vx, vy, vz], axis=1), Lc.value, pr, nreb)
 
 
 def threads() -> int:

@@ -723,6 +723,158 @@ int orc_vv(int64_t n, double *x, double *y, double *z, double *vx, double *vy, d
     return bad ? -1 : rebuilds;
 }
 
+/* ------------------------------------------------------------------ pressure */
+
+/*
+ * Virial of eq. (6) for a periodic box.  Summing f_i . r_i over atoms is not
+ * invariant under the periodic images, so the sum is taken in its pair form:
+ * with the pair decomposition of eq. (3), f_i = sum_j f_ij and f_ji = -f_ij,
+ * sum_i f_i . r_i = sum_{i<j} f_ij . r_ij with r_ij = r_i - r_j the minimum
+ * image separation.  f_ij = -[(F'_i + F'_j) f'(r) + phi'(r)] r_ij / r, so
+ *   W = -1/2 sum_i sum_{j in L_i, r < rc} [(F'_i + F'_j) f'(r_ij) + phi'(r_ij)] r_ij.
+ * The pressure is then P = (N k_B T + W/3)/V with N k_B T = (2/3) E_kin,
+ * i.e. P = (2 E_kin + W) / (3 V).
+ */
+double orc_virial(int64_t n, const double *x, const double *y, const double *z, double L,
+                  const orc_pot *p, const int32_t *count, const int32_t *ids, int maxn,
+                  const double *Fp)
+{
+    double rc2 = p->rc * p->rc;
+    double w = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int k = 0; k < count[i]; ++k) {
+            int64_t j = ids[i * maxn + k];
+            double dx, dy, dz;
+            double r2 = sep2(x, y, z, i, j, L, &dx, &dy, &dz);
+            if (r2 < rc2) {
+                double r = sqrt(r2), v, dv, f, df;
+                pot_pair(p, r, &v, &dv);
+                pot_dens(p, r, &f, &df);
+                w += ((Fp[i] + Fp[j]) * df + dv) * r;
+            }
+        }
+    }
+    return -0.5 * w;
+}
+
+/* The same virial by a direct sum over all pairs (densities included). */
+double orc_virial_direct(int64_t n, const double *x, const double *y, const double *z, double L,
+                         const orc_pot *p)
+{
+    double rc2 = p->rc * p->rc;
+    double *Fp = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx, dy, dz;
+            double r2 = sep2(x, y, z, i, j, L, &dx, &dy, &dz);
+            if (r2 < rc2) {
+                double f, df;
+                pot_dens(p, sqrt(r2), &f, &df);
+                s += f;
+            }
+        }
+        double F, ddF;
+        pot_embed(p, s, &F, &Fp[i], &ddF);
+    }
+    double w = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = i + 1; j < n; ++j) {
+            double dx, dy, dz;
+            double r2 = sep2(x, y, z, i, j, L, &dx, &dy, &dz);
+            if (r2 < rc2) {
+                double r = sqrt(r2), v, dv, f, df;
+                pot_pair(p, r, &v, &dv);
+                pot_dens(p, r, &f, &df);
+                w -= ((Fp[i] + Fp[j]) * df + dv) * r;
+            }
+        }
+    free(Fp);
+    return w;
+}
+
+/*
+ * Velocity Verlet with the Berendsen barostat of eq. (5).  Every step: half
+ * kick, drift, then every coordinate and the box edge are multiplied by
+ * mu = [1 - beta (dt / tau) (P0 - P)]^(1/3), with P the pressure of eq. (6)
+ * at the end of the previous step (for the first step, of the initial state);
+ * conditional rebuild, forces, half kick, new pressure.  The paper writes
+ * eq. (5) without the compressibility beta (beta = 1 in its units).
+ * The list radius is fixed from the initial box; the reference positions of
+ * the rebuild test are scaled with the coordinates, and the list is rebuilt
+ * when 2 max|x - x_ref| + |1 - s| r_list reaches r_list - rc, with s the
+ * product of the scale factors since the last build (pair separations that
+ * were >= r_list at the build are then still >= rc).
+ * L (in/out) is the box edge; press (length nsteps+1, may be NULL) receives
+ * the pressures.  Returns the number of rebuilds, or -1 on row overflow.
+ */
+int orc_vv_baro(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
+                double *Lio, const orc_pot *p, double mass, double dt, double skin, int nsteps,
+                int maxn, double p0, double tau, double beta, double *press)
+{
+    double L = *Lio;
+    orc_md s = {n, x, y, z, vx, vy, vz, L, mass, dt, skin, p, maxn};
+    double rlist = orc_rlist(p->rc, skin, L);
+    size_t nb = sizeof(double) * (n > 0 ? n : 1);
+    int32_t *count = (int32_t *)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+    int32_t *ids = (int32_t *)malloc(sizeof(int32_t) * (n > 0 ? n : 1) * maxn);
+    double *xr = malloc(nb), *yr = malloc(nb), *zr = malloc(nb);
+    double *rho = malloc(nb), *F = malloc(nb), *Fp = malloc(nb);
+    double *fx = malloc(nb), *fy = malloc(nb), *fz = malloc(nb), *e = malloc(nb);
+    int rebuilds = 0, bad = 0;
+    bad |= md_rebuild(&s, rlist, count, ids, xr, yr, zr);
+    md_forces(&s, count, ids, rho, F, Fp, fx, fy, fz, e);
+    double W = orc_virial(n, x, y, z, s.L, p, count, ids, maxn, Fp);
+    double P = (2.0 * md_kinetic(&s) + W) / (3.0 * s.L * s.L * s.L);
+    if (press) press[0] = P;
+    double c = 0.5 * dt * ORC_KAPPA / mass, strain = 1.0;
+    for (int step = 1; step <= nsteps; ++step) {
+        double mu = cbrt(1.0 - beta * (dt / tau) * (p0 - P));
+        for (int64_t i = 0; i < n; ++i) {
+            vx[i] += c * fx[i];
+            vy[i] += c * fy[i];
+            vz[i] += c * fz[i];
+            x[i] += dt * vx[i];
+            y[i] += dt * vy[i];
+            z[i] += dt * vz[i];
+            x[i] *= mu;
+            y[i] *= mu;
+            z[i] *= mu;
+            xr[i] *= mu;
+            yr[i] *= mu;
+            zr[i] *= mu;
+        }
+        s.L *= mu;
+        strain *= mu;
+        double worst = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            double ddx = x[i] - xr[i], ddy = y[i] - yr[i], ddz = z[i] - zr[i];
+            double d2 = ddx * ddx + ddy * ddy + ddz * ddz;
+            if (d2 > worst) worst = d2;
+        }
+        double half = 0.5 * ((rlist - p->rc) - fabs(1.0 - strain) * rlist);
+        if (half < 0.0 || worst > half * half) {
+            bad |= md_rebuild(&s, rlist, count, ids, xr, yr, zr);
+            strain = 1.0;
+            ++rebuilds;
+        }
+        md_forces(&s, count, ids, rho, F, Fp, fx, fy, fz, e);
+        for (int64_t i = 0; i < n; ++i) {
+            vx[i] += c * fx[i];
+            vy[i] += c * fy[i];
+            vz[i] += c * fz[i];
+        }
+        W = orc_virial(n, x, y, z, s.L, p, count, ids, maxn, Fp);
+        P = (2.0 * md_kinetic(&s) + W) / (3.0 * s.L * s.L * s.L);
+        if (press) press[step] = P;
+    }
+    *Lio = s.L;
+    free(count); free(ids); free(xr); free(yr); free(zr);
+    free(rho); free(F); free(Fp); free(fx); free(fy); free(fz); free(e);
+    return bad ? -1 : rebuilds;
+}
+
 /* ------------------------------------------------------------------ adjoint */
 
 /*
