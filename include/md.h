@@ -60,7 +60,11 @@ enum {
     MD_FLAG_NLIST_OVERFLOW = 1u,
     MD_FLAG_TABLE_RANGE = 2u,
     MD_FLAG_NONFINITE = 4u,
-    MD_FLAG_TILE_OVERFLOW = 8u   /* a tile's halo exceeded its LDS capacity        */
+    MD_FLAG_TILE_OVERFLOW = 8u,  /* a tile's halo exceeded its LDS capacity        */
+    MD_FLAG_BOX_RANGE = 16u      /* the barostat would have shrunk a box below its
+                                    cell grid (cells narrower than the list radius,
+                                    or the list radius >= half the box); that
+                                    box was left unscaled                          */
 };
 
 /* Potential kinds. */
@@ -189,6 +193,34 @@ int md_status(md_ctx *ctx, void *stream, uint32_t *flags, int64_t *counters);
  * list; the reduction order is fixed, so results are bitwise reproducible. */
 int md_adjoint(md_ctx *ctx, const double *g, const double *e, double *gtheta, void *stream);
 
+/* Instantaneous pressure per box, eq. (6) of Section 2:
+ * P_b = (N k_B T + W_b / 3) / V_b with N k_B T = (2/3) E_kin,b.  For a periodic
+ * box the sum over atoms f_i . r_i is taken in its pair form
+ * W_b = sum over pairs i<j of r_ij . f_ij (r_ij the minimum-image separation,
+ * f_ij the pair contribution of eq. (3) to f_i), which the force pass
+ * accumulates per atom.  Runs the force pass with energies (as md_forces)
+ * and writes p_box[B] (eV/Angstrom^3) and w_box[B] (eV), device pointers,
+ * either may be NULL but not both. */
+int md_pressure(md_ctx *ctx, double *p_box, double *w_box, void *stream);
+
+/* Berendsen barostat, eq. (5) of Section 2, applied by md_step: after the
+ * drift of every step, all coordinates of box b and its edge are multiplied
+ * by mu_b = [1 - beta (dt / tau) (p0 - P_b)]^(1/3), P_b the pressure at the
+ * end of the previous step (of the current state for the first step).  The
+ * paper's eq. (5) is this form with beta = 1 in its units; beta is the
+ * coupling compressibility (Angstrom^3/eV), p0 the target (eV/Angstrom^3),
+ * tau the coupling time (fs).  tau > 0 switches the barostat on (beta > 0
+ * and finite values required, else MD_ERR_ARG); tau <= 0 switches it off.
+ * While it is on, md_step uses the merged-box path for several boxes, the
+ * list radius of each box stays fixed, and the list is also rebuilt when the
+ * strain since the last build could bring a listed-out pair inside the
+ * cutoff; a box that would shrink below its cell grid is left unscaled and
+ * raises MD_FLAG_BOX_RANGE. */
+int md_set_barostat(md_ctx *ctx, double p0, double tau, double beta);
+
+/* Current box edges (host box_len[B]; synchronises stream). */
+int md_get_box(md_ctx *ctx, double *box_len, void *stream);
+
 /* Benchmarking: launch one pass `reps` times on `stream`, bracketed by HIP
  * events recorded on that stream, and return the mean duration per launch in
  * *avg_ms (synchronises).  Passes: MD_PASS_BUILD (list build), MD_PASS_DENSITY
@@ -203,7 +235,9 @@ enum {
     MD_PASS_DENSITY = 1,
     MD_PASS_FORCE = 2,
     MD_PASS_KICK_DRIFT = 3,
-    MD_PASS_FORCE_STEP = 4
+    MD_PASS_FORCE_STEP = 4,
+    MD_PASS_PRESSURE = 5   /* force pass with energies and the virial, then the
+                              per-box pressure of md_pressure                  */
 };
 int md_time_pass(md_ctx *ctx, int32_t pass, int32_t reps, void *stream, double *avg_ms);
 

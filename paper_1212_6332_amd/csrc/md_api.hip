@@ -206,15 +206,41 @@ void ensure_density(Ctx &c, hipStream_t s)
     }
 }
 
-// One captured graph of nsteps velocity-Verlet steps.  In tiled contexts
-// the force pass of a step also performs the next step's half kick and drift
-// (the same operations, in the same order, as the separate kick-drift
-// kernel), writing the new positions to the other position buffer; the
-// steps then alternate between the two buffers.  The last one or two steps
-// are not fused, so that the state ends where it began: in the primary
-// buffer, with velocities at the full step.  The device's rebuild request
-// is counted and cleared right after the gated build, before a fused force
-// pass can raise the next one.
+// One velocity-Verlet step on stream s.  kick_drift: the step starts with
+// the half kick and drift (false when the previous force pass performed
+// them); force_mode: 1 the force pass ends with the half kick, 2 it also
+// performs the next step's half kick and drift into the second position
+// buffer.  The device's rebuild request is counted and cleared right after
+// the gated build, before a fused force pass can raise the next one.  With
+// the barostat (eq. 5) the coordinates and boxes are scaled after the drift,
+// and the force pass computes energies and the virial for the next pressure
+// (eq. 6) and scale factor.
+void launch_step(Ctx &c, hipStream_t s, bool kick_drift, int force_mode)
+{
+    if (c.baro_on) {
+        launch_kick_drift(c, s);
+        launch_baro_box_scale(c, s);
+        launch_build(c, true, s);
+        launch_step_end(c, s);
+        launch_density(c, s);
+        launch_force(c, true, 1, s);
+        launch_pressure_eval(c, s);
+        launch_baro_mu(c, s);
+        return;
+    }
+    if (kick_drift) launch_kick_drift(c, s);
+    launch_build(c, true, s);
+    launch_step_end(c, s);
+    launch_density(c, s);
+    launch_force(c, false, force_mode, s);
+}
+
+// One captured graph of nsteps steps.  In tiled contexts without the
+// barostat the force pass of a step also performs the next step's half kick
+// and drift (the same operations, in the same order, as the separate
+// kick-drift kernel) and the steps alternate between the two position
+// buffers; the last one or two steps are not fused, so that the state ends
+// where it began: in the primary buffer, with velocities at the full step.
 int capture_steps(Ctx &c, int nsteps)
 {
     graph_reset(c);
@@ -224,15 +250,11 @@ int capture_steps(Ctx &c, int nsteps)
     std::swap(alt.x, alt.xo);
     std::swap(alt.y, alt.yo);
     std::swap(alt.z, alt.zo);
-    int fused = c.tiled ? (nsteps % 2 ? nsteps - 1 : nsteps - 2) : 0;
+    int fused = (c.tiled && !c.baro_on) ? (nsteps % 2 ? nsteps - 1 : nsteps - 2) : 0;
     HIP_TRY(hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeRelaxed));
     for (int k = 0; k < nsteps; ++k) {
         c.st = (k < fused && k % 2) ? alt : prim;
-        if (k == 0 || k > fused) launch_kick_drift(c, c.cap_stream);
-        launch_build(c, true, c.cap_stream);
-        launch_step_end(c, c.cap_stream);
-        launch_density(c, c.cap_stream);
-        launch_force(c, false, k < fused ? 2 : 1, c.cap_stream);
+        launch_step(c, c.cap_stream, k == 0 || k > fused, k < fused ? 2 : 1);
     }
     c.st = prim;
     HIP_TRY(hipStreamEndCapture(c.cap_stream, &g));
@@ -463,7 +485,7 @@ int md_create(const md_system *sys, const md_potential *pot, md_ctx **out)
     double **dbl[] = {&c.st.x, &c.st.y, &c.st.z, &c.st.xo, &c.st.yo, &c.st.zo, &c.st.vx,
                       &c.st.vy, &c.st.vz, &c.st.fx,
                       &c.st.fy, &c.st.fz, &c.st.xr, &c.st.yr, &c.st.zr, &c.st.rho, &c.st.Fp,
-                      &c.st.Femb, &c.st.eat, &c.bd.sx, &c.bd.sy, &c.bd.sz, &c.bd.svx,
+                      &c.st.Femb, &c.st.eat, &c.st.wat, &c.bd.sx, &c.bd.sy, &c.bd.sz, &c.bd.svx,
                       &c.bd.svy, &c.bd.svz};
     for (double **p : dbl)
         if ((rc = dev_alloc(c, p, (size_t)N)) != MD_OK) return fail(rc);
@@ -479,6 +501,19 @@ int md_create(const md_system *sys, const md_potential *pot, md_ctx **out)
         return fail(MD_ERR_DEVICE);
     if ((rc = alloc_list(c, mn)) != MD_OK) return fail(rc);
     if ((rc = dev_alloc(c, &c.dev.flags, 8)) != MD_OK) return fail(rc);
+    {
+        // barostat state per box: mu = 1, strain = 1, list radius, then results
+        std::vector<double> hb(7 * (size_t)B, 0.0);
+        for (int b = 0; b < B; ++b) {
+            hb[b] = 1.0;
+            hb[B + b] = 1.0;
+            hb[2 * B + b] = c.box_rlist[b];
+        }
+        if ((rc = dev_alloc(c, &c.d_baro, hb.size())) != MD_OK) return fail(rc);
+        if (hipMemcpy(c.d_baro, hb.data(), hb.size() * sizeof(double), hipMemcpyHostToDevice) !=
+            hipSuccess)
+            return fail(MD_ERR_DEVICE);
+    }
     if (hipMemset(c.dev.flags, 0, 8 * sizeof(unsigned)) != hipSuccess) return fail(MD_ERR_DEVICE);
     if (hipMemset(c.nl.count, 0, sizeof(int) * N) != hipSuccess ||
         hipMemset(c.nl.total, 0, sizeof(int) * N) != hipSuccess)
@@ -556,6 +591,7 @@ int md_set_theta(md_ctx *h, const double *theta, void *stream)
                            hipMemcpyDeviceToDevice, s));
     launch_bspline_tables(c, c.theta, s);
     c.density_valid = c.forces_valid = false;
+    c.baro_mu_valid = false;
     return MD_OK;
 }
 
@@ -566,6 +602,7 @@ int md_set_state(md_ctx *h, const double *pos, const double *vel, void *stream)
     launch_set_state(c, pos, vel, as_stream(stream));
     c.state_set = true;
     c.list_valid = c.density_valid = c.forces_valid = false;
+    c.baro_mu_valid = false;
     return MD_OK;
 }
 
@@ -639,7 +676,7 @@ int md_step(md_ctx *h, int nsteps, void *stream)
     if (!c.state_set) return MD_ERR_STATE;
     if (nsteps == 0) return MD_OK;
     hipStream_t s = as_stream(stream);
-    if (c.B > 1 && c.batched) {
+    if (c.B > 1 && c.batched && !c.baro_on) {
         launch_batched_steps(c, nsteps, s);
         c.host_steps += nsteps;
         // forces in the state arrays match the new positions; the merged-box
@@ -649,7 +686,14 @@ int md_step(md_ctx *h, int nsteps, void *stream)
         return MD_OK;
     }
     ensure_list(c, s);
-    if (!c.forces_valid) {
+    if (c.baro_on && !c.baro_mu_valid) {
+        // pressure of the current state: the first step's scale factor
+        ensure_density(c, s);
+        launch_force(c, true, 0, s);
+        launch_pressure_eval(c, s);
+        launch_baro_mu(c, s);
+        c.forces_valid = c.baro_mu_valid = true;
+    } else if (!c.forces_valid) {
         ensure_density(c, s);
         launch_force(c, false, 0, s);
         c.forces_valid = true;
@@ -663,15 +707,65 @@ int md_step(md_ctx *h, int nsteps, void *stream)
         for (; done + c.graph_len <= nsteps; done += c.graph_len)
             HIP_TRY(hipGraphLaunch(c.graph_exec, s));
     }
-    for (; done < nsteps; ++done) {
-        launch_kick_drift(c, s);
-        launch_build(c, true, s);
-        launch_step_end(c, s);
-        launch_density(c, s);
-        launch_force(c, false, 1, s);
-    }
+    for (; done < nsteps; ++done) launch_step(c, s, true, 1);
     c.list_valid = c.density_valid = c.forces_valid = true;
     batched_invalidate(c);
+    return MD_OK;
+}
+
+int md_pressure(md_ctx *h, double *p_box, double *w_box, void *stream)
+{
+    if (!h || (!p_box && !w_box)) return MD_ERR_ARG;
+    Ctx &c = h->c;
+    if (!c.state_set) return MD_ERR_STATE;
+    hipStream_t s = as_stream(stream);
+    ensure_density(c, s);
+    launch_force(c, true, 0, s);
+    c.forces_valid = true;
+    launch_pressure_eval(c, s);
+    size_t nb = sizeof(double) * (size_t)c.B;
+    if (p_box) HIP_TRY(hipMemcpyAsync(p_box, c.d_baro + 3 * c.B, nb, hipMemcpyDeviceToDevice, s));
+    if (w_box) HIP_TRY(hipMemcpyAsync(w_box, c.d_baro + 4 * c.B, nb, hipMemcpyDeviceToDevice, s));
+    return MD_OK;
+}
+
+int md_set_barostat(md_ctx *h, double p0, double tau, double beta)
+{
+    if (!h) return MD_ERR_ARG;
+    Ctx &c = h->c;
+    if (tau > 0.0) {
+        if (!std::isfinite(p0) || !std::isfinite(tau) || !(beta > 0.0) || !std::isfinite(beta))
+            return MD_ERR_ARG;
+        c.baro_on = true;
+        c.baro_p0 = p0;
+        c.baro_tau = tau;
+        c.baro_beta = beta;
+    } else if (c.baro_on) {
+        // back to fixed boxes: the host takes the current box lengths, and the
+        // next pass rebuilds the list without strain
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipMemcpy(c.box_len.data(), c.d_boxd, sizeof(double) * (size_t)c.B,
+                          hipMemcpyDeviceToHost));
+        c.baro_on = false;
+        c.list_valid = c.density_valid = c.forces_valid = false;
+        if (c.B > 1) {
+            int rc = batched_prepare(c);
+            if (rc != MD_OK) return rc;
+        }
+    }
+    c.baro_mu_valid = false;
+    graph_reset(c);
+    return MD_OK;
+}
+
+int md_get_box(md_ctx *h, double *box_len, void *stream)
+{
+    if (!h || !box_len) return MD_ERR_ARG;
+    Ctx &c = h->c;
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(hipMemcpyAsync(box_len, c.d_boxd, sizeof(double) * (size_t)c.B,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
     return MD_OK;
 }
 
@@ -755,7 +849,7 @@ int md_adjoint(md_ctx *h, const double *g, const double *e, double *gtheta, void
 
 int md_time_pass(md_ctx *h, int32_t pass, int32_t reps, void *stream, double *avg_ms)
 {
-    if (!h || !avg_ms || reps < 1 || pass < MD_PASS_BUILD || pass > MD_PASS_FORCE_STEP)
+    if (!h || !avg_ms || reps < 1 || pass < MD_PASS_BUILD || pass > MD_PASS_PRESSURE)
         return MD_ERR_ARG;
     Ctx &c = h->c;
     if (!c.state_set) return MD_ERR_STATE;
@@ -779,6 +873,10 @@ int md_time_pass(md_ctx *h, int32_t pass, int32_t reps, void *stream, double *av
         case MD_PASS_DENSITY: launch_density(c, s); break;
         case MD_PASS_FORCE: launch_force(c, false, 1, s); break;
         case MD_PASS_FORCE_STEP: launch_force(c, false, c.tiled ? 2 : 1, s); break;
+        case MD_PASS_PRESSURE:
+            launch_force(c, true, 0, s);
+            launch_pressure_eval(c, s);
+            break;
         case MD_PASS_KICK_DRIFT: launch_kick_drift(c, s); break;
         }
     }

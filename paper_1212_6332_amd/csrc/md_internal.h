@@ -56,6 +56,7 @@ struct State {
     double *pk;                        // [N][4] packed x, y, z, F'(rho) for neighbour gathers
     int *id;                           // original index of each sorted slot
     double *rho, *Fp, *Femb, *eat;     // density, F'(rho), F(rho), per-atom energy
+    double *wat;                       // per-atom virial term sum_j [(F'_i + F'_j) rho' + V'] r
 };
 
 // Per-box geometry (device arrays of length B, box_of of length N).
@@ -105,6 +106,9 @@ void launch_embed(Ctx &c, hipStream_t s);
 // kick: 0 none, 1 half kick, 2 half kick and the next step's half kick and
 // drift into the other position buffer (tiled contexts only)
 void launch_force(Ctx &c, bool energy, int kick, hipStream_t s);
+void launch_pressure_eval(Ctx &c, hipStream_t s);  // after a force pass with energies
+void launch_baro_mu(Ctx &c, hipStream_t s);
+void launch_baro_box_scale(Ctx &c, hipStream_t s);
 void launch_kick_drift(Ctx &c, hipStream_t s);
 void launch_step_end(Ctx &c, hipStream_t s);
 void launch_scatter_scalar(Ctx &c, const double *src, double *dst, hipStream_t s);
@@ -184,6 +188,12 @@ struct Ctx {
 
     // host-side state machine
     bool state_set = false, list_valid = false, density_valid = false, forces_valid = false;
+
+    // pressure (eq. 6) and Berendsen barostat (eq. 5)
+    bool baro_on = false;              // md_step scales coordinates and boxes
+    bool baro_mu_valid = false;        // d_baro holds the scale factors of the next step
+    double baro_p0 = 0.0, baro_tau = 0.0, baro_beta = 0.0;
+    double *d_baro = nullptr;          // per box: mu | strain | rlist | pressure | virial | kinetic | virial sum
 
     // graph replay of md_step
     bool use_graph = true;

@@ -559,7 +559,7 @@ __global__ __launch_bounds__(kBlock) void k_force(int N, State st, Boxes bx, NLi
     double fpi = st.Fp[i];
     Row rw = row_of(nl, i);
     unsigned bad = 0;
-    double ax = 0.0, ay = 0.0, az = 0.0, ep = 0.0;
+    double ax = 0.0, ay = 0.0, az = 0.0, ep = 0.0, wv = 0.0;
     auto body = [&](double dx, double dy, double dz, double fpj) {
         double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
         if (r2 < pot.rc2) {
@@ -571,7 +571,10 @@ __global__ __launch_bounds__(kBlock) void k_force(int N, State st, Boxes bx, NLi
             ax = fma(coef, dx, ax);
             ay = fma(coef, dy, ay);
             az = fma(coef, dz, az);
-            if constexpr (ENERGY) ep += v;
+            if constexpr (ENERGY) {
+                ep += v;
+                wv = fma(coef, r2, wv);  // [(F'_i + F'_j) rho' + V'] r
+            }
         }
     };
     for_pairs<false, true>(nl.idx, i, N, 0, rw.np, pk, xi, yi, zi, L, invL, body);
@@ -579,7 +582,10 @@ __global__ __launch_bounds__(kBlock) void k_force(int N, State st, Boxes bx, NLi
     st.fx[i] = ax;
     st.fy[i] = ay;
     st.fz[i] = az;
-    if constexpr (ENERGY) st.eat[i] = fma(0.5, ep, st.Femb[i]);
+    if constexpr (ENERGY) {
+        st.eat[i] = fma(0.5, ep, st.Femb[i]);
+        st.wat[i] = wv;
+    }
     if constexpr (KICK) {
         st.vx[i] = fma(kick, ax, st.vx[i]);
         st.vy[i] = fma(kick, ay, st.vy[i]);
@@ -663,6 +669,8 @@ __global__ __launch_bounds__(kBlock) void k_chunk_sums(int what, State st, doubl
     for (int i = s + threadIdx.x; i < e; i += blockDim.x) {
         if (what == 0) {
             acc += st.eat[i];
+        } else if (what == 2) {
+            acc += st.wat[i];
         } else {
             double vx = st.vx[i], vy = st.vy[i], vz = st.vz[i];
             acc += half_m_over_k * fma(vz, vz, fma(vy, vy, vx * vx));
@@ -685,6 +693,101 @@ __global__ void k_box_sums(int B, const int *__restrict__ box_chunk, const doubl
     double s = 0.0;
     for (int c = box_chunk[b]; c < box_chunk[b + 1]; ++c) s += partial[c];
     out[b] = s;
+}
+
+// ---------------------------------------------------------------- pressure, barostat
+
+// Eq. (6) per box from the kinetic energy K and the per-atom virial sum S
+// (W = -S/2, the pair form of sum_i f_i . r_i): P = (2 K + W) / (3 V).
+// d_baro layout per box: mu | strain | rlist | pressure | virial | kinetic | virial sum.
+__global__ void k_pressure_eval(int B, const double *__restrict__ L, double *__restrict__ baro)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double w = -0.5 * baro[6 * B + b], k = baro[5 * B + b], l = L[b];
+    baro[4 * B + b] = w;
+    baro[3 * B + b] = (2.0 * k + w) / (3.0 * (l * l * l));
+}
+
+// Eq. (5): mu = [1 - beta (dt / tau) (P0 - P)]^(1/3) for the next step.
+__global__ void k_baro_mu(int B, double p0, double beta_dt_tau, double *__restrict__ baro)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    baro[b] = cbrt(1.0 - beta_dt_tau * (p0 - baro[3 * B + b]));
+}
+
+// Box update of a barostat step: L *= mu, the strain since the last build
+// s *= mu and the rebuild threshold ((r_list - rc) - |1 - s| r_list) / 2
+// (negative: rebuild at once).  A box that would shrink below its cell grid
+// keeps its size (mu = 1) and raises MD_FLAG_BOX_RANGE.  The rebuild request
+// of the kick-drift kernel is withdrawn: it is decided again on the scaled
+// coordinates.
+__global__ void k_baro_box(int B, double rc, double *__restrict__ boxd, const int *__restrict__ nc,
+                           double *__restrict__ baro, unsigned *flags)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b == 0) flags[1] = 0u;
+    if (b >= B) return;
+    double *L = boxd, *invL = boxd + B, *thr2 = boxd + 3 * B;
+    double mu = baro[b], rl = baro[2 * B + b], Ln = L[b] * mu;
+    if (!(Ln >= nc[b] * rl * (1.0 + 1e-12) && rl < 0.5 * Ln)) {
+        mu = 1.0;
+        Ln = L[b];
+        atomicOr(flags, (unsigned)MD_FLAG_BOX_RANGE);
+    }
+    baro[b] = mu;
+    L[b] = Ln;
+    invL[b] = 1.0 / Ln;
+    double st = baro[B + b] * mu;
+    baro[B + b] = st;
+    double half = 0.5 * ((rl - rc) - fabs(1.0 - st) * rl);
+    thr2[b] = half < 0.0 ? -1.0 : half * half;
+}
+
+// Scale coordinates and reference positions by their box's mu and decide the
+// rebuild on the scaled coordinates.
+template <bool PACK>
+__global__ __launch_bounds__(kBlock) void k_baro_scale(int N, State st, Boxes bx,
+                                                       const double *__restrict__ baro,
+                                                       unsigned *flags)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool need = false;
+    if (i < N) {
+        int b = bx.box_of[i];
+        double mu = baro[b];
+        double x = st.x[i] * mu, y = st.y[i] * mu, z = st.z[i] * mu;
+        double xr = st.xr[i] * mu, yr = st.yr[i] * mu, zr = st.zr[i] * mu;
+        st.x[i] = x;
+        st.y[i] = y;
+        st.z[i] = z;
+        st.xr[i] = xr;
+        st.yr[i] = yr;
+        st.zr[i] = zr;
+        if constexpr (PACK) {
+            reinterpret_cast<double2 *>(st.pk)[2 * (size_t)i] = make_double2(x, y);
+            st.pk[4 * (size_t)i + 2] = z;
+        }
+        double ddx = x - xr, ddy = y - yr, ddz = z - zr;
+        double d2 = fma(ddz, ddz, fma(ddy, ddy, ddx * ddx));
+        need = d2 > bx.thr2[b];
+    }
+    if (__any(need) && (threadIdx.x & 63) == 0 &&
+        __atomic_load_n(flags + 1, __ATOMIC_RELAXED) == 0u)
+        atomicOr(flags + 1, 1u);
+}
+
+// After a list build: no strain since the build, the plain half-skin test.
+__global__ void k_baro_rebuilt(const unsigned *gate, int B, double rc, double *__restrict__ boxd,
+                               double *__restrict__ baro)
+{
+    if (skip(gate)) return;
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double half = 0.5 * (baro[2 * B + b] - rc);
+    baro[B + b] = 1.0;
+    boxd[3 * B + b] = half * half;
 }
 
 // ---------------------------------------------------------------- neighbours out
@@ -793,6 +896,8 @@ void launch_build(Ctx &c, bool gated, hipStream_t s)
         launch_tile_nlist(c, gate, s);
     else
         k_nlist<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.st, c.bx, c.bd, c.nl, c.dev.flags);
+    if (c.baro_on)
+        k_baro_rebuilt<<<grid_for(c.B), kBlock, 0, s>>>(gate, c.B, c.pot.rc, c.d_boxd, c.d_baro);
     if (!gated) k_count_build<<<1, 1, 0, s>>>(c.dev.flags);
 }
 
@@ -802,7 +907,8 @@ void launch_density(Ctx &c, hipStream_t s)
         launch_tile_density(c, s);
         return;
     }
-    bool multi = c.B > 1;
+    // with the barostat the box lengths live on the device only
+    bool multi = c.B > 1 || c.baro_on;
     switch (c.pot.kind) {
     case MD_POT_FS: multi ? density_t<MD_POT_FS, true>(c, s) : density_t<MD_POT_FS, false>(c, s); break;
     case MD_POT_SMTB: multi ? density_t<MD_POT_SMTB, true>(c, s) : density_t<MD_POT_SMTB, false>(c, s); break;
@@ -827,7 +933,7 @@ void launch_force(Ctx &c, bool energy, int kick_mode, hipStream_t s)
         return;
     }
     bool kick = kick_mode > 0;  // fused drifts are captured for tiled contexts only
-    bool multi = c.B > 1;
+    bool multi = c.B > 1 || c.baro_on;
     switch (c.pot.kind) {
     case MD_POT_FS: multi ? force_t<MD_POT_FS, true>(c, energy, kick, s) : force_t<MD_POT_FS, false>(c, energy, kick, s); break;
     case MD_POT_SMTB: multi ? force_t<MD_POT_SMTB, true>(c, energy, kick, s) : force_t<MD_POT_SMTB, false>(c, energy, kick, s); break;
@@ -841,9 +947,10 @@ void launch_kick_drift(Ctx &c, hipStream_t s)
     double h = 0.5 * (c.box_rlist[0] - c.pot.rc);
     // the packed neighbour records feed only the per-atom kernels
     int g = grid_for(c.N), N = (int)c.N;
-    if (c.B > 1 && c.tiled)
+    bool multi = c.B > 1 || c.baro_on;
+    if (multi && c.tiled)
         k_kick_drift<true, false><<<g, kBlock, 0, s>>>(N, c.st, c.bx, k, c.dt, 0.0, c.dev.flags);
-    else if (c.B > 1)
+    else if (multi)
         k_kick_drift<true, true><<<g, kBlock, 0, s>>>(N, c.st, c.bx, k, c.dt, 0.0, c.dev.flags);
     else if (c.tiled)
         k_kick_drift<false, false><<<g, kBlock, 0, s>>>(N, c.st, c.bx, k, c.dt, h * h, c.dev.flags);
@@ -869,6 +976,29 @@ void launch_box_sums(Ctx &c, int what, double *out, hipStream_t s)
     const int *cs = c.d_chunks, *ce = c.d_chunks + c.n_chunks, *bc = c.d_chunks + 2 * c.n_chunks;
     k_chunk_sums<<<c.n_chunks, kBlock, 0, s>>>(what, c.st, 0.5 * c.mass / kKappa, cs, ce, c.d_partial);
     k_box_sums<<<grid_for(c.B), kBlock, 0, s>>>(c.B, bc, c.d_partial, out);
+}
+
+void launch_pressure_eval(Ctx &c, hipStream_t s)
+{
+    launch_box_sums(c, 1, c.d_baro + 5 * c.B, s);
+    launch_box_sums(c, 2, c.d_baro + 6 * c.B, s);
+    k_pressure_eval<<<grid_for(c.B), kBlock, 0, s>>>(c.B, c.d_boxd, c.d_baro);
+}
+
+void launch_baro_mu(Ctx &c, hipStream_t s)
+{
+    k_baro_mu<<<grid_for(c.B), kBlock, 0, s>>>(c.B, c.baro_p0, c.baro_beta * c.dt / c.baro_tau,
+                                              c.d_baro);
+}
+
+void launch_baro_box_scale(Ctx &c, hipStream_t s)
+{
+    k_baro_box<<<grid_for(c.B), kBlock, 0, s>>>(c.B, c.pot.rc, c.d_boxd, c.bx.nc, c.d_baro,
+                                               c.dev.flags);
+    if (c.tiled)
+        k_baro_scale<false><<<grid_for(c.N), kBlock, 0, s>>>((int)c.N, c.st, c.bx, c.d_baro, c.dev.flags);
+    else
+        k_baro_scale<true><<<grid_for(c.N), kBlock, 0, s>>>((int)c.N, c.st, c.bx, c.d_baro, c.dev.flags);
 }
 
 void launch_get_neighbors(Ctx &c, int32_t *counts, int32_t *ids, int32_t max_cols, hipStream_t s)

@@ -576,7 +576,7 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
                 ry = st.yr[i];
                 rz = st.zr[i];
             }
-            double ax = 0.0, ay = 0.0, az = 0.0, ep = 0.0;
+            double ax = 0.0, ay = 0.0, az = 0.0, ep = 0.0, wv = 0.0;
             auto body = [&](double dx, double dy, double dz, double fpj) {
                 double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
                 if (r2 < pot.rc2) {
@@ -588,6 +588,7 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
                         pair_terms<KIND>(pot, r2 * inv_r, dfr, v, dv, bad);
                         coef = fma(fpi + fpj, dfr, dv) * inv_r;
                         ep += v;
+                        wv = fma(coef, r2, wv);  // virial term [(F'_i + F'_j) rho' + V'] r
                     } else {
                         coef = pair_coef<KIND>(pot, r2 * inv_r, fpi + fpj, bad) * inv_r;
                     }
@@ -606,7 +607,10 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
             st.fx[i] = ax;
             st.fy[i] = ay;
             st.fz[i] = az;
-            if constexpr (ENERGY) st.eat[i] = fma(0.5, ep, st.Femb[i]);
+            if constexpr (ENERGY) {
+                st.eat[i] = fma(0.5, ep, st.Femb[i]);
+                st.wat[i] = wv;
+            }
             if constexpr (MODE >= 1) {
                 double vx = fma(kick, ax, v0x);
                 double vy = fma(kick, ay, v0y);

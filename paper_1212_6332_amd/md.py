@@ -19,10 +19,12 @@ LIB_PATH = os.path.join(_HERE, "libmd.so")
 MD_OK = 0
 MD_ERR_ARG, MD_ERR_BOX, MD_ERR_NLIST_OVERFLOW, MD_ERR_TABLE_RANGE = -1, -2, -3, -4
 MD_ERR_NONFINITE, MD_ERR_DEVICE, MD_ERR_STATE, MD_ERR_NOMEM = -5, -6, -7, -8
-MD_FLAG_NLIST_OVERFLOW, MD_FLAG_TABLE_RANGE, MD_FLAG_NONFINITE, MD_FLAG_TILE_OVERFLOW = 1, 2, 4, 8
+(MD_FLAG_NLIST_OVERFLOW, MD_FLAG_TABLE_RANGE, MD_FLAG_NONFINITE, MD_FLAG_TILE_OVERFLOW,
+ MD_FLAG_BOX_RANGE) = 1, 2, 4, 8, 16
 MD_POT_FS, MD_POT_SMTB, MD_POT_SPLINE, MD_POT_BSPLINE = 1, 2, 3, 4
 MD_OPT_BATCHED, MD_OPT_BATCH_BLOCK, MD_OPT_USE_GRAPH, MD_OPT_GRAPH_STEPS, MD_OPT_TILED = 1, 2, 3, 4, 5
-MD_PASS_BUILD, MD_PASS_DENSITY, MD_PASS_FORCE, MD_PASS_KICK_DRIFT, MD_PASS_FORCE_STEP = 0, 1, 2, 3, 4
+(MD_PASS_BUILD, MD_PASS_DENSITY, MD_PASS_FORCE, MD_PASS_KICK_DRIFT, MD_PASS_FORCE_STEP,
+ MD_PASS_PRESSURE) = 0, 1, 2, 3, 4, 5
 
 
 class MDError(RuntimeError):
@@ -67,6 +69,9 @@ _SIGS = {
     "md_get_option": ([C.c_void_p, C.c_int32, C.POINTER(C.c_int64)], C.c_int),
     "md_time_pass": ([C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_double)],
                      C.c_int),
+    "md_pressure": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "md_set_barostat": ([C.c_void_p, C.c_double, C.c_double, C.c_double], C.c_int),
+    "md_get_box": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
 }
 
 
@@ -252,6 +257,24 @@ class System:
         K = int(self._pot.s.n_tab[0])
         out = self._f64(3 * K)
         _check(lib().md_adjoint(self._h, _ptr(g), _ptr(e), _ptr(out), _stream()), "md_adjoint")
+        return out
+
+    def pressure(self):
+        """Per-box pressure of eq. (6) (eV/Angstrom^3) and pair virial W (eV)."""
+        p = torch.empty(self.n_boxes, dtype=torch.float64, device=self.device)
+        w = torch.empty(self.n_boxes, dtype=torch.float64, device=self.device)
+        _check(lib().md_pressure(self._h, _ptr(p), _ptr(w), _stream()), "md_pressure")
+        return p, w
+
+    def set_barostat(self, p0, tau, beta):
+        """Berendsen barostat of eq. (5) in md_step; tau <= 0 switches it off."""
+        _check(lib().md_set_barostat(self._h, float(p0), float(tau), float(beta)),
+               "md_set_barostat")
+
+    def box(self):
+        """Current box edges (numpy, length B)."""
+        out = np.zeros(self.n_boxes)
+        _check(lib().md_get_box(self._h, out.ctypes.data_as(C.c_void_p), _stream()), "md_get_box")
         return out
 
     def time_pass(self, which, reps):
