@@ -225,6 +225,31 @@ def bench_adjoint(evals=50, steps=100):
             "plain_step_atom_steps_per_s": wl.n_atoms * steps / wall}
 
 
+def bench_pressure(steps=100, warmup=10, reps=10):
+    """The 4M-atom box with the pressure of eq. (6): force pass with energies
+    and the pair virial (plus the per-box reductions) against the plain force
+    pass, and steps with the Berendsen barostat of eq. (5) switched on."""
+    from paper_1212_6332_amd import md, workloads as W
+
+    wl = W.fcc4m()
+    S = md.System.from_workload(wl)
+    S.set_state(wl.pos, wl.vel)
+    p0, _ = S.pressure()
+    ms_plain = S.time_pass(md.MD_PASS_FORCE, reps)
+    ms_virial = S.time_pass(md.MD_PASS_PRESSURE, reps)
+    S.set_barostat(0.0, 1000.0, 1.0)
+    wall, _, reb = timed_steps(S, steps, warmup)
+    L = float(S.box()[0])
+    p1, _ = S.pressure()
+    S.close()
+    return {"workload": "fcc4m with the Berendsen barostat (P0 = 0, tau = 1000 fs, beta = 1 A^3/eV)",
+            "force_pass_ms": ms_plain, "force_pass_with_virial_ms": ms_virial,
+            "barostat_atom_steps_per_s": wl.n_atoms * steps / wall,
+            "barostat_ms_per_step": wall / steps * 1e3, "rebuilds": int(reb),
+            "pressure_start_eV_A3": float(p0[0]), "pressure_end_eV_A3": float(p1[0]),
+            "box_start_A": float(wl.box_len[0, 0]), "box_end_A": L}
+
+
 def bench_c2(steps=1000, warmup=20):
     from paper_1212_6332_amd import md, workloads as W
 
@@ -238,10 +263,10 @@ def bench_c2(steps=1000, warmup=20):
             "rebuilds": int(reb), "steps": steps}
 
 
-def cpu_baseline(ncell=50, steps=100):
+def cpu_baseline(ncell=50, steps=120):
     """The CPU oracle on a bounded sample: the same material (FCC SMTB, a =
     3.615, 300 K, sigma 0.05) in a 50^3-cell box (500,000 atoms, 1/8 of the
-    full system), 100 velocity-Verlet steps (about 10-20 s on the host's
+    full system), 120 velocity-Verlet steps (about 10-20 s on the host's
     cores); list build and initial forces timed separately and excluded."""
     import oracle as O
     from paper_1212_6332_amd import workloads as W
@@ -265,9 +290,9 @@ def cpu_baseline(ncell=50, steps=100):
 
 
 def pmc_probe(reps):
-    """Short run for hardware-counter collection: force and density passes of
-    the 4M-atom workload, then one plain 2 GiB device copy used to scale the
-    counters."""
+    """Short run for hardware-counter collection: force (plain and as run in
+    the step), density and list-build passes of the 4M-atom workload, then one
+    plain 2 GiB device copy used to scale the counters."""
     import torch
     from paper_1212_6332_amd import md, workloads as W
 
@@ -279,7 +304,9 @@ def pmc_probe(reps):
     print(json.dumps({"mean_list_len": float(counts.double().mean()), "n_atoms": wl.n_atoms,
                       "force_bytes": force_pass_bytes(wl.n_atoms, float(counts.double().mean()))}))
     S.time_pass(md.MD_PASS_FORCE, reps)
+    S.time_pass(md.MD_PASS_FORCE_STEP, reps)
     S.time_pass(md.MD_PASS_DENSITY, reps)
+    S.time_pass(md.MD_PASS_BUILD, reps)
     torch.cuda.synchronize()
     src = torch.ones(2 ** 28, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
@@ -327,6 +354,7 @@ def main():
         out["batched"] = bench_batched()
         out["adjoint"] = bench_adjoint()
         out["bcc128k"] = bench_c2()
+        out["pressure"] = bench_pressure()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
