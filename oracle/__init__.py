@@ -85,8 +85,11 @@ def lib():
         L.orc_virial_direct.restype = dbl
         L.orc_vv_baro.argtypes = [i64, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p,
                                   C.POINTER(dbl), P, dbl, dbl, dbl, i32, i32, dbl, dbl, dbl,
-                                  C.c_void_p]
+                                  dbl, dbl, C.c_void_p]
         L.orc_vv_baro.restype = i32
+        L.orc_vv_thermo.argtypes = [i64, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p, dbl, P, dbl,
+                                    dbl, dbl, i32, i32, dbl, dbl, C.c_void_p, C.c_void_p]
+        L.orc_vv_thermo.restype = i32
         _lib = L
     return _lib
 
@@ -280,8 +283,10 @@ def pressure(pos, vel, L, pot: Pot, mass, skin=0.3):
     return (2.0 * kinetic(vel, mass) + virial(pos, L, pot, skin)) / (3.0 * float(L) ** 3)
 
 
-def vv_baro(pos, vel, L, pot: Pot, mass, dt, skin, nsteps, p0, tau, beta, maxn=256):
-    """Velocity Verlet with the Berendsen barostat of eq. (5).
+def vv_baro(pos, vel, L, pot: Pot, mass, dt, skin, nsteps, p0, tau, beta, maxn=256,
+            te=0.0, tau_t=0.0):
+    """Velocity Verlet with the Berendsen barostat of eq. (5), and the
+    electron-gas friction of eq. (4) when tau_t > 0.
     Returns (pos, vel, L, pressures[nsteps + 1], rebuilds)."""
     x, y, z = _xyz(pos)
     vx, vy, vz = _xyz(vel)
@@ -289,10 +294,26 @@ def vv_baro(pos, vel, L, pot: Pot, mass, dt, skin, nsteps, p0, tau, beta, maxn=2
     pr = np.zeros(nsteps + 1)
     nreb = lib().orc_vv_baro(x.size, x, y, z, vx, vy, vz, C.byref(Lc), pot.ref, float(mass),
                              float(dt), float(skin), int(nsteps), int(maxn), float(p0),
-                             float(tau), float(beta), pr.ctypes.data)
+                             float(tau), float(beta), float(te), float(tau_t),
+                             pr.ctypes.data)
     if nreb < 0:
         raise ValueError("neighbour row overflow in orc_vv_baro")
     return (np.stack([x, y, z], axis=1), np.stack([vx, vy, vz], axis=1), Lc.value, pr, nreb)
+
+
+def vv_thermo(pos, vel, L, pot: Pot, mass, dt, skin, nsteps, te, tau, maxn=256):
+    """Velocity Verlet with the electron-gas friction of eq. (4) (tau <= 0: none).
+    Returns (pos, vel, epot, ekin, rebuilds)."""
+    x, y, z = _xyz(pos)
+    vx, vy, vz = _xyz(vel)
+    ep = np.zeros(nsteps + 1)
+    ek = np.zeros(nsteps + 1)
+    nreb = lib().orc_vv_thermo(x.size, x, y, z, vx, vy, vz, float(L), pot.ref, float(mass),
+                               float(dt), float(skin), int(nsteps), int(maxn), float(te),
+                               float(tau), ep.ctypes.data, ek.ctypes.data)
+    if nreb < 0:
+        raise ValueError("neighbour row overflow in orc_vv_thermo")
+    return (np.stack([x, y, z], axis=1), np.stack([vx, vy, vz], axis=1), ep, ek, nreb)
 
 
 def threads() -> int:

@@ -723,6 +723,109 @@ int orc_vv(int64_t n, double *x, double *y, double *z, double *vx, double *vy, d
     return bad ? -1 : rebuilds;
 }
 
+/* ---------------------------------------------------------------- thermostat */
+
+/*
+ * Eq. (4): each atom exchanges energy with an electron gas held at T_e through
+ * the friction -(m / tau) ((T_i - T_e) / T_i) v_i (the printed equation leaves
+ * out the mass that makes the term a force), T_i = m v_i^2 / (3 k_B) being
+ * the instantaneous temperature of atom i.  On its own the friction keeps the
+ * direction of v_i and gives d(v^2)/dt = -(2 / tau) (v^2 - v_e^2) with
+ * v_e^2 = 3 k_B T_e / m, so over a time t
+ *     v^2(t) = v_e^2 + (v^2(0) - v_e^2) exp(-2 t / tau).
+ * Velocity Verlet takes this flow exactly over each half step, outside the
+ * force half kicks (friction, kick, drift, force, kick, friction), which is
+ * stable for any tau and any T_i.  An atom at rest has no direction and is
+ * left at rest.
+ */
+static const double ORC_KB = 8.617333262e-5; /* eV/K */
+
+typedef struct {
+    int on;
+    double e;  /* exp(-dt / tau): the flow over half a step */
+    double ve2; /* v_e^2 in the velocity units (Angstrom/fs)^2 */
+} orc_thermo;
+
+static orc_thermo thermo_of(double te, double tau, double dt, double mass)
+{
+    orc_thermo t = {0, 1.0, 0.0};
+    if (tau > 0.0) {
+        t.on = 1;
+        t.e = exp(-dt / tau);
+        t.ve2 = 3.0 * ORC_KB * te * ORC_KAPPA / mass;
+    }
+    return t;
+}
+
+static void friction_flow(orc_md *s, const orc_thermo *t)
+{
+    if (!t->on) return;
+    for (int64_t i = 0; i < s->n; ++i) {
+        double v2 = s->vx[i] * s->vx[i] + s->vy[i] * s->vy[i] + s->vz[i] * s->vz[i];
+        if (v2 > 0.0) {
+            double g = sqrt(t->e * v2 + (1.0 - t->e) * t->ve2) / sqrt(v2);
+            s->vx[i] *= g;
+            s->vy[i] *= g;
+            s->vz[i] *= g;
+        }
+    }
+}
+
+/* Velocity Verlet with the electron-gas friction of eq. (4) (tau <= 0: none,
+ * which is orc_vv).  Arguments and results as orc_vv. */
+int orc_vv_thermo(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
+                  double L, const orc_pot *p, double mass, double dt, double skin, int nsteps,
+                  int maxn, double te, double tau, double *epot, double *ekin)
+{
+    orc_md s = {n, x, y, z, vx, vy, vz, L, mass, dt, skin, p, maxn};
+    orc_thermo th = thermo_of(te, tau, dt, mass);
+    double rlist = orc_rlist(p->rc, skin, L);
+    double half_skin = 0.5 * (rlist - p->rc);
+    size_t nb = sizeof(double) * (n > 0 ? n : 1);
+    int32_t *count = (int32_t *)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+    int32_t *ids = (int32_t *)malloc(sizeof(int32_t) * (n > 0 ? n : 1) * maxn);
+    double *xr = malloc(nb), *yr = malloc(nb), *zr = malloc(nb);
+    double *rho = malloc(nb), *F = malloc(nb), *Fp = malloc(nb);
+    double *fx = malloc(nb), *fy = malloc(nb), *fz = malloc(nb), *e = malloc(nb);
+    int rebuilds = 0, bad = 0;
+    bad |= md_rebuild(&s, rlist, count, ids, xr, yr, zr);
+    double E = md_forces(&s, count, ids, rho, F, Fp, fx, fy, fz, e);
+    if (epot) epot[0] = E;
+    if (ekin) ekin[0] = md_kinetic(&s);
+    double c = 0.5 * dt * ORC_KAPPA / mass;
+    for (int step = 1; step <= nsteps; ++step) {
+        friction_flow(&s, &th);
+        double worst = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            vx[i] += c * fx[i];
+            vy[i] += c * fy[i];
+            vz[i] += c * fz[i];
+            x[i] += dt * vx[i];
+            y[i] += dt * vy[i];
+            z[i] += dt * vz[i];
+            double ddx = x[i] - xr[i], ddy = y[i] - yr[i], ddz = z[i] - zr[i];
+            double d2 = ddx * ddx + ddy * ddy + ddz * ddz;
+            if (d2 > worst) worst = d2;
+        }
+        if (worst > half_skin * half_skin) {
+            bad |= md_rebuild(&s, rlist, count, ids, xr, yr, zr);
+            ++rebuilds;
+        }
+        E = md_forces(&s, count, ids, rho, F, Fp, fx, fy, fz, e);
+        for (int64_t i = 0; i < n; ++i) {
+            vx[i] += c * fx[i];
+            vy[i] += c * fy[i];
+            vz[i] += c * fz[i];
+        }
+        friction_flow(&s, &th);
+        if (epot) epot[step] = E;
+        if (ekin) ekin[step] = md_kinetic(&s);
+    }
+    free(count); free(ids); free(xr); free(yr); free(zr);
+    free(rho); free(F); free(Fp); free(fx); free(fy); free(fz); free(e);
+    return bad ? -1 : rebuilds;
+}
+
 /* ------------------------------------------------------------------ pressure */
 
 /*
@@ -806,15 +909,20 @@ double orc_virial_direct(int64_t n, const double *x, const double *y, const doub
  * when 2 max|x - x_ref| + |1 - s| r_list reaches r_list - rc, with s the
  * product of the scale factors since the last build (pair separations that
  * were >= r_list at the build are then still >= rc).
+ * With tau_t > 0 the friction of eq. (4) is applied as in orc_vv_thermo (its
+ * flow before the first half kick and after the second, the pressure taken
+ * after it).
  * L (in/out) is the box edge; press (length nsteps+1, may be NULL) receives
  * the pressures.  Returns the number of rebuilds, or -1 on row overflow.
  */
 int orc_vv_baro(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
                 double *Lio, const orc_pot *p, double mass, double dt, double skin, int nsteps,
-                int maxn, double p0, double tau, double beta, double *press)
+                int maxn, double p0, double tau, double beta, double te, double tau_t,
+                double *press)
 {
     double L = *Lio;
     orc_md s = {n, x, y, z, vx, vy, vz, L, mass, dt, skin, p, maxn};
+    orc_thermo th = thermo_of(te, tau_t, dt, mass);
     double rlist = orc_rlist(p->rc, skin, L);
     size_t nb = sizeof(double) * (n > 0 ? n : 1);
     int32_t *count = (int32_t *)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
@@ -831,6 +939,7 @@ int orc_vv_baro(int64_t n, double *x, double *y, double *z, double *vx, double *
     double c = 0.5 * dt * ORC_KAPPA / mass, strain = 1.0;
     for (int step = 1; step <= nsteps; ++step) {
         double mu = cbrt(1.0 - beta * (dt / tau) * (p0 - P));
+        friction_flow(&s, &th);
         for (int64_t i = 0; i < n; ++i) {
             vx[i] += c * fx[i];
             vy[i] += c * fy[i];
@@ -865,6 +974,7 @@ int orc_vv_baro(int64_t n, double *x, double *y, double *z, double *vx, double *
             vy[i] += c * fy[i];
             vz[i] += c * fz[i];
         }
+        friction_flow(&s, &th);
         W = orc_virial(n, x, y, z, s.L, p, count, ids, maxn, Fp);
         P = (2.0 * md_kinetic(&s) + W) / (3.0 * s.L * s.L * s.L);
         if (press) press[step] = P;
