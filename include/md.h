@@ -218,6 +218,19 @@ int md_pressure(md_ctx *ctx, double *p_box, double *w_box, void *stream);
  * raises MD_FLAG_BOX_RANGE. */
 int md_set_barostat(md_ctx *ctx, double p0, double tau, double beta);
 
+/* Electron-gas thermostat, eq. (4) of Section 2, applied by md_step: each
+ * atom feels the friction -(m / tau_t) ((T_i - T_e) / T_i) v_i, with T_i =
+ * m v_i^2 / (3 k_B) its instantaneous temperature and T_e (K) the electron
+ * temperature; tau_t (fs) is the coupling time.  The friction alone keeps the
+ * direction of v_i and relaxes v_i^2 exponentially to 3 k_B T_e / m at rate
+ * 2 / tau_t; md_step applies that exact flow over half a step before the
+ * first half kick and after the second one of every step (an atom at rest
+ * stays at rest).  Every box shares T_e and tau_t.  tau_t > 0 switches the
+ * thermostat on (T_e >= 0 and finite required, else MD_ERR_ARG); tau_t <= 0
+ * switches it off; a NaN or infinite tau_t is MD_ERR_ARG.  Works with the
+ * barostat (the pressure then includes the kinetic term after the flow). */
+int md_set_thermostat(md_ctx *ctx, double t_e, double tau_t);
+
 /* Current box edges (host box_len[B]; synchronises stream). */
 int md_get_box(md_ctx *ctx, double *box_len, void *stream);
 

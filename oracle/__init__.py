@@ -301,7 +301,7 @@ def vv_baro(pos, vel, L, pot: Pot, mass, dt, skin, nsteps, p0, tau, beta, maxn=2
     return (np.stack([x, y, z], axis=1), np.stack([vx, vy, vz], axis=1), Lc.value, pr, nreb)
 
 
-def vv_thermo(pos, vel, L, pot: Pot, mass, dt, skin, nsteps, te, tau, maxn=256):
+def vv_thermo(pos, vel, L, pot: Pot, mass, dt, skin, nsteps, te, tau, maxn=256, energies=True):
     """Velocity Verlet with the electron-gas friction of eq. (4) (tau <= 0: none).
     Returns (pos, vel, epot, ekin, rebuilds)."""
     x, y, z = _xyz(pos)
@@ -310,7 +310,8 @@ def vv_thermo(pos, vel, L, pot: Pot, mass, dt, skin, nsteps, te, tau, maxn=256):
     ek = np.zeros(nsteps + 1)
     nreb = lib().orc_vv_thermo(x.size, x, y, z, vx, vy, vz, float(L), pot.ref, float(mass),
                                float(dt), float(skin), int(nsteps), int(maxn), float(te),
-                               float(tau), ep.ctypes.data, ek.ctypes.data)
+                               float(tau), ep.ctypes.data if energies else None,
+                               ek.ctypes.data if energies else None)
     if nreb < 0:
         raise ValueError("neighbour row overflow in orc_vv_thermo")
     return (np.stack([x, y, z], axis=1), np.stack([vx, vy, vz], axis=1), ep, ek, nreb)

@@ -758,6 +758,29 @@ int md_set_barostat(md_ctx *h, double p0, double tau, double beta)
     return MD_OK;
 }
 
+int md_set_thermostat(md_ctx *h, double t_e, double tau_t)
+{
+    if (!h) return MD_ERR_ARG;
+    Ctx &c = h->c;
+    if (std::isnan(tau_t) || std::isinf(tau_t)) return MD_ERR_ARG;
+    if (tau_t > 0.0) {
+        if (!(t_e >= 0.0) || !std::isfinite(t_e)) return MD_ERR_ARG;
+        // v_e^2 = 3 k_B T_e / m in (Angstrom/fs)^2
+        const double kb = 8.617333262e-5;
+        const double kappa = 1.602176634e-19 / 1.66053906660e-27 * 1e-10;
+        double e = std::exp(-c.dt / tau_t);
+        double ve2 = 3.0 * kb * t_e * kappa / c.mass;
+        c.thermo = Thermo{e, (1.0 - e) * ve2, 1};
+        c.thermo_te = t_e;
+        c.thermo_tau = tau_t;
+    } else {
+        c.thermo = Thermo{1.0, 0.0, 0};
+        c.thermo_te = c.thermo_tau = 0.0;
+    }
+    graph_reset(c);
+    return MD_OK;
+}
+
 int md_get_box(md_ctx *h, double *box_len, void *stream)
 {
     if (!h || !box_len) return MD_ERR_ARG;

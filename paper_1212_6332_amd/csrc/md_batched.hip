@@ -44,6 +44,7 @@ struct BArgs {
     int mn;
     Pot pot;
     double kick, dt;
+    Thermo th;        // friction of eq. (4)
     int nsteps;
     int mode;         // bit 0: rebuild every box first; bit 1: compute forces first
     unsigned *flags;
@@ -318,9 +319,13 @@ __global__ __launch_bounds__(T) void k_batched(BArgs a)
                 fy[i] = ay;
                 fz[i] = az;
                 if (kick) {
-                    vx[i] = fma(a.kick, ax, vx[i]);
-                    vy[i] = fma(a.kick, ay, vy[i]);
-                    vz[i] = fma(a.kick, az, vz[i]);
+                    double ux = fma(a.kick, ax, vx[i]);
+                    double uy = fma(a.kick, ay, vy[i]);
+                    double uz = fma(a.kick, az, vz[i]);
+                    if (a.th.on) friction_flow(a.th, ux, uy, uz);
+                    vx[i] = ux;
+                    vy[i] = uy;
+                    vz[i] = uz;
                 }
             }
             __syncthreads();
@@ -334,9 +339,11 @@ __global__ __launch_bounds__(T) void k_batched(BArgs a)
         for (int s = 0; s < a.nsteps; ++s) {
             unsigned *flag = &s_flag[s & 1];
             for (int i = tid; i < n; i += T) {
-                double ux = fma(a.kick, fx[i], vx[i]);
-                double uy = fma(a.kick, fy[i], vy[i]);
-                double uz = fma(a.kick, fz[i], vz[i]);
+                double ux = vx[i], uy = vy[i], uz = vz[i];
+                if (a.th.on) friction_flow(a.th, ux, uy, uz);
+                ux = fma(a.kick, fx[i], ux);
+                uy = fma(a.kick, fy[i], uy);
+                uz = fma(a.kick, fz[i], uz);
                 vx[i] = ux;
                 vy[i] = uy;
                 vz[i] = uz;
@@ -523,6 +530,7 @@ void launch_batched_steps(Ctx &c, int nsteps, hipStream_t s)
     a.pot = c.pot;
     a.kick = 0.5 * c.dt * kKappa / c.mass;
     a.dt = c.dt;
+    a.th = c.thermo;
     a.flags = c.dev.flags;
     a.nmax = b.nmax;
     int mode = (b.list_valid ? 0 : 1) | (c.forces_valid ? 0 : 2);

@@ -49,6 +49,28 @@ struct Pot {
     Table tab[3];                      // V(r), rho(r), F(rho)
 };
 
+// Electron-gas friction of eq. (4) as the kick kernels see it: over half a
+// step v^2 -> e v^2 + a along the direction of v, e = exp(-dt / tau_T),
+// a = (1 - e) 3 k_B T_e / m in (Angstrom/fs)^2.
+struct Thermo {
+    double e, a;
+    int on;
+};
+
+// The friction's exact flow over half a step: with T_i = m v^2 / (3 k_B),
+// eq. (4) alone gives d(v^2)/dt = -(2 / tau_T) (v^2 - 3 k_B T_e / m) and keeps
+// the direction of v.  An atom at rest has no direction and stays at rest.
+__device__ __forceinline__ void friction_flow(const Thermo &th, double &vx, double &vy, double &vz)
+{
+    double v2 = fma(vz, vz, fma(vy, vy, vx * vx));
+    if (v2 > 0.0) {
+        double g = sqrt(fma(th.e, v2, th.a)) / sqrt(v2);
+        vx *= g;
+        vy *= g;
+        vz *= g;
+    }
+}
+
 // Atom state in sorted (cell) order, structure of arrays.
 struct State {
     double *x, *y, *z, *vx, *vy, *vz, *fx, *fy, *fz, *xr, *yr, *zr;
@@ -194,6 +216,10 @@ struct Ctx {
     bool baro_mu_valid = false;        // d_baro holds the scale factors of the next step
     double baro_p0 = 0.0, baro_tau = 0.0, baro_beta = 0.0;
     double *d_baro = nullptr;          // per box: mu | strain | rlist | pressure | virial | kinetic | virial sum
+
+    // electron-gas thermostat (eq. 4)
+    Thermo thermo{1.0, 0.0, 0};
+    double thermo_te = 0.0, thermo_tau = 0.0;
 
     // graph replay of md_step
     bool use_graph = true;

@@ -544,11 +544,12 @@ __global__ void k_embed(int N, State st, Pot pot, unsigned *flags)
 }
 
 // Force pass (eq. 3) gathered per atom, optionally fused with the second
-// half kick of velocity Verlet.
+// half kick of velocity Verlet (and after it the half-step friction flow of
+// eq. (4)).
 template <int KIND, bool MULTI, bool ENERGY, bool KICK>
 __global__ __launch_bounds__(kBlock) void k_force(int N, State st, Boxes bx, NList nl, Pot pot,
                                                   double L1, double invL1, double kick,
-                                                  unsigned *flags)
+                                                  Thermo th, unsigned *flags)
 {
     int i = atom_index();
     if (i >= N) return;
@@ -587,26 +588,33 @@ __global__ __launch_bounds__(kBlock) void k_force(int N, State st, Boxes bx, NLi
         st.wat[i] = wv;
     }
     if constexpr (KICK) {
-        st.vx[i] = fma(kick, ax, st.vx[i]);
-        st.vy[i] = fma(kick, ay, st.vy[i]);
-        st.vz[i] = fma(kick, az, st.vz[i]);
+        double vx = fma(kick, ax, st.vx[i]);
+        double vy = fma(kick, ay, st.vy[i]);
+        double vz = fma(kick, az, st.vz[i]);
+        if (th.on) friction_flow(th, vx, vy, vz);
+        st.vx[i] = vx;
+        st.vy[i] = vy;
+        st.vz[i] = vz;
     }
     raise_flags(flags, bad);
 }
 
-// First half of a velocity-Verlet step: v += (dt/2) a; x += dt v; request a
-// list rebuild when an atom has moved more than half the skin since the last
-// build.
+// First half of a velocity-Verlet step: the half-step friction flow of
+// eq. (4) when the thermostat is on, v += (dt/2) a; x += dt v; request a list
+// rebuild when an atom has moved more than half the skin since the last build.
 template <bool MULTI, bool PACK>
 __global__ __launch_bounds__(kBlock) void k_kick_drift(int N, State st, Boxes bx, double kick,
-                                                       double dt, double thr2_1, unsigned *flags)
+                                                       double dt, double thr2_1, Thermo th,
+                                                       unsigned *flags)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     bool need = false, bad = false;
     if (i < N) {
-        double vx = fma(kick, st.fx[i], st.vx[i]);
-        double vy = fma(kick, st.fy[i], st.vy[i]);
-        double vz = fma(kick, st.fz[i], st.vz[i]);
+        double vx = st.vx[i], vy = st.vy[i], vz = st.vz[i];
+        if (th.on) friction_flow(th, vx, vy, vz);
+        vx = fma(kick, st.fx[i], vx);
+        vy = fma(kick, st.fy[i], vy);
+        vz = fma(kick, st.fz[i], vz);
         double x = fma(dt, vx, st.x[i]);
         double y = fma(dt, vy, st.y[i]);
         double z = fma(dt, vz, st.z[i]);
@@ -843,13 +851,13 @@ void force_t(Ctx &c, bool energy, bool kick, hipStream_t s)
     int g = grid_for(c.N);
     int N = (int)c.N;
     if (energy && kick)
-        k_force<KIND, MULTI, true, true><<<g, kBlock, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.dev.flags);
+        k_force<KIND, MULTI, true, true><<<g, kBlock, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.thermo, c.dev.flags);
     else if (energy)
-        k_force<KIND, MULTI, true, false><<<g, kBlock, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.dev.flags);
+        k_force<KIND, MULTI, true, false><<<g, kBlock, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.thermo, c.dev.flags);
     else if (kick)
-        k_force<KIND, MULTI, false, true><<<g, kBlock, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.dev.flags);
+        k_force<KIND, MULTI, false, true><<<g, kBlock, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.thermo, c.dev.flags);
     else
-        k_force<KIND, MULTI, false, false><<<g, kBlock, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.dev.flags);
+        k_force<KIND, MULTI, false, false><<<g, kBlock, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.thermo, c.dev.flags);
 }
 
 }  // namespace
@@ -949,13 +957,13 @@ void launch_kick_drift(Ctx &c, hipStream_t s)
     int g = grid_for(c.N), N = (int)c.N;
     bool multi = c.B > 1 || c.baro_on;
     if (multi && c.tiled)
-        k_kick_drift<true, false><<<g, kBlock, 0, s>>>(N, c.st, c.bx, k, c.dt, 0.0, c.dev.flags);
+        k_kick_drift<true, false><<<g, kBlock, 0, s>>>(N, c.st, c.bx, k, c.dt, 0.0, c.thermo, c.dev.flags);
     else if (multi)
-        k_kick_drift<true, true><<<g, kBlock, 0, s>>>(N, c.st, c.bx, k, c.dt, 0.0, c.dev.flags);
+        k_kick_drift<true, true><<<g, kBlock, 0, s>>>(N, c.st, c.bx, k, c.dt, 0.0, c.thermo, c.dev.flags);
     else if (c.tiled)
-        k_kick_drift<false, false><<<g, kBlock, 0, s>>>(N, c.st, c.bx, k, c.dt, h * h, c.dev.flags);
+        k_kick_drift<false, false><<<g, kBlock, 0, s>>>(N, c.st, c.bx, k, c.dt, h * h, c.thermo, c.dev.flags);
     else
-        k_kick_drift<false, true><<<g, kBlock, 0, s>>>(N, c.st, c.bx, k, c.dt, h * h, c.dev.flags);
+        k_kick_drift<false, true><<<g, kBlock, 0, s>>>(N, c.st, c.bx, k, c.dt, h * h, c.thermo, c.dev.flags);
 }
 
 void launch_step_end(Ctx &c, hipStream_t s) { k_step_end<<<1, 1, 0, s>>>(c.dev.flags); }

@@ -542,7 +542,7 @@ __global__ __launch_bounds__(kT) void k_tile_density(int N, int G, State st, Box
 template <int KIND, bool ENERGY, int MODE>
 __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes bx, Build bd,
                                                    NList nl, Pot pot_arg, int hmax, double kick,
-                                                   double dt, unsigned *flags)
+                                                   double dt, Thermo th, unsigned *flags)
 {
     extern __shared__ __attribute__((aligned(256))) double rec[];
     const Pot pot = pinned(pot_arg);
@@ -615,7 +615,9 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
                 double vx = fma(kick, ax, v0x);
                 double vy = fma(kick, ay, v0y);
                 double vz = fma(kick, az, v0z);
+                if (th.on) friction_flow(th, vx, vy, vz);
                 if constexpr (MODE == 2) {
+                    if (th.on) friction_flow(th, vx, vy, vz);
                     vx = fma(kick, ax, vx);
                     vy = fma(kick, ay, vy);
                     vz = fma(kick, az, vz);
@@ -677,7 +679,7 @@ void force_launch(Ctx &c, bool energy, int mode, double k, hipStream_t s)
     size_t lds = c.tile_lds;
     double dt = c.dt;
 #define MDK_FORCE(E, M) \
-    k_tile_force<KIND, E, M><<<G, kT, lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, k, dt, c.dev.flags)
+    k_tile_force<KIND, E, M><<<G, kT, lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, k, dt, c.thermo, c.dev.flags)
     if (energy && mode > 0)
         MDK_FORCE(true, 1);
     else if (energy)

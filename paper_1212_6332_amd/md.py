@@ -72,6 +72,7 @@ _SIGS = {
     "md_pressure": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "md_set_barostat": ([C.c_void_p, C.c_double, C.c_double, C.c_double], C.c_int),
     "md_get_box": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "md_set_thermostat": ([C.c_void_p, C.c_double, C.c_double], C.c_int),
 }
 
 
@@ -270,6 +271,10 @@ class System:
         """Berendsen barostat of eq. (5) in md_step; tau <= 0 switches it off."""
         _check(lib().md_set_barostat(self._h, float(p0), float(tau), float(beta)),
                "md_set_barostat")
+
+    def set_thermostat(self, t_e, tau_t):
+        """Electron-gas friction of eq. (4) in md_step; tau_t <= 0 switches it off."""
+        _check(lib().md_set_thermostat(self._h, float(t_e), float(tau_t)), "md_set_thermostat")
 
     def box(self):
         """Current box edges (numpy, length B)."""
