@@ -250,6 +250,33 @@ def bench_pressure(steps=100, warmup=10, reps=10):
             "box_start_A": float(wl.box_len[0, 0]), "box_end_A": L}
 
 
+def bench_thermostat(steps=100, warmup=10, reps=10):
+    """The 4M-atom box with the electron-gas friction of eq. (4) in every
+    half kick: steps with the thermostat on, and the fused force pass with and
+    without the friction."""
+    from paper_1212_6332_amd import md, workloads as W
+
+    wl = W.fcc4m()
+    te, tau = 600.0, 100.0
+    S = md.System.from_workload(wl)
+    S.set_state(wl.pos, wl.vel)
+    S.step(1)
+    ms_plain = S.time_pass(md.MD_PASS_FORCE_STEP, reps)
+    S.set_thermostat(te, tau)
+    ms_fric = S.time_pass(md.MD_PASS_FORCE_STEP, reps)
+    t_of = lambda: 2 * float(S.kinetic()[0]) / (3 * wl.n_atoms * W.KB_EV)
+    t0 = t_of()
+    wall, _, reb = timed_steps(S, steps, warmup)
+    t1 = t_of()
+    S.close()
+    return {"workload": f"fcc4m with the electron-gas thermostat (T_e = {te:g} K, "
+                        f"tau_T = {tau:g} fs)",
+            "thermostat_atom_steps_per_s": wl.n_atoms * steps / wall,
+            "thermostat_ms_per_step": wall / steps * 1e3, "rebuilds": int(reb),
+            "force_step_pass_ms": ms_plain, "force_step_pass_with_friction_ms": ms_fric,
+            "kinetic_T_start_K": t0, "kinetic_T_end_K": t1}
+
+
 def bench_c2(steps=1000, warmup=20):
     from paper_1212_6332_amd import md, workloads as W
 
@@ -355,6 +382,7 @@ def main():
         out["adjoint"] = bench_adjoint()
         out["bcc128k"] = bench_c2()
         out["pressure"] = bench_pressure()
+        out["thermostat"] = bench_thermostat()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
