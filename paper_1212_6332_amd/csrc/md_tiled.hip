@@ -272,6 +272,45 @@ __device__ __forceinline__ int halo_index(const Tile &t, int ix, int iy, int iz)
 
 // ---------------------------------------------------------------- list build
 
+// Candidates [k0, k1) of one stencil cell against atom i, 32 at a time: first
+// a hit mask with no branch per candidate, then one store per hit, in
+// ascending record order (the order of the rows the passes sum in).  The
+// record kself (the atom itself) is never listed.  SHIFT adds the cell's
+// periodic image shift to the difference, (x_j - x_i) + s, as the minimum
+// image convention rounds it.
+template <bool SHIFT>
+__device__ __forceinline__ void list_cell(const double *rec, int k0, int k1, int kself,
+                                          double xi, double yi, double zi, double sx, double sy,
+                                          double sz, double rl2, int *__restrict__ idx, int i,
+                                          int N, int mn, int &n, int &total)
+{
+#pragma clang fp contract(off)
+    for (int c0 = k0; c0 < k1; c0 += 32) {
+        const int m = min(32, k1 - c0);
+        const double *r = rec + 4 * c0;
+        unsigned mask = 0u;
+#pragma unroll 2
+        for (int q = 0; q < m; ++q, r += 4) {
+            double dx = r[0] - xi, dy = r[1] - yi, dz = r[2] - zi;
+            if constexpr (SHIFT) {
+                dx = dx + sx;
+                dy = dy + sy;
+                dz = dz + sz;
+            }
+            double r2 = (dx * dx + dy * dy) + dz * dz;
+            mask |= (r2 < rl2 ? 1u : 0u) << q;
+        }
+        unsigned d = (unsigned)(kself - c0);
+        if (d < 32u) mask &= ~(1u << d);
+        total += __popc(mask);
+        while (mask) {
+            int q = __ffs(mask) - 1;
+            mask &= mask - 1u;
+            if (n < mn) idx[nl_off(n++, i, N)] = (c0 + q) << 5;
+        }
+    }
+}
+
 __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, State st, Boxes bx,
                                                    Build bd, NList nl, int hmax, unsigned *flags)
 {
@@ -314,33 +353,13 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
                         int h = halo_index(t, lx + dx_, ly + dy, lz + dz);
                         int code = H.shift[h];
                         int k0 = H.off[h], k1 = min(H.off[h + 1], hmax);
-                        if (code == kNoShift) {
-                            for (int k = k0; k < k1; ++k) {
-                                const double *r = rec + 4 * k;
-                                double dx = r[0] - xi;
-                                double dy2 = r[1] - yi;
-                                double dz2 = r[2] - zi;
-                                double r2 = (dx * dx + dy2 * dy2) + dz2 * dz2;
-                                if (r2 < rl2 && k != kself) {
-                                    if (n < mn) nl.idx[nl_off(n++, i, N)] = k << 5;
-                                    ++total;
-                                }
-                            }
-                        } else {
-                            double sx = shift_of(code, 0, L), sy = shift_of(code, 1, L),
-                                   sz = shift_of(code, 2, L);
-                            for (int k = k0; k < k1; ++k) {
-                                const double *r = rec + 4 * k;
-                                double dx = (r[0] - xi) + sx;
-                                double dy2 = (r[1] - yi) + sy;
-                                double dz2 = (r[2] - zi) + sz;
-                                double r2 = (dx * dx + dy2 * dy2) + dz2 * dz2;
-                                if (r2 < rl2) {
-                                    if (n < mn) nl.idx[nl_off(n++, i, N)] = k << 5;
-                                    ++total;
-                                }
-                            }
-                        }
+                        if (code == kNoShift)
+                            list_cell<false>(rec, k0, k1, kself, xi, yi, zi, 0.0, 0.0, 0.0, rl2,
+                                             nl.idx, i, N, mn, n, total);
+                        else
+                            list_cell<true>(rec, k0, k1, -1, xi, yi, zi, shift_of(code, 0, L),
+                                            shift_of(code, 1, L), shift_of(code, 2, L), rl2,
+                                            nl.idx, i, N, mn, n, total);
                     }
         } else {
             int kself = H.off[(cz * nc + cy) * nc + cx] + (i - H.start[(cz * nc + cy) * nc + cx]);
