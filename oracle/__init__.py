@@ -317,6 +317,95 @@ def vv_thermo(pos, vel, L, pot: Pot, mass, dt, skin, nsteps, te, tau, maxn=256, 
     return (np.stack([x, y, z], axis=1), np.stack([vx, vy, vz], axis=1), ep, ek, nreb)
 
 
+class _Alloy(C.Structure):
+    _fields_ = [("ntypes", C.c_int), ("rc", C.c_double), ("V", C.c_void_p), ("rho", C.c_void_p),
+                ("F", C.c_void_p), ("nint", C.c_int * 3), ("lo", C.c_double * 3),
+                ("hi", C.c_double * 3)]
+
+
+class Alloy:
+    """Several-species tables (workloads.Potential with n_types > 1) in oracle form."""
+
+    def __init__(self, pot):
+        self.pot = pot
+        T = int(pot.n_types)
+        self._t = [np.ascontiguousarray(np.asarray(t, dtype=np.float64)) for t in pot.tables]
+        assert self._t[0].shape[0] == T * T and self._t[1].shape[0] == T * T
+        assert self._t[2].shape[0] == T
+        s = _Alloy()
+        s.ntypes = T
+        s.rc = float(pot.rc)
+        s.V, s.rho, s.F = (t.ctypes.data for t in self._t)
+        for k in range(3):
+            s.nint[k] = self._t[k].shape[1]
+            s.lo[k] = float(pot.lo[k])
+            s.hi[k] = float(pot.hi[k])
+        self._s = s
+
+    @property
+    def ref(self):
+        return C.byref(self._s)
+
+
+def _alloy_lib():
+    L = lib()
+    if not hasattr(L, "_alloy_ready"):
+        i32, i64, dbl = C.c_int, C.c_int64, C.c_double
+        L.orc_alloy_eval.argtypes = [i64, _f64p, _f64p, _f64p, dbl, C.c_void_p, _i32p,
+                                     C.c_void_p, C.c_void_p, i32, C.c_void_p, C.c_void_p, _f64p,
+                                     _f64p, _f64p, _f64p, _f64p]
+        L.orc_alloy_eval.restype = dbl
+        L.orc_alloy_vv.argtypes = [i64, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p, dbl,
+                                   C.c_void_p, _i32p, _f64p, dbl, dbl, i32, i32, dbl, dbl,
+                                   C.c_void_p, C.c_void_p]
+        L.orc_alloy_vv.restype = i32
+        L._alloy_ready = True
+    return L
+
+
+def alloy_eval(pos, L, pot: Alloy, types, count=None, ids=None):
+    """Densities, embedding values, forces, per-atom energies, total energy and
+    pair virial of one box with several species (eqs. 1-3 and 6), by the list
+    (count, ids) or, when it is None, over all pairs."""
+    x, y, z = (np.ascontiguousarray(pos[:, k], dtype=np.float64) for k in range(3))
+    n = x.size
+    t = np.ascontiguousarray(types, dtype=np.int32)
+    out = {k: np.zeros(n) for k in ("rho", "F", "Fp", "fx", "fy", "fz", "e_atom")}
+    if count is not None:
+        count = np.ascontiguousarray(count, dtype=np.int32)
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        cp, ip, maxn = count.ctypes.data, ids.ctypes.data, ids.shape[1]
+    else:
+        cp, ip, maxn = None, None, 0
+    W = _alloy_lib().orc_alloy_eval(n, x, y, z, float(L), pot.ref, t, cp, ip, int(maxn),
+                                    out["rho"].ctypes.data, out["F"].ctypes.data, out["Fp"],
+                                    out["fx"], out["fy"], out["fz"], out["e_atom"])
+    f = np.stack([out.pop("fx"), out.pop("fy"), out.pop("fz")], axis=1)
+    out["f"] = f
+    out["E"] = float(out["e_atom"].sum())
+    out["W"] = float(W)
+    return out
+
+
+def alloy_vv(pos, vel, L, pot: Alloy, types, type_mass, dt, skin, nsteps, te=0.0, tau=0.0,
+             maxn=256, energies=True):
+    """Velocity Verlet for several species (per-type masses; the friction of
+    eq. (4) when tau > 0).  Returns (pos, vel, epot, ekin, rebuilds)."""
+    x, y, z = _xyz(pos)
+    vx, vy, vz = _xyz(vel)
+    ep = np.zeros(nsteps + 1)
+    ek = np.zeros(nsteps + 1)
+    t = np.ascontiguousarray(types, dtype=np.int32)
+    m = np.ascontiguousarray(type_mass, dtype=np.float64)
+    nreb = _alloy_lib().orc_alloy_vv(x.size, x, y, z, vx, vy, vz, float(L), pot.ref, t, m,
+                                     float(dt), float(skin), int(nsteps), int(maxn), float(te),
+                                     float(tau), ep.ctypes.data if energies else None,
+                                     ek.ctypes.data if energies else None)
+    if nreb < 0:
+        raise ValueError("neighbour row overflow in orc_alloy_vv")
+    return (np.stack([x, y, z], axis=1), np.stack([vx, vy, vz], axis=1), ep, ek, nreb)
+
+
 def threads() -> int:
     return int(lib().orc_threads())
 

@@ -985,6 +985,209 @@ int orc_vv_baro(int64_t n, double *x, double *y, double *z, double *vx, double *
     return bad ? -1 : rebuilds;
 }
 
+/* ----------------------------------------------------------- several species */
+
+/*
+ * Eqs. (1)-(3) with atom types, a the type of atom i and b that of atom j:
+ *   rho_i = sum_j rho^(ab)(r_ij)    (density at an a atom contributed by a b atom)
+ *   E_i   = F^(a)(rho_i) + 1/2 sum_j V^(ab)(r_ij)
+ *   f_i   = -sum_j [F^(a)'(rho_i) rho^(ab)'(r) + F^(b)'(rho_j) rho^(ba)'(r)
+ *                   + V^(ab)'(r)] (x_i - x_j) / r
+ * The derivative of rho_j with respect to r_ij comes from the function that
+ * builds rho_j, rho^(ba); eq. (3) as printed writes rho^(ab) in both places,
+ * which is the same function when there is one species.  The embedding
+ * function is taken per type of the embedded atom.  V^(ab) = V^(ba).
+ * Tables are per-interval cubics on grids shared by all tables of one kind.
+ */
+typedef struct {
+    int ntypes;
+    double rc;
+    const double *V;   /* [T*T][nint[0]][4], index a*T + b */
+    const double *rho; /* [T*T][nint[1]][4], index a*T + b */
+    const double *F;   /* [T][nint[2]][4] */
+    int nint[3];
+    double lo[3], hi[3];
+} orc_alloy;
+
+static void alloy_fn(const orc_alloy *p, int which, int idx, double x, double *s, double *ds,
+                     double *dds)
+{
+    const double *base = which == 0 ? p->V : (which == 1 ? p->rho : p->F);
+    spline_eval(base + (size_t)idx * p->nint[which] * 4, p->nint[which], p->lo[which],
+                p->hi[which], x, s, ds, dds);
+}
+
+/* Neighbour j of atom i: the k-th list entry, or (ids == NULL) the k-th atom
+ * other than i in index order. */
+static int64_t alloy_nb(const int32_t *ids, int maxn, int64_t i, int k)
+{
+    if (ids) return ids[i * maxn + k];
+    return k < i ? k : k + 1;
+}
+
+/* rho, F, F' (any may be NULL except Fp), forces, per-atom energies and the
+ * pair virial W = -1/2 sum_i sum_j [...] r of eq. (6), for one box.  With
+ * ids == NULL every pair is visited (minimum image); else the list. */
+double orc_alloy_eval(int64_t n, const double *x, const double *y, const double *z, double L,
+                      const orc_alloy *p, const int32_t *type, const int32_t *count,
+                      const int32_t *ids, int maxn, double *rho_out, double *F_out, double *Fp,
+                      double *fx, double *fy, double *fz, double *e_atom)
+{
+    const int T = p->ntypes;
+    double rc2 = p->rc * p->rc;
+    double *rho = malloc(sizeof(double) * (n > 0 ? n : 1));
+    double *Fe = malloc(sizeof(double) * (n > 0 ? n : 1));
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        int cnt = ids ? count[i] : (int)(n - 1);
+        double s = 0.0;
+        for (int k = 0; k < cnt; ++k) {
+            int64_t j = alloy_nb(ids, maxn, i, k);
+            double dx, dy, dz;
+            double r2 = sep2(x, y, z, i, j, L, &dx, &dy, &dz);
+            if (r2 < rc2) {
+                double f, df, dd;
+                alloy_fn(p, 1, type[i] * T + type[j], sqrt(r2), &f, &df, &dd);
+                s += f;
+            }
+        }
+        rho[i] = s;
+        double dd;
+        alloy_fn(p, 2, type[i], s, &Fe[i], &Fp[i], &dd);
+    }
+    double W = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : W)
+    for (int64_t i = 0; i < n; ++i) {
+        int cnt = ids ? count[i] : (int)(n - 1);
+        int a = type[i];
+        double ax = 0.0, ay = 0.0, az = 0.0, ep = 0.0, w = 0.0;
+        for (int k = 0; k < cnt; ++k) {
+            int64_t j = alloy_nb(ids, maxn, i, k);
+            int b = type[j];
+            double dx, dy, dz;
+            double r2 = sep2(x, y, z, i, j, L, &dx, &dy, &dz);
+            if (r2 < rc2) {
+                double r = sqrt(r2), dd;
+                double v, dv, fab, dfab, fba, dfba;
+                alloy_fn(p, 0, a * T + b, r, &v, &dv, &dd);
+                alloy_fn(p, 1, a * T + b, r, &fab, &dfab, &dd);
+                alloy_fn(p, 1, b * T + a, r, &fba, &dfba, &dd);
+                double g = Fp[i] * dfab + Fp[j] * dfba + dv;
+                double coef = g / r;
+                /* (x_i - x_j) = -(dx, dy, dz) */
+                ax += coef * dx;
+                ay += coef * dy;
+                az += coef * dz;
+                ep += 0.5 * v;
+                w += g * r;
+            }
+        }
+        if (fx) { fx[i] = ax; fy[i] = ay; fz[i] = az; }
+        if (e_atom) e_atom[i] = Fe[i] + ep;
+        W += w;
+    }
+    if (rho_out) memcpy(rho_out, rho, sizeof(double) * n);
+    if (F_out) memcpy(F_out, Fe, sizeof(double) * n);
+    free(rho);
+    free(Fe);
+    return -0.5 * W;
+}
+
+static double alloy_kinetic(int64_t n, const double *vx, const double *vy, const double *vz,
+                            const int32_t *type, const double *mass_t)
+{
+    double K = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        K += 0.5 * mass_t[type[i]] * (vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]) / ORC_KAPPA;
+    return K;
+}
+
+/* The friction flow of eq. (4) over half a step (see orc_vv_thermo), with the
+ * per-atom factors e = exp(-dt / tau) and v_e^2 of the atom's type. */
+static void alloy_friction(int64_t n, double *vx, double *vy, double *vz, const double *ge,
+                           const double *gv2)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double v2 = vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i];
+        if (v2 > 0.0) {
+            double g = sqrt(ge[i] * v2 + (1.0 - ge[i]) * gv2[i]) / sqrt(v2);
+            vx[i] *= g;
+            vy[i] *= g;
+            vz[i] *= g;
+        }
+    }
+}
+
+/* Velocity Verlet for several species: atom i has mass mass_t[type[i]]; with
+ * tau > 0 the electron-gas friction of eq. (4) as in orc_vv_thermo, with
+ * v_e^2 = 3 k_B T_e / m of the atom's type.  Otherwise as orc_vv. */
+int orc_alloy_vv(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
+                 double L, const orc_alloy *p, const int32_t *type, const double *mass_t,
+                 double dt, double skin, int nsteps, int maxn, double te, double tau,
+                 double *epot, double *ekin)
+{
+    double rlist = orc_rlist(p->rc, skin, L);
+    double half_skin = 0.5 * (rlist - p->rc);
+    size_t nb = sizeof(double) * (n > 0 ? n : 1);
+    int32_t *count = (int32_t *)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+    int32_t *ids = (int32_t *)malloc(sizeof(int32_t) * (n > 0 ? n : 1) * maxn);
+    double *xr = malloc(nb), *yr = malloc(nb), *zr = malloc(nb), *c = malloc(nb);
+    double *Fp = malloc(nb), *e = malloc(nb);
+    double *fx = malloc(nb), *fy = malloc(nb), *fz = malloc(nb);
+    double *ge = malloc(nb), *gv2 = malloc(nb);
+    orc_md s = {n, x, y, z, vx, vy, vz, L, 0.0, dt, skin, NULL, maxn};
+    for (int64_t i = 0; i < n; ++i) {
+        double m = mass_t[type[i]];
+        c[i] = 0.5 * dt * ORC_KAPPA / m;
+        orc_thermo th = thermo_of(te, tau, dt, m);
+        ge[i] = th.e;
+        gv2[i] = th.ve2;
+    }
+    int on = tau > 0.0;
+    int rebuilds = 0, bad = 0;
+    bad |= md_rebuild(&s, rlist, count, ids, xr, yr, zr);
+    orc_alloy_eval(n, x, y, z, L, p, type, count, ids, maxn, NULL, NULL, Fp, fx, fy, fz, e);
+    if (epot) {
+        epot[0] = 0.0;
+        for (int64_t i = 0; i < n; ++i) epot[0] += e[i];
+    }
+    if (ekin) ekin[0] = alloy_kinetic(n, vx, vy, vz, type, mass_t);
+    for (int step = 1; step <= nsteps; ++step) {
+        if (on) alloy_friction(n, vx, vy, vz, ge, gv2);
+        double worst = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            vx[i] += c[i] * fx[i];
+            vy[i] += c[i] * fy[i];
+            vz[i] += c[i] * fz[i];
+            x[i] += dt * vx[i];
+            y[i] += dt * vy[i];
+            z[i] += dt * vz[i];
+            double ddx = x[i] - xr[i], ddy = y[i] - yr[i], ddz = z[i] - zr[i];
+            double d2 = ddx * ddx + ddy * ddy + ddz * ddz;
+            if (d2 > worst) worst = d2;
+        }
+        if (worst > half_skin * half_skin) {
+            bad |= md_rebuild(&s, rlist, count, ids, xr, yr, zr);
+            ++rebuilds;
+        }
+        orc_alloy_eval(n, x, y, z, L, p, type, count, ids, maxn, NULL, NULL, Fp, fx, fy, fz, e);
+        for (int64_t i = 0; i < n; ++i) {
+            vx[i] += c[i] * fx[i];
+            vy[i] += c[i] * fy[i];
+            vz[i] += c[i] * fz[i];
+        }
+        if (on) alloy_friction(n, vx, vy, vz, ge, gv2);
+        if (epot) {
+            epot[step] = 0.0;
+            for (int64_t i = 0; i < n; ++i) epot[step] += e[i];
+        }
+        if (ekin) ekin[step] = alloy_kinetic(n, vx, vy, vz, type, mass_t);
+    }
+    free(count); free(ids); free(xr); free(yr); free(zr); free(c);
+    free(Fp); free(e); free(fx); free(fy); free(fz); free(ge); free(gv2);
+    return bad ? -1 : rebuilds;
+}
+
 /* ------------------------------------------------------------------ adjoint */
 
 /*

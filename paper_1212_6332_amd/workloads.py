@@ -15,6 +15,7 @@ The five workloads
   fcc4m      FCC 100^3 (4,000,000 atoms), analytic second-moment tight binding
   batch2048  2,048 uneven FCC boxes n^3, n in {3..8}, spline tables of bcc128k
   adjoint64  64 BCC 5^3 boxes (250 atoms each), B-spline potential parameters
+  alloy      binary FCC 100^3 (4,000,000 atoms), two species, per-type-pair tables
 """
 from __future__ import annotations
 
@@ -70,6 +71,9 @@ class Potential:
     tables: tuple = ()
     lo: tuple = (0.0, 0.0, 0.0)
     hi: tuple = (0.0, 0.0, 0.0)
+    n_types: int = 1         # SPLINE with T > 1 species: tables[0] V^(ab) [T*T, n, 4],
+                             # tables[1] rho^(ab) [T*T, n, 4] (density at an a atom from
+                             # a b atom), tables[2] F^(a) [T, n, 4]; index a*T + b
 
 
 @dataclass
@@ -87,6 +91,8 @@ class Workload:
     lattice_const: float = 0.0
     structure: str = ""
     extra: dict = field(default_factory=dict)
+    types: np.ndarray = None     # int32 [N] species of each atom (several species only)
+    type_mass: np.ndarray = None  # float64 [T] mass of each species (amu)
 
     @property
     def n_atoms(self) -> int:
@@ -324,6 +330,76 @@ def batch2048(n_boxes: int = 2048, nmin: int = 3, nmax: int = 8) -> Workload:
                     extra={"ncell": ns, "temps": temps})
 
 
+MASS_AG = 107.8682
+
+
+def alloy_tables(pars, chis, rho_hi: float, knots: int = 5000) -> Potential:
+    """Tabulated EAM for several species from per-species FS forms (cutoff c
+    shared) and density strengths chi: V^(aa) the species' own pair term,
+    V^(ab) = (V^(aa) + V^(bb))/2 for a != b, rho^(ab)(r) = chi_b f(r) (an
+    atom's density is the sum of the functions of its neighbours' species),
+    F^(a) = -(A_a / sqrt(chi_a)) sqrt(rho), so that each pure species is its
+    FS form.  Clamped cubic interpolating splines through `knots` samples, as
+    in spline_tables_from_fs."""
+    T = len(pars)
+    c = float(pars[0][0])
+    assert all(float(p[0]) == c and float(p[1]) == c for p in pars)
+    single = []
+    for p, chi in zip(pars, chis):
+        q = np.array(p, dtype=np.float64)
+        q[5] /= np.sqrt(chi)
+        single.append(spline_tables_from_fs(q, rho_hi, knots))
+    V = np.empty((T * T,) + single[0].tables[0].shape)
+    R = np.empty((T * T,) + single[0].tables[1].shape)
+    F = np.empty((T,) + single[0].tables[2].shape)
+    for a in range(T):
+        F[a] = single[a].tables[2]
+        for b in range(T):
+            V[a * T + b] = 0.5 * (single[a].tables[0] + single[b].tables[0])
+            R[a * T + b] = chis[b] * single[b].tables[1]
+    return Potential(kind=POT_SPLINE, rc=c, tables=(V, R, F), lo=single[0].lo,
+                     hi=single[0].hi, n_types=T)
+
+
+def alloy(ncell: int = 100, frac: float = 0.3) -> Workload:
+    """Random substitutional binary FCC alloy: 100^3 cells (4,000,000 atoms),
+    a = 3.615, a fraction `frac` of the sites species 1 (mass 107.8682), the
+    rest species 0 (mass 63.546); two seeded FS species (cutoff 5.3, each with
+    A from its own zero-pressure condition at a; density strengths 1 and 1.6)
+    tabulated on 5,000 knots with alloy_tables; sigma 0.05, 300 K.  Smaller ncell gives the same material in
+    a smaller box."""
+    ss = np.random.SeedSequence(SEED_BASE + 5)
+    kids = ss.spawn(3)
+    a, cut = 3.615, 5.3
+    pars = [draw_fs(np.random.Generator(np.random.PCG64(kids[k])), "fcc", a, cut)
+            for k in range(2)]
+    r, n = shells("fcc", a, cut)
+    rho0 = float((n * (r - cut) ** 2).sum())
+    chis = (1.0, 1.6)
+    pot = alloy_tables(pars, chis, rho_hi=2.0 * max(chis) * rho0)
+    rng = np.random.Generator(np.random.PCG64(kids[2]))
+    sites = lattice("fcc", ncell, a)
+    types = (rng.random(sites.shape[0]) < frac).astype(np.int32)
+    mass_t = np.array([MASS_CU, MASS_AG])
+    pos = _displace(rng, sites, 0.05)
+    # Maxwell velocities per species, then the whole box's momentum removed and
+    # the kinetic energy set to 300 K with 3N - 3 degrees of freedom
+    vel = np.zeros_like(pos)
+    for t in range(2):
+        sel = types == t
+        vel[sel] = rng.normal(0.0, np.sqrt(KB_EV * 300.0 * KAPPA / mass_t[t]),
+                              size=(int(sel.sum()), 3))
+    m = mass_t[types][:, None]
+    vel -= (m * vel).sum(axis=0) / m.sum()
+    ekin = 0.5 * float((m * vel * vel).sum()) / KAPPA
+    vel *= np.sqrt(1.5 * (sites.shape[0] - 1) * KB_EV * 300.0 / ekin)
+    L = ncell * a
+    return Workload(name="alloy", box_offset=np.array([0, sites.shape[0]], dtype=np.int64),
+                    box_len=np.full((1, 3), L), pos=pos, vel=vel, mass=MASS_CU, dt=1.0,
+                    skin=0.3, pot=pot, steps=200, lattice_const=a, structure="fcc",
+                    types=types, type_mass=mass_t)
+
+
 def adjoint64(n_boxes: int = 64, ncell: int = 5) -> Workload:
     """64 BCC 5^3 boxes (250 atoms each), a = 2.8665, sigma 0.1.
 
@@ -355,4 +431,4 @@ def adjoint64(n_boxes: int = 64, ncell: int = 5) -> Workload:
 
 
 WORKLOADS = {"fs256": fs256, "bcc128k": bcc128k, "fcc4m": fcc4m,
-             "batch2048": batch2048, "adjoint64": adjoint64}
+             "batch2048": batch2048, "adjoint64": adjoint64, "alloy": alloy}
