@@ -97,6 +97,17 @@ typedef struct {
                                 BSPLINE [n_tab[k]] coefficients                   */
     int32_t n_tab[3];        /* SPLINE: intervals; BSPLINE: coefficients          */
     double lo[3], hi[3];     /* grid range of each table                          */
+    int32_t n_types;         /* species T (eq. 1: V^(ab), rho^(ab) for an atom of
+                                type a with a neighbour of type b).  0 or 1: one
+                                species.  T in 2..32: SPLINE only; tab[0] holds T*T
+                                tables V^(ab) back to back (table a*T + b, each
+                                n_tab[0] intervals; V^(ab) = V^(ba) required),
+                                tab[1] T*T tables rho^(ab) (the density at an atom
+                                of type a contributed by an atom of type b), tab[2]
+                                T tables F^(a); the V and rho tables share one
+                                grid (lo[0] = lo[1], hi[0] = hi[1], n_tab[0] =
+                                n_tab[1]); one cutoff rc for every pair.  Atom
+                                types come from md_set_types (default: all 0).   */
 } md_potential;
 
 typedef struct {
@@ -217,6 +228,19 @@ int md_pressure(md_ctx *ctx, double *p_box, double *w_box, void *stream);
  * cutoff; a box that would shrink below its cell grid is left unscaled and
  * raises MD_FLAG_BOX_RANGE. */
 int md_set_barostat(md_ctx *ctx, double p0, double tau, double beta);
+
+/* Species of the atoms (several-species contexts, n_types = T > 1): types is
+ * a HOST array [N] in the original atom order with values in [0, T);
+ * type_mass a host array [T] of masses (amu, > 0), or NULL for the system
+ * mass for every species.  Validated on the host (MD_ERR_ARG on a value out
+ * of range, or when the context has one species).  The force of eq. (3)
+ * then reads, with a the type of atom i and b that of atom j,
+ *   f_i = -sum_j [F^(a)'(rho_i) rho^(ab)'(r) + F^(b)'(rho_j) rho^(ba)'(r)
+ *                 + V^(ab)'(r)] (x_i - x_j) / r,
+ * and every kick, the friction of md_set_thermostat and the kinetic energy
+ * take the mass of the atom's species.  Several-species contexts step
+ * several boxes with the merged-box kernels (MD_OPT_BATCHED is 0). */
+int md_set_types(md_ctx *ctx, const int32_t *types, const double *type_mass);
 
 /* Electron-gas thermostat, eq. (4) of Section 2, applied by md_step: each
  * atom feels the friction -(m / tau_t) ((T_i - T_e) / T_i) v_i, with T_i =

@@ -59,6 +59,22 @@ int cells_per_dim(double L, double rl)
 int check_potential(const md_potential *p)
 {
     if (!p || !(p->rc > 0.0)) return MD_ERR_ARG;
+    if (p->n_types < 0 || p->n_types > kMaxTypes) return MD_ERR_ARG;
+    if (p->n_types > 1) {
+        // several species: spline tables, V and rho on one grid
+        if (p->kind != MD_POT_SPLINE) return MD_ERR_ARG;
+        if (p->lo[0] != p->lo[1] || p->hi[0] != p->hi[1] || p->n_tab[0] != p->n_tab[1])
+            return MD_ERR_ARG;
+        if (!p->tab[0] || p->n_tab[0] < 1) return MD_ERR_ARG;
+        // V^(ab) = V^(ba), coefficient for coefficient
+        const int T = p->n_types;
+        const size_t n0 = 4 * (size_t)p->n_tab[0];
+        for (int a = 0; a < T; ++a)
+            for (int b = a + 1; b < T; ++b)
+                if (std::memcmp(p->tab[0] + (size_t)(a * T + b) * n0,
+                                p->tab[0] + (size_t)(b * T + a) * n0, n0 * sizeof(double)) != 0)
+                    return MD_ERR_ARG;
+    }
     switch (p->kind) {
     case MD_POT_FS: return (p->params && p->n_params >= 6) ? MD_OK : MD_ERR_ARG;
     case MD_POT_SMTB: return (p->params && p->n_params >= 5) ? MD_OK : MD_ERR_ARG;
@@ -90,6 +106,7 @@ int upload_potential(Ctx &c, const md_potential *p, hipStream_t s, bool first)
     q.rc2 = p->rc * p->rc;
     if (p->kind == MD_POT_FS) {
         q.kind = MD_POT_FS;
+        q.nt = 1;
         q.c = p->params[0];
         q.d = p->params[1];
         q.c0 = p->params[2];
@@ -98,6 +115,7 @@ int upload_potential(Ctx &c, const md_potential *p, hipStream_t s, bool first)
         q.A = p->params[5];
     } else if (p->kind == MD_POT_SMTB) {
         q.kind = MD_POT_SMTB;
+        q.nt = 1;
         double A = p->params[0], xi = p->params[1], pp = p->params[2], qq = p->params[3],
                r0 = p->params[4];
         if (!(A > 0.0 && xi > 0.0 && r0 > 0.0 && pp > 0.0 && qq > 0.0)) return MD_ERR_ARG;
@@ -126,14 +144,18 @@ int upload_potential(Ctx &c, const md_potential *p, hipStream_t s, bool first)
         long double w = 1.0L;
         for (int m = 0; m < 12; ++m, w *= ln2) q.ec[m] = (double)(kExpPoly[m] * w);
     } else {
-        q.kind = MD_POT_SPLINE;
+        const int T = std::max(1, (int)p->n_types);
+        q.kind = T > 1 ? kTyped : MD_POT_SPLINE;
+        // tables per function: T*T for V and rho, T for F (one of each for one species)
+        const int per[3] = {T * T, T * T, T};
+        if (!first && T != c.ntypes) return MD_ERR_ARG;
         if (first) {
             size_t total = 0;
             c.tab_len.assign(3, 0);
             for (int k = 0; k < 3; ++k) {
                 int nint = p->kind == MD_POT_SPLINE ? p->n_tab[k] : p->n_tab[k] - 3;
-                c.tab_len[k] = 4 * nint;
-                total += 4 * (size_t)nint;
+                c.tab_len[k] = 4 * nint * per[k];
+                total += (size_t)c.tab_len[k];
             }
             ALLOC(c.tables, total);
             if (p->kind == MD_POT_BSPLINE) {
@@ -143,12 +165,13 @@ int upload_potential(Ctx &c, const md_potential *p, hipStream_t s, bool first)
         } else {
             for (int k = 0; k < 3; ++k) {
                 int nint = p->kind == MD_POT_SPLINE ? p->n_tab[k] : p->n_tab[k] - 3;
-                if (c.tab_len[k] != 4 * nint) return MD_ERR_ARG;
+                if (c.tab_len[k] != 4 * nint * per[k]) return MD_ERR_ARG;
             }
         }
+        q.nt = T;
         size_t off = 0;
         for (int k = 0; k < 3; ++k) {
-            int nint = c.tab_len[k] / 4;
+            int nint = c.tab_len[k] / (4 * per[k]);
             q.tab[k].c = c.tables + off;
             q.tab[k].n = nint;
             q.tab[k].lo = p->lo[k];
@@ -183,6 +206,26 @@ int alloc_list(Ctx &c, int mn)
     c.nl.mn = mn;
     ALLOC(c.nl.idx, (size_t)mn * c.N);
     HIP_TRY(hipMemset(c.nl.idx, 0, sizeof(int) * (size_t)mn * c.N));
+    return MD_OK;
+}
+
+// Per-type kick factor, friction addend and m / (2 kappa) (several species),
+// uploaded after the device is idle (kernels of any stream may read them).
+int upload_type_coef(Ctx &c)
+{
+    if (c.ntypes < 2) return MD_OK;
+    const double kb = 8.617333262e-5;
+    const double kappa = 1.602176634e-19 / 1.66053906660e-27 * 1e-10;
+    std::vector<double> h(4 * (size_t)c.ntypes, 0.0);
+    for (int t = 0; t < c.ntypes; ++t) {
+        double m = c.type_mass[t];
+        h[4 * t + kTcKick] = 0.5 * c.dt * kappa / m;
+        h[4 * t + kTcFric] =
+            c.thermo.on ? (1.0 - c.thermo.e) * (3.0 * kb * c.thermo_te * kappa / m) : 0.0;
+        h[4 * t + kTcHalfM] = 0.5 * m / kappa;
+    }
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(c.d_tcoef, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
     return MD_OK;
 }
 
@@ -542,6 +585,20 @@ int md_create(const md_system *sys, const md_potential *pot, md_ctx **out)
             return fail(MD_ERR_DEVICE);
     }
 
+    c.ntypes = std::max(1, (int)pot->n_types);
+    if (c.ntypes > 1) {
+        if ((rc = dev_alloc(c, &c.d_type0, (size_t)N)) != MD_OK) return fail(rc);
+        if ((rc = dev_alloc(c, &c.d_type, (size_t)N)) != MD_OK) return fail(rc);
+        if ((rc = dev_alloc(c, &c.d_tcoef, 4 * (size_t)c.ntypes)) != MD_OK) return fail(rc);
+        if (hipMemset(c.d_type0, 0, sizeof(int) * (size_t)N) != hipSuccess ||
+            hipMemset(c.d_type, 0, sizeof(int) * (size_t)N) != hipSuccess)
+            return fail(MD_ERR_DEVICE);
+        c.type_mass.assign(c.ntypes, c.mass);
+        c.st.type = c.d_type;
+        c.st.type0 = c.d_type0;
+        c.st.tcoef = c.d_tcoef;
+        if ((rc = upload_type_coef(c)) != MD_OK) return fail(rc);
+    }
     if ((rc = upload_potential(c, pot, s, true)) != MD_OK) return fail(rc);
     if (c.kind_user == MD_POT_BSPLINE) {
         size_t nd = adjoint_scratch_doubles(N, c.n_theta);
@@ -758,6 +815,36 @@ int md_set_barostat(md_ctx *h, double p0, double tau, double beta)
     return MD_OK;
 }
 
+int md_set_types(md_ctx *h, const int32_t *types, const double *type_mass)
+{
+    if (!h || !types) return MD_ERR_ARG;
+    Ctx &c = h->c;
+    if (c.ntypes < 2) return MD_ERR_ARG;
+    for (int64_t i = 0; i < c.N; ++i)
+        if (types[i] < 0 || types[i] >= c.ntypes) return MD_ERR_ARG;
+    std::vector<double> m(c.ntypes, c.mass);
+    if (type_mass)
+        for (int t = 0; t < c.ntypes; ++t) {
+            if (!(type_mass[t] > 0.0) || !std::isfinite(type_mass[t])) return MD_ERR_ARG;
+            m[t] = type_mass[t];
+        }
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(c.d_type0, types, sizeof(int) * (size_t)c.N, hipMemcpyHostToDevice));
+    c.type_mass = m;
+    int rc = upload_type_coef(c);
+    if (rc != MD_OK) return rc;
+    if (c.state_set) {
+        // the slots' species follow their original ids
+        launch_refresh_types(c, nullptr);
+        HIP_TRY(hipDeviceSynchronize());
+    }
+    // rows carry the neighbours' species; energies and forces change
+    c.list_valid = c.density_valid = c.forces_valid = false;
+    c.baro_mu_valid = false;
+    graph_reset(c);
+    return MD_OK;
+}
+
 int md_set_thermostat(md_ctx *h, double t_e, double tau_t)
 {
     if (!h) return MD_ERR_ARG;
@@ -777,6 +864,8 @@ int md_set_thermostat(md_ctx *h, double t_e, double tau_t)
         c.thermo = Thermo{1.0, 0.0, 0};
         c.thermo_te = c.thermo_tau = 0.0;
     }
+    int rc = upload_type_coef(c);
+    if (rc != MD_OK) return rc;
     graph_reset(c);
     return MD_OK;
 }

@@ -421,6 +421,11 @@ int batched_prepare(Ctx &c)
         b = new Batch();
         c.batch = b;
     }
+    if (c.ntypes > 1) {
+        // the persistent stepper evaluates one species
+        c.batch_feasible = c.batched = false;
+        return MD_OK;
+    }
     int nmax = 0, cmax = 0;
     for (int i = 0; i < c.B; ++i) {
         nmax = std::max<int>(nmax, (int)(c.box_off[i + 1] - c.box_off[i]));

@@ -151,6 +151,56 @@ __device__ __forceinline__ double pair_coef(const Pot &p, double r, double fpij,
     }
 }
 
+// Several species: interval and local coordinate of x on a grid shared by
+// the tables of one kind, and the coefficients of table idx there.
+__device__ __forceinline__ double table_locate(const Table &t, double x, int &m, unsigned &bad)
+{
+    double u = (x - t.lo) * t.inv_h;
+    m = (int)floor(u);
+    if (!(x >= t.lo && x <= t.hi)) bad |= MD_FLAG_TABLE_RANGE;
+    m = m < 0 ? 0 : (m > t.n - 1 ? t.n - 1 : m);
+    return u - (double)m;
+}
+
+__device__ __forceinline__ void table_cubic(const Table &t, int idx, int m, double tt, double &s,
+                                            double &ds)
+{
+    const double2 *p = reinterpret_cast<const double2 *>(t.c + 4 * ((size_t)idx * t.n + m));
+    double2 ab = p[0], cd = p[1];
+    s = fma(tt, fma(tt, fma(tt, cd.y, cd.x), ab.y), ab.x);
+    ds = fma(tt, fma(tt, 3.0 * cd.y, 2.0 * cd.x), ab.y) * t.inv_h;
+}
+
+// rho^(ab)(r): density at an atom of type a contributed by one of type b.
+__device__ __forceinline__ double dens_typed(const Pot &p, double r, int a, int b, unsigned &bad)
+{
+    int m;
+    double tt = table_locate(p.tab[1], r, m, bad), s, ds;
+    table_cubic(p.tab[1], a * p.nt + b, m, tt, s, ds);
+    return s;
+}
+
+// rho^(ab)'(r), rho^(ba)'(r), V^(ab)(r), V^(ab)'(r) on the shared r grid.
+__device__ __forceinline__ void pair_terms_typed(const Pot &p, double r, int a, int b,
+                                                 double &dab, double &dba, double &v, double &dv,
+                                                 unsigned &bad)
+{
+    int m;
+    double tt = table_locate(p.tab[0], r, m, bad), s;
+    table_cubic(p.tab[0], a * p.nt + b, m, tt, v, dv);
+    table_cubic(p.tab[1], a * p.nt + b, m, tt, s, dab);
+    table_cubic(p.tab[1], b * p.nt + a, m, tt, s, dba);
+}
+
+// F^(a)(rho), F^(a)'(rho).
+__device__ __forceinline__ void embed_typed(const Pot &p, double rho, int a, double &F, double &Fp,
+                                            unsigned &bad)
+{
+    int m;
+    double tt = table_locate(p.tab[2], rho, m, bad);
+    table_cubic(p.tab[2], a, m, tt, F, Fp);
+}
+
 // F(rho), F'(rho).
 template <int KIND>
 __device__ __forceinline__ void embed(const Pot &p, double rho, double &F, double &Fp,

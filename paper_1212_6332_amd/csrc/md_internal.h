@@ -16,6 +16,9 @@ constexpr int kChunk = 4096;       // atoms per partial sum of the energy reduct
 constexpr int kTileThreads = 1024; // threads of a tiled-pass workgroup (one tile)
 constexpr int kHaloCells = 512;    // halo cells a tile may have
 constexpr int kTileGlobal = 0, kTileA = 1, kTileB = 2;  // halo modes of a box
+constexpr int kTyped = 13;         // kernel kind: spline tables for several species
+constexpr int kMaxTypes = 32;      // the type of a neighbour rides in the 5 low bits
+                                   // of its (32-byte aligned) row entry
 
 // Per-interval cubic table on a uniform grid: c[4*m + {0,1,2,3}] = a, b, c, d.
 struct Table {
@@ -47,6 +50,8 @@ struct Pot {
     double av, bv, af, bf, bvd, bfd, avn, afn;
     double ec[12];                     // kExpPoly[m] ln(2)^m, kernel arguments (scalar registers)
     Table tab[3];                      // V(r), rho(r), F(rho)
+    int nt;                            // species; with nt > 1 each Table holds nt*nt (V, rho)
+                                       // or nt (F) tables back to back, table a*nt + b
 };
 
 // Electron-gas friction of eq. (4) as the kick kernels see it: over half a
@@ -79,7 +84,26 @@ struct State {
     int *id;                           // original index of each sorted slot
     double *rho, *Fp, *Femb, *eat;     // density, F'(rho), F(rho), per-atom energy
     double *wat;                       // per-atom virial term sum_j [(F'_i + F'_j) rho' + V'] r
+    // several species (null otherwise): type of each slot, type of each
+    // original atom, and per type: half-kick factor, friction addend, m / (2 kappa)
+    int *type;
+    const int *type0;
+    const double *tcoef;
 };
+
+// Per-type coefficients (several species): [4 t + k], k as below.
+constexpr int kTcKick = 0, kTcFric = 1, kTcHalfM = 2;
+
+// Half-kick factor and friction addend of atom i: those of its species in
+// several-species contexts, else the context's (already in kick and th).
+__device__ __forceinline__ void species_kick(const State &st, int i, double &kick, Thermo &th)
+{
+    if (st.type) {
+        const double *c = st.tcoef + 4 * st.type[i];
+        kick = c[kTcKick];
+        th.a = c[kTcFric];
+    }
+}
 
 // Per-box geometry (device arrays of length B, box_of of length N).
 struct Boxes {
@@ -121,6 +145,7 @@ struct Ctx;
 
 // Launchers (md_kernels.hip).
 void launch_set_state(Ctx &c, const double *pos, const double *vel, hipStream_t s);
+void launch_refresh_types(Ctx &c, hipStream_t s);
 void launch_get_state(Ctx &c, double *pos, double *vel, hipStream_t s);
 void launch_build(Ctx &c, bool gated, hipStream_t s);
 void launch_density(Ctx &c, hipStream_t s);
@@ -216,6 +241,12 @@ struct Ctx {
     bool baro_mu_valid = false;        // d_baro holds the scale factors of the next step
     double baro_p0 = 0.0, baro_tau = 0.0, baro_beta = 0.0;
     double *d_baro = nullptr;          // per box: mu | strain | rlist | pressure | virial | kinetic | virial sum
+
+    // several species
+    int ntypes = 1;
+    std::vector<double> type_mass;     // [ntypes]
+    int *d_type0 = nullptr, *d_type = nullptr;
+    double *d_tcoef = nullptr;         // [4 ntypes]
 
     // electron-gas thermostat (eq. 4)
     Thermo thermo{1.0, 0.0, 0};

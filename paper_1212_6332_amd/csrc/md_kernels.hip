@@ -93,6 +93,7 @@ __device__ __forceinline__ void for_pairs(const int *__restrict__ idx, int i, in
     double2 b;
     if constexpr (FPJ) b = ldpk(pk, j, 1);
     else b.x = ldpk_z(pk, j);
+    unsigned jc = j;
     for (int n = n0; n < n1; ++n) {
         unsigned jnn = (n + 2 < n1) ? (unsigned)idx[nl_off(n + 2, i, N)] : jn;
         double2 an = ldpk(pk, jn, 0);
@@ -105,7 +106,8 @@ __device__ __forceinline__ void for_pairs(const int *__restrict__ idx, int i, in
             dy = min_image(dy, L, invL);
             dz = min_image(dz, L, invL);
         }
-        body(dx, dy, dz, FPJ ? b.y : 0.0);
+        body(dx, dy, dz, FPJ ? b.y : 0.0, jc);
+        jc = jn;
         jn = jnn;
         a = an;
         b = bn;
@@ -140,6 +142,15 @@ __global__ void k_set_state(int N, const double *__restrict__ pos, const double 
     st.vy[i] = vel ? vel[3 * (size_t)i + 1] : 0.0;
     st.vz[i] = vel ? vel[3 * (size_t)i + 2] : 0.0;
     st.id[i] = i;
+    if (st.type) st.type[i] = st.type0[i];
+}
+
+// Species of every slot from its original id.
+__global__ void k_refresh_types(int N, State st)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    st.type[i] = st.type0[st.id[i]];
 }
 
 __global__ void k_get_state(int N, State st, double *__restrict__ pos, double *__restrict__ vel)
@@ -385,6 +396,7 @@ __global__ void k_commit(const unsigned *gate, int N, State st, Build bd)
     st.vy[q] = bd.svy[q];
     st.vz[q] = bd.svz[q];
     st.id[q] = bd.sid[q];
+    if (st.type) st.type[q] = st.type0[bd.sid[q]];
 }
 
 // Full list of slot i.  r^2 = (dx*dx + dy*dy) + dz*dz with separate
@@ -515,14 +527,23 @@ __global__ __launch_bounds__(kBlock) void k_density(int N, State st, Boxes bx, N
     Row rw = row_of(nl, i);
     unsigned bad = 0;
     double rho = 0.0;
-    auto body = [&](double dx, double dy, double dz, double) {
+    const int ai = KIND == kTyped ? st.type[i] : 0;
+    auto body = [&](double dx, double dy, double dz, double, unsigned j) {
         double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-        if (r2 < pot.rc2) rho += dens<KIND>(pot, r2 * rsqrt_nr(r2), bad);
+        if (r2 < pot.rc2) {
+            if constexpr (KIND == kTyped)
+                rho += dens_typed(pot, r2 * rsqrt_nr(r2), ai, st.type[j], bad);
+            else
+                rho += dens<KIND>(pot, r2 * rsqrt_nr(r2), bad);
+        }
     };
     for_pairs<false, false>(nl.idx, i, N, 0, rw.np, pk, xi, yi, zi, L, invL, body);
     for_pairs<true, false>(nl.idx, i, N, nl.mn - rw.ni, nl.mn, pk, xi, yi, zi, L, invL, body);
     double F, Fp;
-    embed<KIND>(pot, rho, F, Fp, bad);
+    if constexpr (KIND == kTyped)
+        embed_typed(pot, rho, ai, F, Fp, bad);
+    else
+        embed<KIND>(pot, rho, F, Fp, bad);
     st.rho[i] = rho;
     st.Femb[i] = F;
     st.Fp[i] = Fp;
@@ -537,7 +558,10 @@ __global__ void k_embed(int N, State st, Pot pot, unsigned *flags)
     if (i >= N) return;
     unsigned bad = 0;
     double F, Fp;
-    embed<KIND>(pot, st.rho[i], F, Fp, bad);
+    if constexpr (KIND == kTyped)
+        embed_typed(pot, st.rho[i], st.type[i], F, Fp, bad);
+    else
+        embed<KIND>(pot, st.rho[i], F, Fp, bad);
     st.Femb[i] = F;
     st.Fp[i] = Fp;
     raise_flags(flags, bad);
@@ -561,14 +585,24 @@ __global__ __launch_bounds__(kBlock) void k_force(int N, State st, Boxes bx, NLi
     Row rw = row_of(nl, i);
     unsigned bad = 0;
     double ax = 0.0, ay = 0.0, az = 0.0, ep = 0.0, wv = 0.0;
-    auto body = [&](double dx, double dy, double dz, double fpj) {
+    const int ai = KIND == kTyped ? st.type[i] : 0;
+    auto body = [&](double dx, double dy, double dz, double fpj, unsigned j) {
         double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
         if (r2 < pot.rc2) {
             double inv_r = rsqrt_nr(r2);
-            double dfr, v, dv;
-            pair_terms<KIND>(pot, r2 * inv_r, dfr, v, dv, bad);
-            // f_i += [(F'_i + F'_j) rho'(r) + V'(r)] (x_j - x_i) / r
-            double coef = fma(fpi + fpj, dfr, dv) * inv_r;
+            double coef, v;
+            if constexpr (KIND == kTyped) {
+                // [F'_i rho^(ab)'(r) + F'_j rho^(ba)'(r) + V^(ab)'(r)] / r
+                double dab, dba, dv;
+                pair_terms_typed(pot, r2 * inv_r, ai, st.type[j], dab, dba, v, dv, bad);
+                coef = fma(fpi, dab, fma(fpj, dba, dv)) * inv_r;
+            } else {
+                // [(F'_i + F'_j) rho'(r) + V'(r)] / r
+                double dfr, dv;
+                pair_terms<KIND>(pot, r2 * inv_r, dfr, v, dv, bad);
+                coef = fma(fpi + fpj, dfr, dv) * inv_r;
+            }
+            // f_i += coef (x_j - x_i)
             ax = fma(coef, dx, ax);
             ay = fma(coef, dy, ay);
             az = fma(coef, dz, az);
@@ -588,6 +622,7 @@ __global__ __launch_bounds__(kBlock) void k_force(int N, State st, Boxes bx, NLi
         st.wat[i] = wv;
     }
     if constexpr (KICK) {
+        species_kick(st, i, kick, th);
         double vx = fma(kick, ax, st.vx[i]);
         double vy = fma(kick, ay, st.vy[i]);
         double vz = fma(kick, az, st.vz[i]);
@@ -610,6 +645,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(int N, State st, Boxes bx
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     bool need = false, bad = false;
     if (i < N) {
+        species_kick(st, i, kick, th);
         double vx = st.vx[i], vy = st.vy[i], vz = st.vz[i];
         if (th.on) friction_flow(th, vx, vy, vz);
         vx = fma(kick, st.fx[i], vx);
@@ -681,7 +717,8 @@ __global__ __launch_bounds__(kBlock) void k_chunk_sums(int what, State st, doubl
             acc += st.wat[i];
         } else {
             double vx = st.vx[i], vy = st.vy[i], vz = st.vz[i];
-            acc += half_m_over_k * fma(vz, vz, fma(vy, vy, vx * vx));
+            double hm = st.type ? st.tcoef[4 * st.type[i] + kTcHalfM] : half_m_over_k;
+            acc += hm * fma(vz, vz, fma(vy, vy, vx * vx));
         }
     }
     red[threadIdx.x] = acc;
@@ -875,6 +912,11 @@ void launch_pack_positions(Ctx &c, hipStream_t s)
     k_pack_positions<<<grid_for(c.N), kBlock, 0, s>>>((int)c.N, c.st);
 }
 
+void launch_refresh_types(Ctx &c, hipStream_t s)
+{
+    k_refresh_types<<<grid_for(c.N), kBlock, 0, s>>>((int)c.N, c.st);
+}
+
 void launch_set_state(Ctx &c, const double *pos, const double *vel, hipStream_t s)
 {
     k_set_state<<<grid_for(c.N), kBlock, 0, s>>>((int)c.N, pos, vel, c.st);
@@ -920,6 +962,7 @@ void launch_density(Ctx &c, hipStream_t s)
     switch (c.pot.kind) {
     case MD_POT_FS: multi ? density_t<MD_POT_FS, true>(c, s) : density_t<MD_POT_FS, false>(c, s); break;
     case MD_POT_SMTB: multi ? density_t<MD_POT_SMTB, true>(c, s) : density_t<MD_POT_SMTB, false>(c, s); break;
+    case kTyped: multi ? density_t<kTyped, true>(c, s) : density_t<kTyped, false>(c, s); break;
     default: multi ? density_t<MD_POT_SPLINE, true>(c, s) : density_t<MD_POT_SPLINE, false>(c, s); break;
     }
 }
@@ -930,6 +973,7 @@ void launch_embed(Ctx &c, hipStream_t s)
     switch (c.pot.kind) {
     case MD_POT_FS: k_embed<MD_POT_FS><<<g, kBlock, 0, s>>>((int)c.N, c.st, c.pot, c.dev.flags); break;
     case MD_POT_SMTB: k_embed<MD_POT_SMTB><<<g, kBlock, 0, s>>>((int)c.N, c.st, c.pot, c.dev.flags); break;
+    case kTyped: k_embed<kTyped><<<g, kBlock, 0, s>>>((int)c.N, c.st, c.pot, c.dev.flags); break;
     default: k_embed<MD_POT_SPLINE><<<g, kBlock, 0, s>>>((int)c.N, c.st, c.pot, c.dev.flags); break;
     }
 }
@@ -945,6 +989,7 @@ void launch_force(Ctx &c, bool energy, int kick_mode, hipStream_t s)
     switch (c.pot.kind) {
     case MD_POT_FS: multi ? force_t<MD_POT_FS, true>(c, energy, kick, s) : force_t<MD_POT_FS, false>(c, energy, kick, s); break;
     case MD_POT_SMTB: multi ? force_t<MD_POT_SMTB, true>(c, energy, kick, s) : force_t<MD_POT_SMTB, false>(c, energy, kick, s); break;
+    case kTyped: multi ? force_t<kTyped, true>(c, energy, kick, s) : force_t<kTyped, false>(c, energy, kick, s); break;
     default: multi ? force_t<MD_POT_SPLINE, true>(c, energy, kick, s) : force_t<MD_POT_SPLINE, false>(c, energy, kick, s); break;
     }
 }

@@ -181,7 +181,7 @@ __device__ __forceinline__ void stage(const Tile &t, const State &st, const Halo
     int total = min(H.total, hmax);
     for (int base = 0; base < total; base += R * kT) {
         double vx[R], vy[R], vz[R], vf[R];
-        int kk[R];
+        int kk[R], ty[R];
 #pragma unroll
         for (int u = 0; u < R; ++u) {
             int k = base + u * kT + (int)threadIdx.x;
@@ -200,6 +200,7 @@ __device__ __forceinline__ void stage(const Tile &t, const State &st, const Halo
                 vy[u] = st.y[j] + (shifted ? shift_of(code, 1, t.L) : 0.0);
                 vz[u] = st.z[j] + (shifted ? shift_of(code, 2, t.L) : 0.0);
                 if constexpr (WITH_FP) vf[u] = st.Fp[j];
+                else ty[u] = st.type ? st.type[j] : 0;
             }
         }
 #pragma unroll
@@ -210,6 +211,7 @@ __device__ __forceinline__ void stage(const Tile &t, const State &st, const Halo
                 r[1] = vy[u];
                 r[2] = vz[u];
                 if constexpr (WITH_FP) r[3] = vf[u];
+                else reinterpret_cast<int *>(r + 3)[0] = ty[u];
             }
         }
     }
@@ -277,12 +279,21 @@ __device__ __forceinline__ int halo_index(const Tile &t, int ix, int iy, int iz)
 // ascending record order (the order of the rows the passes sum in).  The
 // record kself (the atom itself) is never listed.  SHIFT adds the cell's
 // periodic image shift to the difference, (x_j - x_i) + s, as the minimum
-// image convention rounds it.
+// image convention rounds it.  An entry is the record's byte offset, with
+// the record's species (staged in its fourth slot) in the five low bits when
+// `typed`.
+__device__ __forceinline__ int row_entry(const double *rec, int k, bool typed)
+{
+    int e = k << 5;
+    if (typed) e |= reinterpret_cast<const int *>(rec + 4 * (size_t)k + 3)[0];
+    return e;
+}
+
 template <bool SHIFT>
 __device__ __forceinline__ void list_cell(const double *rec, int k0, int k1, int kself,
                                           double xi, double yi, double zi, double sx, double sy,
                                           double sz, double rl2, int *__restrict__ idx, int i,
-                                          int N, int mn, int &n, int &total)
+                                          int N, int mn, bool typed, int &n, int &total)
 {
 #pragma clang fp contract(off)
     for (int c0 = k0; c0 < k1; c0 += 32) {
@@ -306,7 +317,7 @@ __device__ __forceinline__ void list_cell(const double *rec, int k0, int k1, int
         while (mask) {
             int q = __ffs(mask) - 1;
             mask &= mask - 1u;
-            if (n < mn) idx[nl_off(n++, i, N)] = (c0 + q) << 5;
+            if (n < mn) idx[nl_off(n++, i, N)] = row_entry(rec, c0 + q, typed);
         }
     }
 }
@@ -327,6 +338,7 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
     const double L = t.L, invL = t.invL, rl2 = bx.rl2[t.b];
     const int mn = nl.mn, nc = t.nc;
     const double ncL = nc * invL;
+    const bool typed = st.type != nullptr;
     unsigned bad = 0;
     for (int i = t.s0 + threadIdx.x; i < t.s1; i += kT) {
         double xi = st.x[i], yi = st.y[i], zi = st.z[i];
@@ -355,11 +367,11 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
                         int k0 = H.off[h], k1 = min(H.off[h + 1], hmax);
                         if (code == kNoShift)
                             list_cell<false>(rec, k0, k1, kself, xi, yi, zi, 0.0, 0.0, 0.0, rl2,
-                                             nl.idx, i, N, mn, n, total);
+                                             nl.idx, i, N, mn, typed, n, total);
                         else
                             list_cell<true>(rec, k0, k1, -1, xi, yi, zi, shift_of(code, 0, L),
                                             shift_of(code, 1, L), shift_of(code, 2, L), rl2,
-                                            nl.idx, i, N, mn, n, total);
+                                            nl.idx, i, N, mn, typed, n, total);
                     }
         } else {
             int kself = H.off[(cz * nc + cy) * nc + cx] + (i - H.start[(cz * nc + cy) * nc + cx]);
@@ -379,7 +391,7 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
                             dz2 = dz2 - rint(dz2 * invL) * L;
                             double r2 = (dx * dx + dy2 * dy2) + dz2 * dz2;
                             if (r2 < rl2) {
-                                if (n < mn) nl.idx[nl_off(n++, i, N)] = k << 5;
+                                if (n < mn) nl.idx[nl_off(n++, i, N)] = row_entry(rec, k, typed);
                                 ++total;
                             }
                         }
@@ -398,7 +410,7 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
 // 16-byte load per group.  While group q is evaluated, group q + 1 is already in
 // flight; the two registers alternate roles (the loop body is unrolled by
 // two) so that no register copy at the back edge waits for a load.
-template <bool IMG, class Body>
+template <bool IMG, bool TYPED, class Body>
 __device__ __forceinline__ void for_row(const int *__restrict__ idx, int i, int N, int n1,
                                         const double *rec, double xi, double yi, double zi,
                                         double L, double invL, Body &&body)
@@ -411,8 +423,14 @@ __device__ __forceinline__ void for_row(const int *__restrict__ idx, int i, int 
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             if (u < m) {
+                unsigned off = (unsigned)kk[u];
+                int tj = 0;
+                if constexpr (TYPED) {
+                    tj = (int)(off & 31u);
+                    off &= ~31u;
+                }
                 const double2 *r = reinterpret_cast<const double2 *>(
-                    reinterpret_cast<const char *>(rec) + (unsigned)kk[u]);
+                    reinterpret_cast<const char *>(rec) + off);
                 double2 a = r[0], b2 = r[1];
                 double dx = a.x - xi, dy = a.y - yi, dz = b2.x - zi;
                 if constexpr (IMG) {
@@ -420,7 +438,7 @@ __device__ __forceinline__ void for_row(const int *__restrict__ idx, int i, int 
                     dy = min_image(dy, L, invL);
                     dz = min_image(dz, L, invL);
                 }
-                body(dx, dy, dz, b2.y);
+                body(dx, dy, dz, b2.y, tj);
             }
         }
     };
@@ -537,16 +555,26 @@ __global__ __launch_bounds__(kT) void k_tile_density(int N, int G, State st, Box
             double xi = st.x[i], yi = st.y[i], zi = st.z[i];
             int n1 = nl.count[i] & 0xffff;
             double rho = 0.0;
-            auto body = [&](double dx, double dy, double dz, double) {
+            const int ai = KIND == kTyped ? st.type[i] : 0;
+            auto body = [&](double dx, double dy, double dz, double, int tj) {
                 double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                if (r2 < pot.rc2) rho += dens<KIND>(pot, r2 * rsqrt_nr(r2), bad);
+                if (r2 < pot.rc2) {
+                    if constexpr (KIND == kTyped)
+                        rho += dens_typed(pot, r2 * rsqrt_nr(r2), ai, tj, bad);
+                    else
+                        rho += dens<KIND>(pot, r2 * rsqrt_nr(r2), bad);
+                }
             };
+            constexpr bool TY = KIND == kTyped;
             if (shifted)
-                for_row<false>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
+                for_row<false, TY>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
             else
-                for_row<true>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
+                for_row<true, TY>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
             double F, Fp;
-            embed<KIND>(pot, rho, F, Fp, bad);
+            if constexpr (KIND == kTyped)
+                embed_typed(pot, rho, ai, F, Fp, bad);
+            else
+                embed<KIND>(pot, rho, F, Fp, bad);
             st.rho[i] = rho;
             st.Femb[i] = F;
             st.Fp[i] = Fp;
@@ -596,13 +624,23 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
                 rz = st.zr[i];
             }
             double ax = 0.0, ay = 0.0, az = 0.0, ep = 0.0, wv = 0.0;
-            auto body = [&](double dx, double dy, double dz, double fpj) {
+            const int ai = KIND == kTyped ? st.type[i] : 0;
+            auto body = [&](double dx, double dy, double dz, double fpj, int tj) {
                 double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
                 if (r2 < pot.rc2) {
                     double inv_r = rsqrt_nr(r2);
-                    // f_i += [(F'_i + F'_j) rho'(r) + V'(r)] (x_j - x_i) / r
+                    // f_i += [(F'_i + F'_j) rho'(r) + V'(r)] (x_j - x_i) / r; with
+                    // several species [F'_i rho^(ab)'(r) + F'_j rho^(ba)'(r) + V^(ab)'(r)]
                     double coef;
-                    if constexpr (ENERGY) {
+                    if constexpr (KIND == kTyped) {
+                        double dab, dba, v, dv;
+                        pair_terms_typed(pot, r2 * inv_r, ai, tj, dab, dba, v, dv, bad);
+                        coef = fma(fpi, dab, fma(fpj, dba, dv)) * inv_r;
+                        if constexpr (ENERGY) {
+                            ep += v;
+                            wv = fma(coef, r2, wv);
+                        }
+                    } else if constexpr (ENERGY) {
                         double dfr, v, dv;
                         pair_terms<KIND>(pot, r2 * inv_r, dfr, v, dv, bad);
                         coef = fma(fpi + fpj, dfr, dv) * inv_r;
@@ -616,10 +654,11 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
                     az = fma(coef, dz, az);
                 }
             };
+            constexpr bool TY = KIND == kTyped;
             if (shifted)
-                for_row<false>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
+                for_row<false, TY>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
             else
-                for_row<true>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
+                for_row<true, TY>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
             ax *= sg;
             ay *= sg;
             az *= sg;
@@ -631,15 +670,18 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
                 st.wat[i] = wv;
             }
             if constexpr (MODE >= 1) {
-                double vx = fma(kick, ax, v0x);
-                double vy = fma(kick, ay, v0y);
-                double vz = fma(kick, az, v0z);
-                if (th.on) friction_flow(th, vx, vy, vz);
+                double ki = kick;
+                Thermo thi = th;
+                species_kick(st, i, ki, thi);
+                double vx = fma(ki, ax, v0x);
+                double vy = fma(ki, ay, v0y);
+                double vz = fma(ki, az, v0z);
+                if (thi.on) friction_flow(thi, vx, vy, vz);
                 if constexpr (MODE == 2) {
-                    if (th.on) friction_flow(th, vx, vy, vz);
-                    vx = fma(kick, ax, vx);
-                    vy = fma(kick, ay, vy);
-                    vz = fma(kick, az, vz);
+                    if (thi.on) friction_flow(thi, vx, vy, vz);
+                    vx = fma(ki, ax, vx);
+                    vy = fma(ki, ay, vy);
+                    vz = fma(ki, az, vz);
                     double x = fma(dt, vx, xi), y = fma(dt, vy, yi), z = fma(dt, vz, zi);
                     st.xo[i] = x;
                     st.yo[i] = y;
@@ -753,6 +795,12 @@ void tiled_prepare(Ctx &c)
     allow(k_tile_force<MD_POT_SPLINE, false, 1>, lds);
     allow(k_tile_force<MD_POT_SPLINE, false, 0>, lds);
     allow(k_tile_force<MD_POT_SPLINE, false, 2>, lds);
+    allow(k_tile_density<kTyped>, lds);
+    allow(k_tile_force<kTyped, true, 1>, lds);
+    allow(k_tile_force<kTyped, true, 0>, lds);
+    allow(k_tile_force<kTyped, false, 1>, lds);
+    allow(k_tile_force<kTyped, false, 0>, lds);
+    allow(k_tile_force<kTyped, false, 2>, lds);
 }
 
 void launch_tile_nlist(Ctx &c, const unsigned *gate, hipStream_t s)
@@ -767,6 +815,7 @@ void launch_tile_density(Ctx &c, hipStream_t s)
     switch (c.pot.kind) {
     case MD_POT_FS: k_tile_density<MD_POT_FS><<<P, kT, c.tile_lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
     case MD_POT_SMTB: k_tile_density<MD_POT_SMTB><<<P, kT, c.tile_lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
+    case kTyped: k_tile_density<kTyped><<<P, kT, c.tile_lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
     default: k_tile_density<MD_POT_SPLINE><<<P, kT, c.tile_lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
     }
 }
@@ -777,6 +826,7 @@ void launch_tile_force(Ctx &c, bool energy, int mode, hipStream_t s)
     switch (c.pot.kind) {
     case MD_POT_FS: force_launch<MD_POT_FS>(c, energy, mode, k, s); break;
     case MD_POT_SMTB: force_launch<MD_POT_SMTB>(c, energy, mode, k, s); break;
+    case kTyped: force_launch<kTyped>(c, energy, mode, k, s); break;
     default: force_launch<MD_POT_SPLINE>(c, energy, mode, k, s); break;
     }
 }

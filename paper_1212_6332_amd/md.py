@@ -36,7 +36,8 @@ class MDError(RuntimeError):
 class md_potential(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n_params", C.c_int32), ("rc", C.c_double),
                 ("params", C.c_void_p), ("tab", C.c_void_p * 3), ("n_tab", C.c_int32 * 3),
-                ("lo", C.c_double * 3), ("hi", C.c_double * 3)]
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("n_types", C.c_int32)]
 
 
 class md_system(C.Structure):
@@ -73,6 +74,7 @@ _SIGS = {
     "md_set_barostat": ([C.c_void_p, C.c_double, C.c_double, C.c_double], C.c_int),
     "md_get_box": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "md_set_thermostat": ([C.c_void_p, C.c_double, C.c_double], C.c_int),
+    "md_set_types": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
 }
 
 
@@ -115,14 +117,17 @@ class _PotHolder:
     def __init__(self, pot):
         self.params = np.ascontiguousarray(np.asarray(pot.params, dtype=np.float64).ravel())
         self.tabs = [np.ascontiguousarray(np.asarray(t, dtype=np.float64)) for t in pot.tables]
+        T = int(getattr(pot, "n_types", 1) or 1)
         s = md_potential()
+        s.n_types = T
         s.kind = int(pot.kind)
         s.n_params = int(self.params.size)
         s.rc = float(pot.rc)
         s.params = self.params.ctypes.data if self.params.size else None
         for k, t in enumerate(self.tabs):
             s.tab[k] = t.ctypes.data
-            s.n_tab[k] = int(t.shape[0])
+            # several species: [tables, intervals, 4] -> intervals per table
+            s.n_tab[k] = int(t.shape[1] if T > 1 else t.shape[0])
         for k in range(3):
             s.lo[k] = float(pot.lo[k])
             s.hi[k] = float(pot.hi[k])
@@ -161,7 +166,20 @@ class System:
     @classmethod
     def from_workload(cls, W, pot=None, **kw):
         s = cls(W.box_offset, W.box_len, pot or W.pot, W.mass, W.dt, W.skin, **kw)
+        if getattr(W, "types", None) is not None and int(getattr(s.pot, "n_types", 1)) > 1:
+            s.set_types(W.types, W.type_mass)
         return s
+
+    def set_types(self, types, type_mass=None):
+        """Species of every atom (host array, original order) and per-species masses."""
+        t = np.ascontiguousarray(np.asarray(types, dtype=np.int32))
+        if t.size != self.n_atoms:
+            raise ValueError("one type per atom")
+        m = None if type_mass is None else np.ascontiguousarray(np.asarray(type_mass,
+                                                                             dtype=np.float64))
+        _check(lib().md_set_types(self._h, t.ctypes.data_as(C.c_void_p),
+                                  None if m is None else m.ctypes.data_as(C.c_void_p)),
+               "md_set_types")
 
     def close(self):
         if getattr(self, "_h", None):

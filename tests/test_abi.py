@@ -51,3 +51,34 @@ def test_strerror_and_host_checks():
     assert L.md_create(C.byref(s), C.byref(bad.s), C.byref(h)) == md.MD_ERR_ARG
     assert L.md_create(C.byref(s), C.byref(pot.s), None) == md.MD_ERR_ARG
     assert L.md_step(None, 1, None) == md.MD_ERR_ARG
+
+
+def test_several_species_descriptor_checks():
+    """Several-species descriptors are checked on the host: spline kind only,
+    at most 32 species, V and rho on one grid, V^(ab) = V^(ba)."""
+    from paper_1212_6332_amd import md, workloads as W
+    L = md.lib()
+    wl = W.alloy(ncell=2)
+    off = np.array([0, wl.n_atoms], dtype=np.int64)
+    bl = np.array([5.0])                   # too small a box: MD_ERR_BOX once the potential passes
+    s = md.md_system(n_boxes=1, max_neighbors=0, box_offset=off.ctypes.data,
+                     box_len=bl.ctypes.data, mass=63.546, dt=1.0, skin=0.3)
+    h = C.c_void_p()
+    good = md._PotHolder(wl.pot)
+    assert good.s.n_types == 2 and good.s.n_tab[0] == wl.pot.tables[0].shape[1]
+    assert L.md_create(C.byref(s), C.byref(good.s), C.byref(h)) == md.MD_ERR_BOX
+    bad = md._PotHolder(wl.pot)
+    bad.s.n_types = 33
+    assert L.md_create(C.byref(s), C.byref(bad.s), C.byref(h)) == md.MD_ERR_ARG
+    bad = md._PotHolder(wl.pot)
+    bad.s.hi[1] = bad.s.hi[1] + 0.5
+    assert L.md_create(C.byref(s), C.byref(bad.s), C.byref(h)) == md.MD_ERR_ARG
+    smtb = md._PotHolder(W.smtb_cu())
+    smtb.s.n_types = 2
+    assert L.md_create(C.byref(s), C.byref(smtb.s), C.byref(h)) == md.MD_ERR_ARG
+    V, R, F = (np.array(t) for t in wl.pot.tables)
+    V[1, 7, 0] += 1e-3                     # V^(01) != V^(10)
+    asym = W.Potential(kind=W.POT_SPLINE, rc=wl.pot.rc, tables=(V, R, F), lo=wl.pot.lo,
+                       hi=wl.pot.hi, n_types=2)
+    assert L.md_create(C.byref(s), C.byref(md._PotHolder(asym).s), C.byref(h)) == md.MD_ERR_ARG
+    assert not h.value
