@@ -101,7 +101,8 @@ __device__ __forceinline__ double dens(const Pot &p, double r, unsigned &bad)
         double u = r - p.d;
         return r < p.d ? u * u : 0.0;
     } else if constexpr (KIND == MD_POT_SMTB) {
-        return exp(fma(p.af, r, p.bf));
+        // the SMTB constants are stored in base 2: rho = 2^(af r + bf)
+        return exp2(fma(p.af, r, p.bf));
     } else {
         double s, ds;
         table_eval(p.tab[1], r, s, ds, bad);
@@ -123,11 +124,12 @@ __device__ __forceinline__ void pair_terms(const Pot &p, double r, double &dfr, 
         v = in ? w * w * poly : 0.0;
         dv = in ? w * fma(w, dpoly, 2.0 * poly) : 0.0;
     } else if constexpr (KIND == MD_POT_SMTB) {
-        double ef = exp(fma(p.af, r, p.bf));
-        double ev = exp(fma(p.av, r, p.bv));
-        dfr = p.af * ef;
+        // base-2 exponents; afn, avn are the slopes of ln rho and ln V
+        double ef = exp2(fma(p.af, r, p.bf));
+        double ev = exp2(fma(p.av, r, p.bv));
+        dfr = p.afn * ef;
         v = ev;
-        dv = p.av * ev;
+        dv = p.avn * ev;
     } else {
         double s;
         table_eval(p.tab[1], r, s, dfr, bad);

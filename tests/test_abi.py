@@ -82,3 +82,19 @@ def test_several_species_descriptor_checks():
                        hi=wl.pot.hi, n_types=2)
     assert L.md_create(C.byref(s), C.byref(md._PotHolder(asym).s), C.byref(h)) == md.MD_ERR_ARG
     assert not h.value
+
+
+def test_empty_box_and_size_limit_are_refused():
+    """A box with fewer than two atoms, and 2^27 atoms or more, are refused on
+    the host (MD_ERR_ARG) before any device call."""
+    from paper_1212_6332_amd import md, workloads as W
+    L = md.lib()
+    pot = md._PotHolder(W.smtb_cu())
+    h = C.c_void_p()
+    for off in (np.array([0, 1], dtype=np.int64), np.array([0, 0], dtype=np.int64),
+                np.array([0, 1 << 27], dtype=np.int64)):
+        bl = np.array([400.0])
+        s = md.md_system(n_boxes=1, max_neighbors=0, box_offset=off.ctypes.data,
+                         box_len=bl.ctypes.data, mass=63.546, dt=1.0, skin=0.3)
+        assert L.md_create(C.byref(s), C.byref(pot.s), C.byref(h)) == md.MD_ERR_ARG
+        assert not h.value

@@ -60,6 +60,31 @@ def test_batched_matches_oracle(block):
     assert rel(v, V) < 1e-9
 
 
+def smtb_boxes(ncells=(4, 5, 6, 4, 7)):
+    """Several SMTB Cu boxes of different sizes (the analytic potential)."""
+    wls = [W.fcc4m(ncell=n) for n in ncells]
+    off = np.concatenate([[0], np.cumsum([w.n_atoms for w in wls])]).astype(np.int64)
+    return W.Workload(name="smtb_boxes", box_offset=off,
+                      box_len=np.concatenate([w.box_len for w in wls]),
+                      pos=np.concatenate([w.pos for w in wls]),
+                      vel=np.concatenate([w.vel for w in wls]), mass=wls[0].mass, dt=1.0,
+                      skin=0.3, pot=wls[0].pot, steps=0)
+
+
+@pytest.mark.parametrize("batched", [True, False])
+def test_smtb_boxes_match_oracle(batched):
+    """The analytic SMTB potential in the persistent stepper (which evaluates
+    its exponentials itself) and in the merged-box kernels, per box against
+    the oracle."""
+    wl = smtb_boxes()
+    nsteps = 25
+    p, v, flags, steps = run_batch(wl, nsteps, batched=batched)
+    assert flags == 0 and steps == nsteps
+    P, V = oracle_batch(wl, nsteps)
+    assert np.abs(wrapped_diff(p, P, wl)).max() < 1e-10
+    assert rel(v, V) < 1e-9
+
+
 def test_batched_equals_merged_box_path():
     wl = W.batch2048(n_boxes=32)
     a = run_batch(wl, 30, batched=True)
