@@ -60,23 +60,29 @@ def test_batched_matches_oracle(block):
     assert rel(v, V) < 1e-9
 
 
-def smtb_boxes(ncells=(4, 5, 6, 4, 7)):
-    """Several SMTB Cu boxes of different sizes (the analytic potential)."""
-    wls = [W.fcc4m(ncell=n) for n in ncells]
+def analytic_boxes(make, ncells):
+    """Several boxes of one analytic potential, of different sizes."""
+    wls = [make(n) for n in ncells]
     off = np.concatenate([[0], np.cumsum([w.n_atoms for w in wls])]).astype(np.int64)
-    return W.Workload(name="smtb_boxes", box_offset=off,
+    return W.Workload(name="analytic_boxes", box_offset=off,
                       box_len=np.concatenate([w.box_len for w in wls]),
                       pos=np.concatenate([w.pos for w in wls]),
                       vel=np.concatenate([w.vel for w in wls]), mass=wls[0].mass, dt=1.0,
                       skin=0.3, pot=wls[0].pot, steps=0)
 
 
+BOXES = {"smtb": (lambda n: W.fcc4m(ncell=n), (4, 5, 6, 4, 7)),
+         "fs": (lambda n: W.fs256(ncell=n), (3, 4, 5, 3, 6))}
+
+
+@pytest.mark.parametrize("kind", list(BOXES))
 @pytest.mark.parametrize("batched", [True, False])
-def test_smtb_boxes_match_oracle(batched):
-    """The analytic SMTB potential in the persistent stepper (which evaluates
-    its exponentials itself) and in the merged-box kernels, per box against
-    the oracle."""
-    wl = smtb_boxes()
+def test_analytic_boxes_match_oracle(kind, batched):
+    """The analytic potentials (SMTB, FS) in the persistent stepper (which
+    evaluates them itself) and in the merged-box kernels, per box against the
+    oracle."""
+    make, ncells = BOXES[kind]
+    wl = analytic_boxes(make, ncells)
     nsteps = 25
     p, v, flags, steps = run_batch(wl, nsteps, batched=batched)
     assert flags == 0 and steps == nsteps

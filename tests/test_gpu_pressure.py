@@ -99,6 +99,33 @@ def test_barostat_trajectory_matches_oracle(name, nsteps):
     assert builds == 1 + nreb
 
 
+def test_barostat_several_boxes_match_oracle():
+    """Three boxes, compressed by different amounts, each scaled by its own
+    pressure (eq. 5 per box) in the merged-box kernels: box edges, positions
+    and velocities against the oracle box by box."""
+    parts = [squeezed(W.fcc4m(ncell=n), s) for n, s in ((4, 0.98), (5, 0.99), (4, 1.01))]
+    off = np.concatenate([[0], np.cumsum([w.n_atoms for w in parts])]).astype(np.int64)
+    wl = W.Workload(name="baro_boxes", box_offset=off,
+                    box_len=np.concatenate([w.box_len for w in parts]),
+                    pos=np.concatenate([w.pos for w in parts]),
+                    vel=np.concatenate([w.vel for w in parts]), mass=parts[0].mass, dt=1.0,
+                    skin=0.3, pot=parts[0].pot, steps=0)
+    nsteps, tau, beta = 30, 100.0, 1.0
+    x, v, L, (flags, builds, steps), pr = run_barostat(wl, nsteps, 0.0, tau, beta)
+    assert flags == 0 and steps == nsteps
+    for b, s, L0 in O.boxes(wl):
+        xo, vo, Lo, pro, nreb = O.vv_baro(O.wrap(wl.pos[s], L0), wl.vel[s], L0, O.Pot(wl.pot),
+                                          wl.mass, wl.dt, wl.skin, nsteps, 0.0, tau, beta)
+        assert abs(L[b] - Lo) <= 1e-13 * Lo
+        d = x[s] - xo
+        d -= Lo * np.round(d / Lo)
+        assert np.abs(d).max() < 1e-10
+        assert np.abs(v[s] - vo).max() <= 1e-9 * np.abs(vo).max()
+        assert abs(pr[b] - pro[-1]) <= 1e-10 * abs(pro[-1])
+    # compressed boxes expand, the stretched one shrinks
+    assert L[0] > wl.box_len[0, 0] and L[2] < wl.box_len[2, 0]
+
+
 def test_barostat_graph_equals_direct_launches():
     wl = squeezed(W.fcc4m(ncell=4), 0.98)
     a = run_barostat(wl, 31, 0.0, 100.0, 1.0, use_graph=1)
