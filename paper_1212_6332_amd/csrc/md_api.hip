@@ -107,6 +107,7 @@ int upload_potential(Ctx &c, const md_potential *p, hipStream_t s, bool first)
     if (p->kind == MD_POT_FS) {
         q.kind = MD_POT_FS;
         q.nt = 1;
+        q.pair = nullptr;
         q.c = p->params[0];
         q.d = p->params[1];
         q.c0 = p->params[2];
@@ -116,6 +117,7 @@ int upload_potential(Ctx &c, const md_potential *p, hipStream_t s, bool first)
     } else if (p->kind == MD_POT_SMTB) {
         q.kind = MD_POT_SMTB;
         q.nt = 1;
+        q.pair = nullptr;
         double A = p->params[0], xi = p->params[1], pp = p->params[2], qq = p->params[3],
                r0 = p->params[4];
         if (!(A > 0.0 && xi > 0.0 && r0 > 0.0 && pp > 0.0 && qq > 0.0)) return MD_ERR_ARG;
@@ -179,6 +181,10 @@ int upload_potential(Ctx &c, const md_potential *p, hipStream_t s, bool first)
             q.tab[k].inv_h = nint / (p->hi[k] - p->lo[k]);
             off += c.tab_len[k];
         }
+        // the force pass reads V and rho of one interval together when they share a grid
+        const bool shared = q.tab[0].n == q.tab[1].n && p->lo[0] == p->lo[1] && p->hi[0] == p->hi[1];
+        if (shared && !c.pair_tab) ALLOC(c.pair_tab, (size_t)(T > 1 ? 16 : 8) * T * T * q.tab[0].n);
+        q.pair = shared ? c.pair_tab : nullptr;
         if (p->kind == MD_POT_SPLINE) {
             off = 0;
             for (int k = 0; k < 3; ++k) {
@@ -186,6 +192,7 @@ int upload_potential(Ctx &c, const md_potential *p, hipStream_t s, bool first)
                                        hipMemcpyHostToDevice, s));
                 off += c.tab_len[k];
             }
+            launch_pair_tables(c, s);
         } else {
             for (int k = 0; k < 3; ++k)
                 HIP_TRY(hipMemcpyAsync(c.theta + (size_t)k * c.n_theta, p->tab[k],

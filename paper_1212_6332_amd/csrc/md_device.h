@@ -123,6 +123,19 @@ __device__ __forceinline__ void pair_terms(const Pot &p, double r, double &dfr, 
         dfr = p.afn * ef;
         v = ev;
         dv = p.avn * ev;
+    } else if (p.pair) {
+        // one interval of V and rho, 64 contiguous bytes
+        const Table &t = p.tab[0];
+        double u = (r - t.lo) * t.inv_h;
+        int m = (int)floor(u);
+        if (!(r >= t.lo && r <= t.hi)) bad |= MD_FLAG_TABLE_RANGE;
+        m = m < 0 ? 0 : (m > t.n - 1 ? t.n - 1 : m);
+        double tt = u - (double)m;
+        const double2 *c = reinterpret_cast<const double2 *>(p.pair + 8 * (size_t)m);
+        double2 va = c[0], vb = c[1], fa = c[2], fb = c[3];
+        v = fma(tt, fma(tt, fma(tt, vb.y, vb.x), va.y), va.x);
+        dv = fma(tt, fma(tt, 3.0 * vb.y, 2.0 * vb.x), va.y) * t.inv_h;
+        dfr = fma(tt, fma(tt, 3.0 * fb.y, 2.0 * fb.x), fa.y) * t.inv_h;
     } else {
         double s;
         table_eval(p.tab[1], r, s, dfr, bad);
@@ -180,16 +193,22 @@ __device__ __forceinline__ double dens_typed(const Pot &p, double r, int a, int 
     return s;
 }
 
-// rho^(ab)'(r), rho^(ba)'(r), V^(ab)(r), V^(ab)'(r) on the shared r grid.
+// rho^(ab)'(r), rho^(ba)'(r), V^(ab)(r), V^(ab)'(r) on the shared r grid,
+// from the interleaved table (one 128-byte line per pair and interval).
 __device__ __forceinline__ void pair_terms_typed(const Pot &p, double r, int a, int b,
                                                  double &dab, double &dba, double &v, double &dv,
                                                  unsigned &bad)
 {
     int m;
-    double tt = table_locate(p.tab[0], r, m, bad), s;
-    table_cubic(p.tab[0], a * p.nt + b, m, tt, v, dv);
-    table_cubic(p.tab[1], a * p.nt + b, m, tt, s, dab);
-    table_cubic(p.tab[1], b * p.nt + a, m, tt, s, dba);
+    const Table &t = p.tab[0];
+    double tt = table_locate(t, r, m, bad);
+    const double2 *c =
+        reinterpret_cast<const double2 *>(p.pair + 16 * ((size_t)(a * p.nt + b) * t.n + m));
+    double2 va = c[0], vb = c[1], aa = c[2], ab = c[3], ba = c[4], bb = c[5];
+    v = fma(tt, fma(tt, fma(tt, vb.y, vb.x), va.y), va.x);
+    dv = fma(tt, fma(tt, 3.0 * vb.y, 2.0 * vb.x), va.y) * t.inv_h;
+    dab = fma(tt, fma(tt, 3.0 * ab.y, 2.0 * ab.x), aa.y) * t.inv_h;
+    dba = fma(tt, fma(tt, 3.0 * bb.y, 2.0 * bb.x), ba.y) * t.inv_h;
 }
 
 // F^(a)(rho), F^(a)'(rho).

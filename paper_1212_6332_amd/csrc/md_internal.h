@@ -50,6 +50,10 @@ struct Pot {
     double av, bv, af, bf, bvd, bfd, avn, afn;
     double ec[12];                     // kExpPoly[m] ln(2)^m, kernel arguments (scalar registers)
     Table tab[3];                      // V(r), rho(r), F(rho)
+    // the force pass's r-grid tables interleaved per interval m (null when the
+    // V and rho grids differ): one species [V | rho] (8 doubles), several
+    // [V^(ab) | rho^(ab) | rho^(ba) | 0] (16 doubles, index (a nt + b) n + m)
+    const double *pair;
     int nt;                            // species; with nt > 1 each Table holds nt*nt (V, rho)
                                        // or nt (F) tables back to back, table a*nt + b
 };
@@ -145,6 +149,7 @@ struct Ctx;
 
 // Launchers (md_kernels.hip).
 void launch_set_state(Ctx &c, const double *pos, const double *vel, hipStream_t s);
+void launch_pair_tables(Ctx &c, hipStream_t s);
 void launch_refresh_types(Ctx &c, hipStream_t s);
 void launch_get_state(Ctx &c, double *pos, double *vel, hipStream_t s);
 void launch_build(Ctx &c, bool gated, hipStream_t s);
@@ -196,6 +201,7 @@ struct Ctx {
     std::vector<int> tab_len;          // doubles per table on the device
     double *tables = nullptr;          // device, 3 tables back to back
     double *theta = nullptr;           // device copy of B-spline coefficients [3K]
+    double *pair_tab = nullptr;        // interleaved r-grid tables (Pot::pair)
 
     // host mirrors of the box geometry
     std::vector<int64_t> box_off;

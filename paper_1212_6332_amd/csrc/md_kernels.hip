@@ -871,6 +871,34 @@ __global__ void k_bspline_tables(int K, const double *__restrict__ theta, double
     o[3] = (-t0 + 3.0 * t1 - 3.0 * t2 + t3) / 6.0;
 }
 
+// Interleaved r-grid tables of the force pass (Pot::pair): thread g fills
+// interval m of table pair ab = g / n.
+__global__ void k_pair_tables(int n, int T, const double *__restrict__ V,
+                              const double *__restrict__ R, double *__restrict__ out)
+{
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= T * T * n) return;
+    int ab = g / n, m = g % n;
+    const double *v = V + 4 * (size_t)g, *rab = R + 4 * (size_t)g;
+    if (T == 1) {
+        double *o = out + 8 * (size_t)m;
+        for (int k = 0; k < 4; ++k) {
+            o[k] = v[k];
+            o[4 + k] = rab[k];
+        }
+        return;
+    }
+    int a = ab / T, b = ab % T;
+    const double *rba = R + 4 * ((size_t)(b * T + a) * n + m);
+    double *o = out + 16 * (size_t)g;
+    for (int k = 0; k < 4; ++k) {
+        o[k] = v[k];
+        o[4 + k] = rab[k];
+        o[8 + k] = rba[k];
+        o[12 + k] = 0.0;
+    }
+}
+
 inline int grid_for(int64_t n, int block = kBlock) { return (int)((n + block - 1) / block); }
 
 template <int KIND, bool MULTI>
@@ -1067,6 +1095,15 @@ void launch_bspline_tables(Ctx &c, const double *theta, hipStream_t s)
 {
     int K = c.n_theta;
     k_bspline_tables<<<grid_for(3 * (K - 3)), kBlock, 0, s>>>(K, theta, c.tables);
+    launch_pair_tables(c, s);
+}
+
+void launch_pair_tables(Ctx &c, hipStream_t s)
+{
+    if (!c.pot.pair) return;
+    const int n = c.pot.tab[0].n, T = c.pot.nt;
+    k_pair_tables<<<grid_for((int64_t)T * T * n), kBlock, 0, s>>>(n, T, c.pot.tab[0].c,
+                                                                 c.pot.tab[1].c, c.pair_tab);
 }
 
 }  // namespace mdk
