@@ -36,13 +36,14 @@ FORCE_KERNEL = "k_tile_force<2, false, 1>"
 # every list entry costs the separation (3 differences), r^2 (1 multiply,
 # 2 fma) and the cutoff compare; every pair inside the cutoff costs 1/r and r
 # (estimate, one third-order correction, one multiply: 7) and, per
-# exponential 2^t, its argument (1), reduction (3), degree-11 polynomial (11)
-# and scaling (1); the force pass takes two exponentials and assembles
-# (F'_i + F'_j) rho' + V' and the three force components (6), the density
-# pass takes one exponential and one accumulation.
+# exponential 2^t, its argument (1), reduction (3), degree-10 polynomial (10,
+# the lowest degree within a few units in the last place) and scaling (1);
+# the force pass takes two exponentials and assembles (F'_i + F'_j) rho' + V'
+# and the three force components (6), the density pass takes one exponential
+# and one accumulation.
 OPS_ENTRY = 7
-OPS_FORCE_PAIR = 7 + 2 * 16 + 6
-OPS_DENSITY_PAIR = 7 + 16 + 1
+OPS_FORCE_PAIR = 7 + 2 * 15 + 6
+OPS_DENSITY_PAIR = 7 + 15 + 1
 
 
 def force_pass_bytes(n_atoms, mean_list):

@@ -144,7 +144,7 @@ int upload_potential(Ctx &c, const md_potential *p, hipStream_t s, bool first)
                 if (!(std::fabs(t) <= 1000.0)) return MD_ERR_ARG;
         static_assert(kExpPoly[0] == 1.0, "leading exp coefficient");
         long double w = 1.0L;
-        for (int m = 0; m < 12; ++m, w *= ln2) q.ec[m] = (double)(kExpPoly[m] * w);
+        for (int m = 0; m <= kExpDeg; ++m, w *= ln2) q.ec[m] = (double)(kExpPoly[m] * w);
     } else {
         const int T = std::max(1, (int)p->n_types);
         q.kind = T > 1 ? kTyped : MD_POT_SPLINE;

@@ -44,9 +44,9 @@ __device__ __forceinline__ double exp2_fast(double t, const Pot &p)
     double s = t + shifter;
     int k = __double2loint(s);
     double f = t - (s - shifter);
-    double q = fma(p.ec[11], f, p.ec[10]);
+    double q = fma(p.ec[kExpDeg], f, p.ec[kExpDeg - 1]);
 #pragma unroll
-    for (int m = 9; m >= 1; --m) q = fma(q, f, p.ec[m]);
+    for (int m = kExpDeg - 2; m >= 1; --m) q = fma(q, f, p.ec[m]);
     q = fma(q, f, 1.0);
     return ldexp(q, k);
 }
@@ -68,7 +68,7 @@ __device__ __forceinline__ Pot pinned(const Pot &p)
         pin_vector(q.bf);
         pin_vector(q.bvd);
         pin_vector(q.bfd);
-        pin_vector(q.ec[10]);
+        pin_vector(q.ec[kExpDeg - 1]);
     }
     return q;
 }

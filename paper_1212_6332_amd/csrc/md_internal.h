@@ -28,16 +28,16 @@ struct Table {
 };
 
 // exp(r) ~ sum_k kExpPoly[k] r^k on |r| <= 0.3466 (just above ln(2)/2, so
-// 2^f = exp(f ln 2) for |f| <= 1/2): the
-// degree-11 polynomial interpolating exp at the 12 Chebyshev nodes of that
-// interval, computed in extended precision; with its coefficients rounded to
-// double its relative error is below 3e-17.  The two leading coefficients
-// round to exactly 1.
-constexpr double kExpPoly[12] = {
-    1.0, 1.0, 0.50000000000000189, 0.16666666666666452, 0.041666666666488585,
-    0.008333333333392973, 0.0013888888952158077, 0.0001984126979465664,
-    2.480148565207557e-05, 2.7557294295755615e-06, 2.7632581262081151e-07,
-    2.5099509922947443e-08};
+// 2^f = exp(f ln 2) for |f| <= 1/2): the degree-10 polynomial interpolating
+// exp at the 11 Chebyshev nodes of that interval, computed in 60-digit
+// decimal arithmetic; with its coefficients rounded to double its relative
+// error is below 3.3e-16 (about three units in the last place).  The leading
+// coefficient rounds to exactly 1.
+constexpr int kExpDeg = 10;
+constexpr double kExpPoly[kExpDeg + 1] = {
+    1.0, 1.0000000000000067, 0.5000000000000006, 0.16666666666554406, 0.04166666666657314,
+    0.008333333385667814, 0.0013888888932488625, 0.00019841170270400204, 2.480150434696448e-05,
+    2.7640180812804505e-06, 2.762635725527078e-07};
 
 // Potential as the kernels see it.  B-spline potentials are converted to
 // per-interval tables on the device and evaluated as kind MD_POT_SPLINE.
@@ -48,7 +48,7 @@ struct Pot {
     // SMTB in base 2: V = 2^(av r + bv), rho = 2^(af r + bf), -V' = 2^(av r + bvd),
     // -rho' = 2^(af r + bfd); avn, afn are the slopes of ln V and ln rho
     double av, bv, af, bf, bvd, bfd, avn, afn;
-    double ec[12];                     // kExpPoly[m] ln(2)^m, kernel arguments (scalar registers)
+    double ec[kExpDeg + 1];            // kExpPoly[m] ln(2)^m, kernel arguments (scalar registers)
     Table tab[3];                      // V(r), rho(r), F(rho)
     // the force pass's r-grid tables interleaved per interval m (null when the
     // V and rho grids differ): one species [V | rho] (8 doubles), several
