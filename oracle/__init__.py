@@ -301,6 +301,32 @@ def vv_baro(pos, vel, L, pot: Pot, mass, dt, skin, nsteps, p0, tau, beta, maxn=2
     return (np.stack([x, y, z], axis=1), np.stack([vx, vy, vz], axis=1), Lc.value, pr, nreb)
 
 
+def vv_frozen(pos, vel, L, pot: Pot, mass, dt, skin, nsteps, frozen, maxn=256, energies=True):
+    """Velocity Verlet with frozen atoms (atom states, Section 3.1): frozen
+    atoms keep zero velocity and stay in place.  Returns (pos, vel, epot,
+    ekin, rebuilds)."""
+    L_ = lib()
+    if not hasattr(L_, "_frozen_ready"):
+        i32, i64, dbl = C.c_int, C.c_int64, C.c_double
+        L_.orc_vv_frozen.argtypes = [i64, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p, dbl,
+                                     C.c_void_p, dbl, dbl, dbl, i32, i32, C.c_void_p,
+                                     C.c_void_p, C.c_void_p]
+        L_.orc_vv_frozen.restype = i32
+        L_._frozen_ready = True
+    x, y, z = _xyz(pos)
+    vx, vy, vz = _xyz(vel)
+    fr = np.ascontiguousarray(frozen, dtype=np.uint8)
+    ep = np.zeros(nsteps + 1)
+    ek = np.zeros(nsteps + 1)
+    nreb = L_.orc_vv_frozen(x.size, x, y, z, vx, vy, vz, float(L), pot.ref, float(mass),
+                            float(dt), float(skin), int(nsteps), int(maxn), fr.ctypes.data,
+                            ep.ctypes.data if energies else None,
+                            ek.ctypes.data if energies else None)
+    if nreb < 0:
+        raise ValueError("neighbour row overflow in orc_vv_frozen")
+    return (np.stack([x, y, z], axis=1), np.stack([vx, vy, vz], axis=1), ep, ek, nreb)
+
+
 def vv_thermo(pos, vel, L, pot: Pot, mass, dt, skin, nsteps, te, tau, maxn=256, energies=True):
     """Velocity Verlet with the electron-gas friction of eq. (4) (tau <= 0: none).
     Returns (pos, vel, epot, ekin, rebuilds)."""

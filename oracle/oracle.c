@@ -723,6 +723,68 @@ int orc_vv(int64_t n, double *x, double *y, double *z, double *vx, double *vy, d
     return bad ? -1 : rebuilds;
 }
 
+/* ------------------------------------------------------------- atom states */
+
+/*
+ * Atom states (Section 3.1): an atom marked frozen is not allowed to move.
+ * It keeps zero velocity (its velocity is zeroed at the start and after
+ * every kick), so the drift leaves it in place; it still exerts and feels
+ * forces, which act on the free atoms.  Otherwise as orc_vv.
+ */
+int orc_vv_frozen(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
+                  double L, const orc_pot *p, double mass, double dt, double skin, int nsteps,
+                  int maxn, const uint8_t *frozen, double *epot, double *ekin)
+{
+    orc_md s = {n, x, y, z, vx, vy, vz, L, mass, dt, skin, p, maxn};
+    double rlist = orc_rlist(p->rc, skin, L);
+    double half_skin = 0.5 * (rlist - p->rc);
+    size_t nb = sizeof(double) * (n > 0 ? n : 1);
+    int32_t *count = (int32_t *)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+    int32_t *ids = (int32_t *)malloc(sizeof(int32_t) * (n > 0 ? n : 1) * maxn);
+    double *xr = malloc(nb), *yr = malloc(nb), *zr = malloc(nb);
+    double *rho = malloc(nb), *F = malloc(nb), *Fp = malloc(nb);
+    double *fx = malloc(nb), *fy = malloc(nb), *fz = malloc(nb), *e = malloc(nb);
+    for (int64_t i = 0; i < n; ++i)
+        if (frozen[i]) vx[i] = vy[i] = vz[i] = 0.0;
+    int rebuilds = 0, bad = 0;
+    bad |= md_rebuild(&s, rlist, count, ids, xr, yr, zr);
+    double E = md_forces(&s, count, ids, rho, F, Fp, fx, fy, fz, e);
+    if (epot) epot[0] = E;
+    if (ekin) ekin[0] = md_kinetic(&s);
+    double c = 0.5 * dt * ORC_KAPPA / mass;
+    for (int step = 1; step <= nsteps; ++step) {
+        double worst = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            if (frozen[i]) continue;
+            vx[i] += c * fx[i];
+            vy[i] += c * fy[i];
+            vz[i] += c * fz[i];
+            x[i] += dt * vx[i];
+            y[i] += dt * vy[i];
+            z[i] += dt * vz[i];
+            double ddx = x[i] - xr[i], ddy = y[i] - yr[i], ddz = z[i] - zr[i];
+            double d2 = ddx * ddx + ddy * ddy + ddz * ddz;
+            if (d2 > worst) worst = d2;
+        }
+        if (worst > half_skin * half_skin) {
+            bad |= md_rebuild(&s, rlist, count, ids, xr, yr, zr);
+            ++rebuilds;
+        }
+        E = md_forces(&s, count, ids, rho, F, Fp, fx, fy, fz, e);
+        for (int64_t i = 0; i < n; ++i) {
+            if (frozen[i]) continue;
+            vx[i] += c * fx[i];
+            vy[i] += c * fy[i];
+            vz[i] += c * fz[i];
+        }
+        if (epot) epot[step] = E;
+        if (ekin) ekin[step] = md_kinetic(&s);
+    }
+    free(count); free(ids); free(xr); free(yr); free(zr);
+    free(rho); free(F); free(Fp); free(fx); free(fy); free(fz); free(e);
+    return bad ? -1 : rebuilds;
+}
+
 /* ---------------------------------------------------------------- thermostat */
 
 /*
