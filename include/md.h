@@ -229,6 +229,16 @@ int md_pressure(md_ctx *ctx, double *p_box, double *w_box, void *stream);
  * raises MD_FLAG_BOX_RANGE. */
 int md_set_barostat(md_ctx *ctx, double p0, double tau, double beta);
 
+/* Atom states (Section 3.1: some atoms are not allowed to move): frozen is a
+ * HOST array [N] in the original atom order, nonzero for an atom that is
+ * frozen; NULL (or all zero) frees every atom.  A frozen atom keeps zero
+ * velocity through every kick of md_step (its velocity is zeroed at once),
+ * so it never moves; it still takes part in the density and force passes
+ * and acts on the free atoms.  Refused (MD_ERR_ARG) while the barostat is
+ * on, and md_set_barostat refuses to switch on while an atom is frozen: the
+ * scaling of eq. (5) would move frozen atoms. */
+int md_set_frozen(md_ctx *ctx, const uint8_t *frozen);
+
 /* Species of the atoms (several-species contexts, n_types = T > 1): types is
  * a HOST array [N] in the original atom order with values in [0, T);
  * type_mass a host array [T] of masses (amu, > 0), or NULL for the system

@@ -592,6 +592,12 @@ int md_create(const md_system *sys, const md_potential *pot, md_ctx **out)
             return fail(MD_ERR_DEVICE);
     }
 
+    // atom states: flags in slot and original order (all free until md_set_frozen)
+    if ((rc = dev_alloc(c, &c.d_frozen, (size_t)N)) != MD_OK) return fail(rc);
+    if ((rc = dev_alloc(c, &c.d_frozen0, (size_t)N)) != MD_OK) return fail(rc);
+    if (hipMemset(c.d_frozen, 0, (size_t)N) != hipSuccess ||
+        hipMemset(c.d_frozen0, 0, (size_t)N) != hipSuccess)
+        return fail(MD_ERR_DEVICE);
     c.ntypes = std::max(1, (int)pot->n_types);
     if (c.ntypes > 1) {
         if ((rc = dev_alloc(c, &c.d_type0, (size_t)N)) != MD_OK) return fail(rc);
@@ -800,6 +806,7 @@ int md_set_barostat(md_ctx *h, double p0, double tau, double beta)
     if (tau > 0.0) {
         if (!std::isfinite(p0) || !std::isfinite(tau) || !(beta > 0.0) || !std::isfinite(beta))
             return MD_ERR_ARG;
+        if (c.any_frozen) return MD_ERR_ARG;  // scaling would move frozen atoms
         c.baro_on = true;
         c.baro_p0 = p0;
         c.baro_tau = tau;
@@ -817,6 +824,36 @@ int md_set_barostat(md_ctx *h, double p0, double tau, double beta)
             if (rc != MD_OK) return rc;
         }
     }
+    c.baro_mu_valid = false;
+    graph_reset(c);
+    return MD_OK;
+}
+
+int md_set_frozen(md_ctx *h, const uint8_t *frozen)
+{
+    if (!h) return MD_ERR_ARG;
+    Ctx &c = h->c;
+    bool any = false;
+    if (frozen)
+        for (int64_t i = 0; i < c.N && !any; ++i) any = frozen[i] != 0;
+    if (any && c.baro_on) return MD_ERR_ARG;
+    HIP_TRY(hipDeviceSynchronize());
+    if (any) {
+        std::vector<unsigned char> f(c.N);
+        for (int64_t i = 0; i < c.N; ++i) f[i] = frozen[i] ? 1 : 0;
+        HIP_TRY(hipMemcpy(c.d_frozen0, f.data(), (size_t)c.N, hipMemcpyHostToDevice));
+        c.st.frozen = c.d_frozen;
+        c.st.frozen0 = c.d_frozen0;
+        if (c.state_set) {
+            // the slots' flags follow their original ids; frozen atoms stop
+            launch_refresh_frozen(c, nullptr);
+            HIP_TRY(hipDeviceSynchronize());
+        }
+    } else {
+        c.st.frozen = nullptr;
+        c.st.frozen0 = nullptr;
+    }
+    c.any_frozen = any;
     c.baro_mu_valid = false;
     graph_reset(c);
     return MD_OK;

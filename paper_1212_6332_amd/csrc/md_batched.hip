@@ -195,6 +195,7 @@ __global__ __launch_bounds__(T) void k_batched(BArgs a)
         double *vx = a.st.vx + off, *vy = a.st.vy + off, *vz = a.st.vz + off;
         double *fx = a.st.fx + off, *fy = a.st.fy + off, *fz = a.st.fz + off;
         double *xr = a.st.xr + off, *yr = a.st.yr + off, *zr = a.st.zr + off;
+        const unsigned char *frz = a.st.frozen ? a.st.frozen + off : nullptr;
         uint16_t *lst = a.list + (size_t)off * a.mn;
         int *cnt = a.count + off;
         unsigned bad = 0;
@@ -325,6 +326,7 @@ __global__ __launch_bounds__(T) void k_batched(BArgs a)
                     double uy = fma(a.kick, ay, vy[i]);
                     double uz = fma(a.kick, az, vz[i]);
                     if (a.th.on) friction_flow(a.th, ux, uy, uz);
+                    if (frz && frz[i]) ux = uy = uz = 0.0;
                     vx[i] = ux;
                     vy[i] = uy;
                     vz[i] = uz;
@@ -346,6 +348,7 @@ __global__ __launch_bounds__(T) void k_batched(BArgs a)
                 ux = fma(a.kick, fx[i], ux);
                 uy = fma(a.kick, fy[i], uy);
                 uz = fma(a.kick, fz[i], uz);
+                if (frz && frz[i]) ux = uy = uz = 0.0;
                 vx[i] = ux;
                 vy[i] = uy;
                 vz[i] = uz;

@@ -93,10 +93,20 @@ struct State {
     int *type;
     const int *type0;
     const double *tcoef;
+    // atom states (null when no atom is frozen): frozen flag of each slot and
+    // of each original atom
+    unsigned char *frozen;
+    const unsigned char *frozen0;
 };
 
 // Per-type coefficients (several species): [4 t + k], k as below.
 constexpr int kTcKick = 0, kTcFric = 1, kTcHalfM = 2;
+
+// Atom states: a frozen atom keeps zero velocity, so no drift moves it.
+__device__ __forceinline__ void hold(const State &st, int i, double &vx, double &vy, double &vz)
+{
+    if (st.frozen && st.frozen[i]) vx = vy = vz = 0.0;
+}
 
 // Half-kick factor and friction addend of atom i: those of its species in
 // several-species contexts, else the context's (already in kick and th).
@@ -151,6 +161,7 @@ struct Ctx;
 void launch_set_state(Ctx &c, const double *pos, const double *vel, hipStream_t s);
 void launch_pair_tables(Ctx &c, hipStream_t s);
 void launch_refresh_types(Ctx &c, hipStream_t s);
+void launch_refresh_frozen(Ctx &c, hipStream_t s);
 void launch_get_state(Ctx &c, double *pos, double *vel, hipStream_t s);
 void launch_build(Ctx &c, bool gated, hipStream_t s);
 void launch_density(Ctx &c, hipStream_t s);
@@ -247,6 +258,10 @@ struct Ctx {
     bool baro_mu_valid = false;        // d_baro holds the scale factors of the next step
     double baro_p0 = 0.0, baro_tau = 0.0, baro_beta = 0.0;
     double *d_baro = nullptr;          // per box: mu | strain | rlist | pressure | virial | kinetic | virial sum
+
+    // atom states
+    unsigned char *d_frozen = nullptr, *d_frozen0 = nullptr;
+    bool any_frozen = false;
 
     // several species
     int ntypes = 1;

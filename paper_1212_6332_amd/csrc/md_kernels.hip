@@ -143,6 +143,20 @@ __global__ void k_set_state(int N, const double *__restrict__ pos, const double 
     st.vz[i] = vel ? vel[3 * (size_t)i + 2] : 0.0;
     st.id[i] = i;
     if (st.type) st.type[i] = st.type0[i];
+    if (st.frozen) {
+        st.frozen[i] = st.frozen0[i];
+        if (st.frozen0[i]) st.vx[i] = st.vy[i] = st.vz[i] = 0.0;
+    }
+}
+
+// Frozen flag of every slot from its original id; frozen atoms stop.
+__global__ void k_refresh_frozen(int N, State st)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    unsigned char f = st.frozen0[st.id[i]];
+    st.frozen[i] = f;
+    if (f) st.vx[i] = st.vy[i] = st.vz[i] = 0.0;
 }
 
 // Species of every slot from its original id.
@@ -397,6 +411,7 @@ __global__ void k_commit(const unsigned *gate, int N, State st, Build bd)
     st.vz[q] = bd.svz[q];
     st.id[q] = bd.sid[q];
     if (st.type) st.type[q] = st.type0[bd.sid[q]];
+    if (st.frozen) st.frozen[q] = st.frozen0[bd.sid[q]];
 }
 
 // Full list of slot i.  r^2 = (dx*dx + dy*dy) + dz*dz with separate
@@ -627,6 +642,7 @@ __global__ __launch_bounds__(kBlock) void k_force(int N, State st, Boxes bx, NLi
         double vy = fma(kick, ay, st.vy[i]);
         double vz = fma(kick, az, st.vz[i]);
         if (th.on) friction_flow(th, vx, vy, vz);
+        hold(st, i, vx, vy, vz);
         st.vx[i] = vx;
         st.vy[i] = vy;
         st.vz[i] = vz;
@@ -651,6 +667,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(int N, State st, Boxes bx
         vx = fma(kick, st.fx[i], vx);
         vy = fma(kick, st.fy[i], vy);
         vz = fma(kick, st.fz[i], vz);
+        hold(st, i, vx, vy, vz);
         double x = fma(dt, vx, st.x[i]);
         double y = fma(dt, vy, st.y[i]);
         double z = fma(dt, vz, st.z[i]);
@@ -938,6 +955,11 @@ void launch_fill_u32(unsigned *p, int n, unsigned v, hipStream_t s)
 void launch_pack_positions(Ctx &c, hipStream_t s)
 {
     k_pack_positions<<<grid_for(c.N), kBlock, 0, s>>>((int)c.N, c.st);
+}
+
+void launch_refresh_frozen(Ctx &c, hipStream_t s)
+{
+    k_refresh_frozen<<<grid_for(c.N), kBlock, 0, s>>>((int)c.N, c.st);
 }
 
 void launch_refresh_types(Ctx &c, hipStream_t s)

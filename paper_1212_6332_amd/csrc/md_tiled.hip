@@ -677,11 +677,13 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
                 double vy = fma(ki, ay, v0y);
                 double vz = fma(ki, az, v0z);
                 if (thi.on) friction_flow(thi, vx, vy, vz);
+                hold(st, i, vx, vy, vz);
                 if constexpr (MODE == 2) {
                     if (thi.on) friction_flow(thi, vx, vy, vz);
                     vx = fma(ki, ax, vx);
                     vy = fma(ki, ay, vy);
                     vz = fma(ki, az, vz);
+                    hold(st, i, vx, vy, vz);
                     double x = fma(dt, vx, xi), y = fma(dt, vy, yi), z = fma(dt, vz, zi);
                     st.xo[i] = x;
                     st.yo[i] = y;

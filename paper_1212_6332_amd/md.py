@@ -75,6 +75,7 @@ _SIGS = {
     "md_get_box": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "md_set_thermostat": ([C.c_void_p, C.c_double, C.c_double], C.c_int),
     "md_set_types": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "md_set_frozen": ([C.c_void_p, C.c_void_p], C.c_int),
 }
 
 
@@ -169,6 +170,17 @@ class System:
         if getattr(W, "types", None) is not None and int(getattr(s.pot, "n_types", 1)) > 1:
             s.set_types(W.types, W.type_mass)
         return s
+
+    def set_frozen(self, frozen):
+        """Atom states: a nonzero entry (host array, original order) freezes that atom;
+        None frees every atom."""
+        if frozen is None:
+            _check(lib().md_set_frozen(self._h, None), "md_set_frozen")
+            return
+        f = np.ascontiguousarray(np.asarray(frozen, dtype=np.uint8))
+        if f.size != self.n_atoms:
+            raise ValueError("one flag per atom")
+        _check(lib().md_set_frozen(self._h, f.ctypes.data_as(C.c_void_p)), "md_set_frozen")
 
     def set_types(self, types, type_mass=None):
         """Species of every atom (host array, original order) and per-species masses."""
