@@ -11,12 +11,18 @@
  * over full Verlet neighbour lists built from periodic linked cells
  * (Section 3.2), driven by velocity Verlet.  Several independent periodic
  * boxes may share one context (the multiple-box scheme of Section 4.4).
+ * Around this path: the pressure of eq. (6) and the Berendsen barostat of
+ * eq. (5) (md_pressure, md_set_barostat), the electron-gas thermostat of
+ * eq. (4) (md_set_thermostat), several atom species with per-type-pair
+ * tables (n_types, md_set_types) and frozen atoms (md_set_frozen).
  *
  * Conventions for every entry point
  *   - Units: Angstrom, eV, fs, amu.  All floating point is IEEE double.
  *   - Per-atom input/output buffers are DEVICE pointers owned by the caller,
  *     in the caller's original atom order.  Vectors are packed [N][3]
  *     (x, y, z of atom 0, then atom 1, ...).  The library never frees them.
+ *     The per-atom settings of md_set_types and md_set_frozen are HOST
+ *     arrays, validated before they are copied.
  *   - `stream` is a hipStream_t passed as void* (NULL: the null stream).
  *     Calls are stream ordered and asynchronous unless stated otherwise.
  *   - Descriptors passed by pointer (md_system, md_potential) and the host

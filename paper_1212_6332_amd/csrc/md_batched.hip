@@ -59,7 +59,9 @@ struct Batch {
     int *count = nullptr;
     int nmax = 0, cmax = 0, grid = 0;
     size_t lds = 0;
+    int list_mn = 0;          // capacity the list storage was sized for
     bool list_valid = false;
+    bool prepared = false;    // later calls keep the caller's MD_OPT_BATCHED choice
 };
 
 __device__ __forceinline__ double min_image(double d, double L, double invL)
@@ -446,7 +448,8 @@ int batched_prepare(Ctx &c)
     // 16-bit local indices; LDS must hold one box
     bool feasible = nmax <= 65535 && cmax <= 65535 && b->lds <= (size_t)max_lds;
     c.batch_feasible = feasible;
-    c.batched = feasible;
+    c.batched = b->prepared ? (c.batched && feasible) : feasible;
+    b->prepared = true;
     if (!feasible) return MD_OK;
     if (b->lds > 65536) {
         if (c.pot.kind == MD_POT_FS) {
@@ -475,6 +478,9 @@ int batched_prepare(Ctx &c)
         c.allocs.push_back(b->order);
         c.allocs.push_back(b->queue);
         c.allocs.push_back(b->count);
+    }
+    {
+        // per-box descriptors from the current box edges (the barostat changes them)
         std::vector<BBox> hb(c.B);
         for (int i = 0; i < c.B; ++i) {
             double L = c.box_len[i], rl = c.box_rlist[i], half = 0.5 * (rl - c.pot.rc);
@@ -492,16 +498,19 @@ int batched_prepare(Ctx &c)
                 hipSuccess)
             return MD_ERR_DEVICE;
     }
-    // list storage follows the capacity (reallocated with it)
-    if (b->list) {
+    // list storage follows the capacity (reallocated when it changes)
+    if (b->list && b->list_mn != c.nl.mn) {
         auto it = std::find(c.allocs.begin(), c.allocs.end(), (void *)b->list);
         if (it != c.allocs.end()) c.allocs.erase(it);
         (void)hipFree(b->list);
         b->list = nullptr;
     }
-    if (hipMalloc(&b->list, sizeof(uint16_t) * (size_t)c.N * c.nl.mn) != hipSuccess)
-        return MD_ERR_NOMEM;
-    c.allocs.push_back(b->list);
+    if (!b->list) {
+        if (hipMalloc(&b->list, sizeof(uint16_t) * (size_t)c.N * c.nl.mn) != hipSuccess)
+            return MD_ERR_NOMEM;
+        c.allocs.push_back(b->list);
+        b->list_mn = c.nl.mn;
+    }
     b->list_valid = false;
     return MD_OK;
 }

@@ -126,6 +126,41 @@ def test_barostat_several_boxes_match_oracle():
     assert L[0] > wl.box_len[0, 0] and L[2] < wl.box_len[2, 0]
 
 
+def test_boxes_after_barostat_step_with_their_new_edges():
+    """Several boxes scaled by the barostat, which is then switched off: the
+    persistent multi-box stepper steps with the new box edges (it agrees with
+    the merged-box kernels, which read them on the device), and a caller's
+    choice of the merged kernels survives the switch."""
+    parts = [squeezed(W.fcc4m(ncell=n), s) for n, s in ((4, 0.98), (5, 0.985))]
+    off = np.concatenate([[0], np.cumsum([w.n_atoms for w in parts])]).astype(np.int64)
+    wl = W.Workload(name="baro_boxes", box_offset=off,
+                    box_len=np.concatenate([w.box_len for w in parts]),
+                    pos=np.concatenate([w.pos for w in parts]),
+                    vel=np.concatenate([w.vel for w in parts]), mass=parts[0].mass, dt=1.0,
+                    skin=0.3, pot=parts[0].pot, steps=0)
+    out = []
+    for batched in (1, 0):
+        S = md.System.from_workload(wl)
+        S.set_option(md.MD_OPT_BATCHED, batched)
+        S.set_state(wl.pos, wl.vel)
+        S.set_barostat(0.0, 50.0, 1.0)
+        S.step(30)
+        S.set_barostat(0.0, 0.0, 1.0)
+        assert S.get_option(md.MD_OPT_BATCHED) == batched
+        L = S.box()
+        S.step(30)
+        p, v = S.get_state()
+        assert S.status()[0] == 0
+        out.append((p.cpu().numpy(), v.cpu().numpy(), L))
+        S.close()
+    assert np.array_equal(out[0][2], out[1][2]) and np.all(out[0][2] > wl.box_len[:, 0])
+    d = out[0][0] - out[1][0]
+    Lr = np.repeat(out[0][2], np.diff(wl.box_offset))[:, None]
+    d -= Lr * np.round(d / Lr)
+    assert np.abs(d).max() < 1e-10
+    assert np.abs(out[0][1] - out[1][1]).max() <= 1e-9 * np.abs(out[1][1]).max()
+
+
 def test_barostat_graph_equals_direct_launches():
     wl = squeezed(W.fcc4m(ncell=4), 0.98)
     a = run_barostat(wl, 31, 0.0, 100.0, 1.0, use_graph=1)
