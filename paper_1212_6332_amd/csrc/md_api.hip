@@ -183,7 +183,8 @@ int upload_potential(Ctx &c, const md_potential *p, hipStream_t s, bool first)
         }
         // the force pass reads V and rho of one interval together when they share a grid
         const bool shared = q.tab[0].n == q.tab[1].n && p->lo[0] == p->lo[1] && p->hi[0] == p->hi[1];
-        if (shared && !c.pair_tab) ALLOC(c.pair_tab, (size_t)(T > 1 ? 16 : 8) * T * T * q.tab[0].n);
+        // sized at creation for the V grid, so a later potential with shared grids fits
+        if (first) ALLOC(c.pair_tab, (size_t)(T > 1 ? 16 : 8) * T * T * q.tab[0].n);
         q.pair = shared ? c.pair_tab : nullptr;
         if (p->kind == MD_POT_SPLINE) {
             off = 0;
