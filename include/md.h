@@ -32,8 +32,9 @@
  *     Conditions found by kernels (list overflow, table range, non-finite
  *     coordinates) set bits in a device status word read by md_status().
  *   - A context belongs to the device that was current at md_create(); it
- *     allocates its device workspace there, once.  No entry point allocates
- *     device memory after md_create() except md_set_max_neighbors().
+ *     allocates its device workspace there, once (or takes it from the
+ *     caller's block, md_create_in).  No entry point allocates device memory
+ *     after md_create() except md_set_max_neighbors().
  *   - One context must not be used from two host threads at once.
  */
 #ifndef MD_H
@@ -134,6 +135,22 @@ typedef struct {
  * (MD_ERR_ARG), requires box_len[b] > 2 rc for every box (MD_ERR_BOX),
  * uploads the potential, and allocates all device memory of the context. */
 int md_create(const md_system *sys, const md_potential *pot, md_ctx **out);
+
+/* Device bytes a context for these descriptors holds (*bytes): the size of
+ * the workspace md_create_in needs.  Computed by creating and destroying
+ * such a context (synchronous; needs that much free device memory). */
+int md_workspace_size(const md_system *sys, const md_potential *pot, size_t *bytes);
+
+/* As md_create, but every device buffer of the context (state in cell
+ * order, cells, neighbour list, densities, tables, flags, scratch) is carved
+ * from the caller's device workspace of `bytes` bytes (256-byte aligned,
+ * else MD_ERR_ARG; too small: MD_ERR_NOMEM).  The library then allocates no
+ * device memory for this context, ever: md_set_max_neighbors takes a new
+ * list from what remains of the workspace (MD_ERR_NOMEM when it does not
+ * fit) and the old one is not returned.  The caller frees the workspace
+ * after md_destroy. */
+int md_create_in(const md_system *sys, const md_potential *pot, void *workspace, size_t bytes,
+                 md_ctx **out);
 
 /* Free every device and host resource of the context. */
 void md_destroy(md_ctx *ctx);

@@ -30,11 +30,9 @@ template <class T>
 int dev_alloc(Ctx &c, T **p, size_t count)
 {
     void *q = nullptr;
-    if (count == 0) count = 1;
-    if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) return MD_ERR_NOMEM;
-    c.allocs.push_back(q);
+    int rc = ctx_alloc(c, &q, (count == 0 ? 1 : count) * sizeof(T));
     *p = static_cast<T *>(q);
-    return MD_OK;
+    return rc;
 }
 
 #define ALLOC(ptr, n)                          \
@@ -207,13 +205,18 @@ int upload_potential(Ctx &c, const md_potential *p, hipStream_t s, bool first)
     return MD_OK;
 }
 
+// The neighbour list at capacity mn; the previous list is released only once
+// the new one exists, so a failure leaves the context as it was.
 int alloc_list(Ctx &c, int mn)
 {
     mn = (mn + 3) / 4 * 4;  // rows are stored in groups of four
     if (mn > 65532) return MD_ERR_ARG;
+    int *idx = nullptr;
+    ALLOC(idx, (size_t)mn * c.N);
+    HIP_TRY(hipMemset(idx, 0, sizeof(int) * (size_t)mn * c.N));
+    ctx_free(c, c.nl.idx);
+    c.nl.idx = idx;
     c.nl.mn = mn;
-    ALLOC(c.nl.idx, (size_t)mn * c.N);
-    HIP_TRY(hipMemset(c.nl.idx, 0, sizeof(int) * (size_t)mn * c.N));
     return MD_OK;
 }
 
@@ -402,7 +405,12 @@ const char *md_strerror(int code)
     return "unknown error";
 }
 
-int md_create(const md_system *sys, const md_potential *pot, md_ctx **out)
+}  // extern "C"
+
+namespace {
+
+int create_impl(const md_system *sys, const md_potential *pot, md_ctx **out, void *workspace,
+                size_t workspace_bytes)
 {
     if (!out) return MD_ERR_ARG;
     *out = nullptr;
@@ -427,6 +435,10 @@ int md_create(const md_system *sys, const md_potential *pot, md_ctx **out)
         md_destroy(h);
         return code;
     };
+    if (workspace) {
+        c.arena = static_cast<char *>(workspace);
+        c.arena_size = workspace_bytes;
+    }
     if (hipGetDevice(&c.device) != hipSuccess) return fail(MD_ERR_DEVICE);
     c.N = N;
     c.B = B;
@@ -627,6 +639,71 @@ int md_create(const md_system *sys, const md_potential *pot, md_ctx **out)
     *out = h;
     return MD_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+int md_create(const md_system *sys, const md_potential *pot, md_ctx **out)
+{
+    return create_impl(sys, pot, out, nullptr, 0);
+}
+
+int md_workspace_size(const md_system *sys, const md_potential *pot, size_t *bytes)
+{
+    if (!bytes) return MD_ERR_ARG;
+    *bytes = 0;
+    md_ctx *h = nullptr;
+    int rc = create_impl(sys, pot, &h, nullptr, 0);
+    if (rc != MD_OK) return rc;
+    *bytes = h->c.alloc_bytes;
+    md_destroy(h);
+    return MD_OK;
+}
+
+int md_create_in(const md_system *sys, const md_potential *pot, void *workspace, size_t bytes,
+                 md_ctx **out)
+{
+    if (out) *out = nullptr;
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return MD_ERR_ARG;
+    return create_impl(sys, pot, out, workspace, bytes);
+}
+
+}  // extern "C"
+
+namespace mdk {
+
+int ctx_alloc(Ctx &c, void **p, size_t bytes)
+{
+    bytes = (bytes + 255) / 256 * 256;
+    if (bytes == 0) bytes = 256;
+    if (c.arena) {
+        if (bytes > c.arena_size - c.arena_used) return MD_ERR_NOMEM;
+        *p = c.arena + c.arena_used;
+        c.arena_used += bytes;
+    } else {
+        void *q = nullptr;
+        if (hipMalloc(&q, bytes) != hipSuccess) return MD_ERR_NOMEM;
+        c.allocs.push_back(q);
+        *p = q;
+    }
+    c.alloc_bytes += bytes;
+    return MD_OK;
+}
+
+void ctx_free(Ctx &c, void *p)
+{
+    if (!p || c.arena) return;  // workspace blocks go back with the workspace
+    auto it = std::find(c.allocs.begin(), c.allocs.end(), p);
+    if (it != c.allocs.end()) {
+        (void)hipFree(p);
+        c.allocs.erase(it);
+    }
+}
+
+}  // namespace mdk
+
+extern "C" {
 
 void md_destroy(md_ctx *h)
 {
@@ -958,12 +1035,6 @@ int md_set_max_neighbors(md_ctx *h, int32_t mn)
     if (!h || mn < 1) return MD_ERR_ARG;
     Ctx &c = h->c;
     HIP_TRY(hipDeviceSynchronize());
-    auto it = std::find(c.allocs.begin(), c.allocs.end(), (void *)c.nl.idx);
-    if (it != c.allocs.end()) {
-        (void)hipFree(*it);
-        c.allocs.erase(it);
-    }
-    c.nl.idx = nullptr;
     int rc = alloc_list(c, mn);
     if (rc != MD_OK) return rc;
     graph_reset(c);

@@ -467,17 +467,17 @@ int batched_prepare(Ctx &c)
         }
     }
     if (!b->boxes) {
-        int rc = hipMalloc(&b->boxes, sizeof(BBox) * c.B) == hipSuccess &&
-                         hipMalloc(&b->order, sizeof(int) * c.B) == hipSuccess &&
-                         hipMalloc(&b->queue, sizeof(unsigned) * 4) == hipSuccess &&
-                         hipMalloc(&b->count, sizeof(int) * c.N) == hipSuccess
-                     ? MD_OK
-                     : MD_ERR_NOMEM;
-        if (rc != MD_OK) return rc;
-        c.allocs.push_back(b->boxes);
-        c.allocs.push_back(b->order);
-        c.allocs.push_back(b->queue);
-        c.allocs.push_back(b->count);
+        void *p[4];
+        const size_t bytes[4] = {sizeof(BBox) * c.B, sizeof(int) * c.B, sizeof(unsigned) * 4,
+                                 sizeof(int) * (size_t)c.N};
+        for (int k = 0; k < 4; ++k) {
+            int rc = ctx_alloc(c, &p[k], bytes[k]);
+            if (rc != MD_OK) return rc;
+        }
+        b->boxes = static_cast<BBox *>(p[0]);
+        b->order = static_cast<int *>(p[1]);
+        b->queue = static_cast<unsigned *>(p[2]);
+        b->count = static_cast<int *>(p[3]);
     }
     {
         // per-box descriptors from the current box edges (the barostat changes them)
@@ -499,16 +499,16 @@ int batched_prepare(Ctx &c)
             return MD_ERR_DEVICE;
     }
     // list storage follows the capacity (reallocated when it changes)
-    if (b->list && b->list_mn != c.nl.mn) {
-        auto it = std::find(c.allocs.begin(), c.allocs.end(), (void *)b->list);
-        if (it != c.allocs.end()) c.allocs.erase(it);
-        (void)hipFree(b->list);
-        b->list = nullptr;
-    }
-    if (!b->list) {
-        if (hipMalloc(&b->list, sizeof(uint16_t) * (size_t)c.N * c.nl.mn) != hipSuccess)
-            return MD_ERR_NOMEM;
-        c.allocs.push_back(b->list);
+    if (!b->list || b->list_mn != c.nl.mn) {
+        void *p = nullptr;
+        int rc = ctx_alloc(c, &p, sizeof(uint16_t) * (size_t)c.N * c.nl.mn);
+        if (rc != MD_OK) {
+            // no room for a list of the new capacity: the merged-box kernels step
+            c.batch_feasible = c.batched = false;
+            return rc;
+        }
+        ctx_free(c, b->list);
+        b->list = static_cast<uint16_t *>(p);
         b->list_mn = c.nl.mn;
     }
     b->list_valid = false;

@@ -161,6 +161,11 @@ struct Ctx;
 void launch_set_state(Ctx &c, const double *pos, const double *vel, hipStream_t s);
 void launch_pair_tables(Ctx &c, hipStream_t s);
 void launch_refresh_types(Ctx &c, hipStream_t s);
+
+// Device memory of a context (md_api.hip): from hipMalloc, or carved from the
+// caller's workspace; sizes are rounded up to 256 bytes.
+int ctx_alloc(Ctx &c, void **p, size_t bytes);
+void ctx_free(Ctx &c, void *p);
 void launch_refresh_frozen(Ctx &c, hipStream_t s);
 void launch_get_state(Ctx &c, double *pos, double *vel, hipStream_t s);
 void launch_build(Ctx &c, bool gated, hipStream_t s);
@@ -281,7 +286,10 @@ struct Ctx {
     int graph_len = 0;
 
     // allocations to free
-    std::vector<void *> allocs;
+    std::vector<void *> allocs;        // device blocks of the context (hipMalloc)
+    size_t alloc_bytes = 0;            // bytes handed out by ctx_alloc (256-byte granules)
+    char *arena = nullptr;             // caller's workspace (md_create_in): blocks are carved
+    size_t arena_size = 0, arena_used = 0;  // from it and never freed
 };
 
 }  // namespace mdk

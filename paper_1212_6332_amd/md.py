@@ -76,6 +76,8 @@ _SIGS = {
     "md_set_thermostat": ([C.c_void_p, C.c_double, C.c_double], C.c_int),
     "md_set_types": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "md_set_frozen": ([C.c_void_p, C.c_void_p], C.c_int),
+    "md_workspace_size": ([C.c_void_p, C.c_void_p, C.POINTER(C.c_size_t)], C.c_int),
+    "md_create_in": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
 }
 
 
@@ -144,7 +146,8 @@ class System:
     original atom order, shaped [N, 3] for vectors.
     """
 
-    def __init__(self, box_offset, box_len, pot, mass, dt=1.0, skin=0.3, max_neighbors=0):
+    def __init__(self, box_offset, box_len, pot, mass, dt=1.0, skin=0.3, max_neighbors=0,
+                 workspace=None):
         lib()
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.box_offset = np.ascontiguousarray(np.asarray(box_offset, dtype=np.int64))
@@ -160,9 +163,39 @@ class System:
         sysd.box_offset = self.box_offset.ctypes.data
         sysd.box_len = self.box_len.ctypes.data
         sysd.mass, sysd.dt, sysd.skin = float(mass), float(dt), float(skin)
+        self._sysd = sysd
         h = C.c_void_p()
-        _check(lib().md_create(C.byref(sysd), C.byref(self._pot.s), C.byref(h)), "md_create")
+        if workspace is None:
+            _check(lib().md_create(C.byref(sysd), C.byref(self._pot.s), C.byref(h)), "md_create")
+        else:
+            # every device buffer of the context comes from this tensor
+            nbytes = workspace.numel() * workspace.element_size()
+            _check(lib().md_create_in(C.byref(sysd), C.byref(self._pot.s),
+                                      C.c_void_p(workspace.data_ptr()), nbytes, C.byref(h)),
+                   "md_create_in")
+        self._workspace = workspace
         self._h = h
+
+    @staticmethod
+    def workspace_size(box_offset, box_len, pot, mass, dt=1.0, skin=0.3, max_neighbors=0):
+        """Device bytes a context for these arguments needs (md_workspace_size)."""
+        lib()
+        off = np.ascontiguousarray(np.asarray(box_offset, dtype=np.int64))
+        bl = np.asarray(box_len, dtype=np.float64)
+        bl = np.ascontiguousarray(bl[:, 0] if bl.ndim == 2 else bl)
+        holder = _PotHolder(pot)
+        sysd = md_system(n_boxes=int(bl.size), max_neighbors=int(max_neighbors),
+                         box_offset=off.ctypes.data, box_len=bl.ctypes.data, mass=float(mass),
+                         dt=float(dt), skin=float(skin))
+        n = C.c_size_t()
+        _check(lib().md_workspace_size(C.byref(sysd), C.byref(holder.s), C.byref(n)),
+               "md_workspace_size")
+        return int(n.value)
+
+    @classmethod
+    def workload_workspace_size(cls, W, pot=None, **kw):
+        return cls.workspace_size(W.box_offset, W.box_len, pot or W.pot, W.mass, W.dt, W.skin,
+                                  **kw)
 
     @classmethod
     def from_workload(cls, W, pot=None, **kw):

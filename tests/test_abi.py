@@ -98,3 +98,21 @@ def test_empty_box_and_size_limit_are_refused():
                          box_len=bl.ctypes.data, mass=63.546, dt=1.0, skin=0.3)
         assert L.md_create(C.byref(s), C.byref(pot.s), C.byref(h)) == md.MD_ERR_ARG
         assert not h.value
+
+
+def test_workspace_create_checks_its_block():
+    """md_create_in refuses a missing or misaligned workspace on the host."""
+    from paper_1212_6332_amd import md, workloads as W
+    L = md.lib()
+    pot = md._PotHolder(W.smtb_cu())
+    off = np.array([0, 256], dtype=np.int64)
+    bl = np.array([14.46])
+    s = md.md_system(n_boxes=1, max_neighbors=0, box_offset=off.ctypes.data,
+                     box_len=bl.ctypes.data, mass=63.546, dt=1.0, skin=0.3)
+    h = C.c_void_p()
+    assert L.md_create_in(C.byref(s), C.byref(pot.s), None, 1 << 20, C.byref(h)) == md.MD_ERR_ARG
+    assert L.md_create_in(C.byref(s), C.byref(pot.s), C.c_void_p(4096 + 8), 1 << 20,
+                          C.byref(h)) == md.MD_ERR_ARG
+    assert not h.value
+    n = C.c_size_t()
+    assert L.md_workspace_size(C.byref(s), C.byref(pot.s), None) == md.MD_ERR_ARG
