@@ -205,3 +205,26 @@ def test_autograd_matches_finite_differences():
         tol = 1e-6 * np.abs(grad).max() + 50 * eps * float(loss) / h
         assert abs(fd - grad[k]) <= tol, (k, fd, grad[k])
     S.close()
+
+
+def test_batched_full_size_sampled_boxes():
+    """All 2,048 boxes in the configuration the benchmark times (persistent
+    stepper), 10 steps; 16 boxes drawn at random, and the largest and the
+    smallest, against the oracle box by box."""
+    wl = W.batch2048()
+    nsteps = 10
+    p, v, flags, steps = run_batch(wl, nsteps)
+    assert flags == 0 and steps == nsteps
+    sizes = np.diff(wl.box_offset)
+    pick = set(np.random.default_rng(11).choice(wl.n_boxes, 16, replace=False).tolist())
+    pick |= {int(np.argmax(sizes)), int(np.argmin(sizes))}
+    pot = O.Pot(wl.pot)
+    for b in sorted(pick):
+        s = slice(int(wl.box_offset[b]), int(wl.box_offset[b + 1]))
+        L = float(wl.box_len[b, 0])
+        x, vo, *_ = O.vv(wl.pos[s], wl.vel[s], L, pot, wl.mass, wl.dt, wl.skin, nsteps,
+                         energies=False)
+        d = p[s] - x
+        d -= L * np.round(d / L)
+        assert np.abs(d).max() < 1e-10, b
+        assert np.abs(v[s] - vo).max() <= 1e-9 * np.abs(vo).max(), b

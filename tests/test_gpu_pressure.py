@@ -192,3 +192,13 @@ def test_barostat_off_and_box_range_guard():
     assert flags & md.MD_FLAG_BOX_RANGE
     assert S.box()[0] == L1
     S.close()
+
+
+def test_pressure_full_size():
+    """The 4,000,000-atom box of the benchmark's pressure leg: virial and
+    pressure against the oracle's list pass over every atom."""
+    wl = W.fcc4m()
+    g = gpu_pressure(wl)
+    o = oracle_pressure(wl)
+    assert abs(g[0, 1] - o[0, 1]) <= 1e-11 * abs(o[0, 1])
+    assert abs(g[0, 0] - o[0, 0]) <= 1e-11 * abs(o[0, 0])
