@@ -94,6 +94,7 @@ void graph_reset(Ctx &c)
     if (c.graph_exec) (void)hipGraphExecDestroy(c.graph_exec);
     c.graph_exec = nullptr;
     c.graph_len = 0;
+    batched_graph_reset(c);
 }
 
 // Analytic constants and device tables of a potential.
@@ -859,6 +860,61 @@ int md_step(md_ctx *h, int nsteps, void *stream)
     c.list_valid = c.density_valid = c.forces_valid = true;
     batched_invalidate(c);
     return MD_OK;
+}
+
+int md_autotune(md_ctx *h, void *stream, int32_t *block)
+{
+    if (!h || !block) return MD_ERR_ARG;
+    Ctx &c = h->c;
+    if (!c.state_set) return MD_ERR_STATE;
+    *block = c.batch_block;
+    if (!(c.B > 1 && c.batched && !c.baro_on)) return MD_OK;  // md_step would not use it
+    hipStream_t s = as_stream(stream);
+    const size_t nb = sizeof(double) * (size_t)c.N;
+    double *keep[6] = {c.bd.sx, c.bd.sy, c.bd.sz, c.bd.svx, c.bd.svy, c.bd.svz};
+    double *live[6] = {c.st.x, c.st.y, c.st.z, c.st.vx, c.st.vy, c.st.vz};
+    // positions and velocities kept in the build scratch (the stepper does not use it)
+    for (int k = 0; k < 6; ++k)
+        HIP_TRY(hipMemcpyAsync(keep[k], live[k], nb, hipMemcpyDeviceToDevice, s));
+    auto restore = [&]() -> int {
+        for (int k = 0; k < 6; ++k)
+            HIP_TRY(hipMemcpyAsync(live[k], keep[k], nb, hipMemcpyDeviceToDevice, s));
+        batched_invalidate(c);
+        c.forces_valid = c.list_valid = c.density_valid = false;
+        return MD_OK;
+    };
+    const int candidates[3] = {256, 512, 1024};
+    const int reps = 20;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best_ms = 0.0f;
+    int best = c.batch_block;
+    int rc = MD_OK;
+    for (int T : candidates) {
+        if ((rc = restore()) != MD_OK) break;
+        c.batch_block = T;
+        launch_batched_steps(c, 5, s);  // lists, forces, first steps
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = MD_ERR_DEVICE; break; }
+        launch_batched_steps(c, reps, s);
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            rc = MD_ERR_DEVICE;
+            break;
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (best_ms == 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best = T;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c.batch_block = best;
+    int rr = restore();
+    HIP_TRY(hipStreamSynchronize(s));
+    *block = best;
+    return rc != MD_OK ? rc : rr;
 }
 
 int md_pressure(md_ctx *h, double *p_box, double *w_box, void *stream)

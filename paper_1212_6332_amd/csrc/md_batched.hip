@@ -62,6 +62,8 @@ struct Batch {
     int list_mn = 0;          // capacity the list storage was sized for
     bool list_valid = false;
     bool prepared = false;    // later calls keep the caller's MD_OPT_BATCHED choice
+    hipGraphExec_t graph = nullptr;  // one captured launch of kMaxSteps steady steps
+    int graph_block = 0;             // workgroup size it was captured with
 };
 
 __device__ __forceinline__ double min_image(double d, double L, double invL)
@@ -520,8 +522,19 @@ void batched_invalidate(Ctx &c)
     if (c.batch) static_cast<Batch *>(c.batch)->list_valid = false;
 }
 
+void batched_graph_reset(Ctx &c)
+{
+    Batch *b = static_cast<Batch *>(c.batch);
+    if (b && b->graph) {
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+        b->graph_block = 0;
+    }
+}
+
 void batched_release(Ctx &c)
 {
+    batched_graph_reset(c);
     delete static_cast<Batch *>(c.batch);
     c.batch = nullptr;
 }
@@ -552,16 +565,43 @@ void launch_batched_steps(Ctx &c, int nsteps, hipStream_t s)
     a.th = c.thermo;
     a.flags = c.dev.flags;
     a.nmax = b.nmax;
-    int mode = (b.list_valid ? 0 : 1) | (c.forces_valid ? 0 : 2);
-    for (int done = 0; done < nsteps;) {
-        int k = std::min(kMaxSteps, nsteps - done);
+    auto launch = [&](int k, int mode, hipStream_t st) {
         a.nsteps = k;
         a.mode = mode;
-        k_reset_queue<<<1, 1, 0, s>>>(b.queue);
-        if (kind == MD_POT_FS) launch_kind<MD_POT_FS>(c, a, s);
-        else if (kind == MD_POT_SMTB) launch_kind<MD_POT_SMTB>(c, a, s);
-        else launch_kind<MD_POT_SPLINE>(c, a, s);
-        mode = 0;
+        k_reset_queue<<<1, 1, 0, st>>>(b.queue);
+        if (kind == MD_POT_FS) launch_kind<MD_POT_FS>(c, a, st);
+        else if (kind == MD_POT_SMTB) launch_kind<MD_POT_SMTB>(c, a, st);
+        else launch_kind<MD_POT_SPLINE>(c, a, st);
+    };
+    int done = 0;
+    const int mode = (b.list_valid ? 0 : 1) | (c.forces_valid ? 0 : 2);
+    if (mode != 0) {
+        // the first launch rebuilds the boxes' lists and/or computes forces first
+        int k = std::min(kMaxSteps, nsteps);
+        launch(k, mode, s);
+        done = k;
+    }
+    if (c.use_graph && nsteps - done >= kMaxSteps) {
+        // full chunks replay one captured launch (reset + persistent kernel)
+        if (!b.graph || b.graph_block != T) {
+            batched_graph_reset(c);
+            hipGraph_t g = nullptr;
+            bool ok = hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeRelaxed) == hipSuccess;
+            if (ok) {
+                launch(kMaxSteps, 0, c.cap_stream);
+                ok = hipStreamEndCapture(c.cap_stream, &g) == hipSuccess && g != nullptr;
+            }
+            if (ok && hipGraphInstantiate(&b.graph, g, nullptr, nullptr, 0) != hipSuccess)
+                b.graph = nullptr;
+            if (g) (void)hipGraphDestroy(g);
+            b.graph_block = b.graph ? T : 0;
+        }
+        if (b.graph)
+            for (; done + kMaxSteps <= nsteps; done += kMaxSteps) (void)hipGraphLaunch(b.graph, s);
+    }
+    while (done < nsteps) {
+        int k = std::min(kMaxSteps, nsteps - done);
+        launch(k, 0, s);
         done += k;
     }
     b.list_valid = true;

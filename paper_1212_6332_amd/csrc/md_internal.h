@@ -161,6 +161,7 @@ struct Ctx;
 void launch_set_state(Ctx &c, const double *pos, const double *vel, hipStream_t s);
 void launch_pair_tables(Ctx &c, hipStream_t s);
 void launch_refresh_types(Ctx &c, hipStream_t s);
+void batched_graph_reset(Ctx &c);
 
 // Device memory of a context (md_api.hip): from hipMalloc, or carved from the
 // caller's workspace; sizes are rounded up to 256 bytes.

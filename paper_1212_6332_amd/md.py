@@ -77,6 +77,7 @@ _SIGS = {
     "md_set_types": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "md_set_frozen": ([C.c_void_p, C.c_void_p], C.c_int),
     "md_workspace_size": ([C.c_void_p, C.c_void_p, C.POINTER(C.c_size_t)], C.c_int),
+    "md_autotune": ([C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)], C.c_int),
     "md_create_in": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
 }
 
@@ -203,6 +204,13 @@ class System:
         if getattr(W, "types", None) is not None and int(getattr(s.pot, "n_types", 1)) > 1:
             s.set_types(W.types, W.type_mass)
         return s
+
+    def autotune(self):
+        """Pick the fastest workgroup size of the persistent multi-box stepper
+        (md_autotune); returns it."""
+        b = C.c_int32()
+        _check(lib().md_autotune(self._h, _stream(), C.byref(b)), "md_autotune")
+        return int(b.value)
 
     def set_frozen(self, frozen):
         """Atom states: a nonzero entry (host array, original order) freezes that atom;

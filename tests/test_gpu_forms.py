@@ -228,3 +228,36 @@ def test_batched_full_size_sampled_boxes():
         d -= L * np.round(d / L)
         assert np.abs(d).max() < 1e-10, b
         assert np.abs(v[s] - vo).max() <= 1e-9 * np.abs(vo).max(), b
+
+
+def test_autotune_and_graph_replay_keep_the_trajectory():
+    """md_autotune between md_set_state and md_step picks a workgroup size and
+    leaves the trajectory bitwise that of an untuned context with that size;
+    250 steps (one launch that rebuilds, one replayed graph of 100 steps, a
+    tail) equal direct launches bitwise; a one-box context has nothing to
+    tune."""
+    wl = W.batch2048(n_boxes=40)
+
+    def run(tune, block=None, use_graph=1):
+        S = md.System.from_workload(wl)
+        S.set_option(md.MD_OPT_USE_GRAPH, use_graph)
+        if block is not None:
+            S.set_option(md.MD_OPT_BATCH_BLOCK, block)
+        S.set_state(wl.pos, wl.vel)
+        chosen = S.autotune() if tune else S.get_option(md.MD_OPT_BATCH_BLOCK)
+        S.step(250)
+        p, v = S.get_state()
+        st = S.status()
+        S.close()
+        return chosen, p.cpu().numpy(), v.cpu().numpy(), st
+
+    t, p1, v1, st1 = run(True)
+    assert t in (256, 512, 1024) and st1[0] == 0 and st1[2] == 250
+    _, p2, v2, st2 = run(False, t)
+    _, p3, v3, st3 = run(False, t, use_graph=0)
+    assert np.array_equal(p1, p2) and np.array_equal(v1, v2)
+    assert np.array_equal(p2, p3) and np.array_equal(v2, v3) and st2 == st3
+    one = md.System.from_workload(W.fs256())
+    one.set_state(W.fs256().pos, W.fs256().vel)
+    assert one.autotune() == one.get_option(md.MD_OPT_BATCH_BLOCK)
+    one.close()
