@@ -19,6 +19,7 @@
 #include <numeric>
 #include <vector>
 
+#include "md_device.h"
 #include "md_internal.h"
 
 namespace mdk {
@@ -134,6 +135,19 @@ __device__ __forceinline__ void pair_terms(const Pot &p, double r, double &dfr, 
         dfr = p.afn * ef;
         v = ev;
         dv = p.avn * ev;
+    } else if (p.pair) {
+        // V and rho of one interval, 64 contiguous bytes (interleaved table)
+        const Table &t = p.tab[0];
+        double u = (r - t.lo) * t.inv_h;
+        int m = (int)floor(u);
+        if (!(r >= t.lo && r <= t.hi)) bad |= MD_FLAG_TABLE_RANGE;
+        m = m < 0 ? 0 : (m > t.n - 1 ? t.n - 1 : m);
+        double tt = u - (double)m;
+        const double2 *c = reinterpret_cast<const double2 *>(p.pair + 8 * (size_t)m);
+        double2 va = c[0], vb = c[1], fa = c[2], fb = c[3];
+        v = fma(tt, fma(tt, fma(tt, vb.y, vb.x), va.y), va.x);
+        dv = fma(tt, fma(tt, 3.0 * vb.y, 2.0 * vb.x), va.y) * t.inv_h;
+        dfr = fma(tt, fma(tt, 3.0 * fb.y, 2.0 * fb.x), fa.y) * t.inv_h;
     } else {
         double s;
         table_eval(p.tab[1], r, s, dfr, bad);
@@ -294,7 +308,7 @@ __global__ __launch_bounds__(T) void k_batched(BArgs a)
                     double dy = min_image(Y[j] - yi, L, invL);
                     double dz = min_image(Z[j] - zi, L, invL);
                     double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                    if (r2 < pot.rc2) rho += dens<KIND>(pot, sqrt(r2), bad);
+                    if (r2 < pot.rc2) rho += dens<KIND>(pot, r2 * dev::rsqrt_nr(r2), bad);
                 }
                 FP[i] = embed_fp<KIND>(pot, rho, bad);
             }
@@ -314,9 +328,9 @@ __global__ __launch_bounds__(T) void k_batched(BArgs a)
                     double dz = min_image(Z[j] - zi, L, invL);
                     double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
                     if (r2 < pot.rc2) {
-                        double r = sqrt(r2), dfr, v, dv;
-                        pair_terms<KIND>(pot, r, dfr, v, dv, bad);
-                        double coef = fma(fpi + FP[j], dfr, dv) / r;
+                        double inv_r = dev::rsqrt_nr(r2), dfr, v, dv;
+                        pair_terms<KIND>(pot, r2 * inv_r, dfr, v, dv, bad);
+                        double coef = fma(fpi + FP[j], dfr, dv) * inv_r;
                         ax = fma(coef, dx, ax);
                         ay = fma(coef, dy, ay);
                         az = fma(coef, dz, az);
