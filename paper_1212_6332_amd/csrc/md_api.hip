@@ -1,8 +1,9 @@
 // Host implementation of the C ABI declared in include/md.h.
 //
-// A context owns one device workspace sized at creation: the sorted atom
-// state, the cell structure, the neighbour list, per-box geometry, partial
-// sums and the status word.  Entry points enqueue kernels on the caller's
+// A context owns one device workspace sized at creation (allocated, or
+// carved from the caller's block): the sorted atom state, the cell
+// structure, the neighbour list, per-box geometry, tables, partial sums and
+// the status word.  Entry points enqueue kernels on the caller's
 // stream; md_step replays a captured HIP graph of several velocity-Verlet
 // steps in which the list rebuild is decided on the device, so the host
 // never waits inside a trajectory.

@@ -3,9 +3,10 @@
 // Layout: every per-atom array is structure-of-arrays FP64 in cell-sorted
 // order, so that a 64-lane wavefront reads 64 consecutive atoms (coalesced)
 // and the neighbours of those atoms lie in a few nearby cells (cache
-// friendly gathers).  The neighbour list is stored slot-fastest,
-// idx[n * N + i], so the n-th neighbour of 64 consecutive atoms is one
-// coalesced 256-byte read.  Lists are full (each pair stored twice): the
+// friendly gathers).  The neighbour list is stored slot-fastest in groups
+// of four entries (entry n of slot i at ((n / 4) N + i) 4 + n % 4), so one
+// 16-byte load returns four neighbours of an atom and 64 consecutive atoms
+// read 1 KiB contiguously.  Lists are full (each pair stored twice): the
 // force on atom i is gathered by the thread of atom i alone, with no
 // scatter and no floating-point atomics, which makes every pass
 // deterministic.

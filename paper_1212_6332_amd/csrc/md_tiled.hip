@@ -21,7 +21,8 @@
 //     the list build and the passes take the minimum image per pair.
 // Rows hold the byte offsets of halo records in the LDS record array
 // (record index times 32), so the passes address a record with no
-// arithmetic.
+// arithmetic; with several species the neighbour's species rides in the
+// five low bits of its entry.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
