@@ -14,10 +14,19 @@
  *   - the density pass and the force pass over a neighbour list with the
  *     cutoff re-checked inside the loop: Section 3.3, Figs. 5 and 6;
  *   - the SETB embedding F = -sqrt(rho): Section 4.
+ *   - the pair virial and pressure of eq. (6) and the Berendsen barostat of
+ *     eq. (5);
+ *   - the electron-gas friction of eq. (4);
+ *   - several atom species (the superscripts a, b of eqs. (1)-(3)) and frozen
+ *     atoms (the atom states of Section 3.1).
  * Velocity-Verlet replaces the paper's predictor-corrector (Section 3.3).
  * The adjoint with respect to B-spline potential coefficients is derived from
  * eqs. (2)-(3) by differentiating the force and energy with respect to the
  * three potential functions (the derivation is written next to orc_adjoint).
+ * Where the paper leaves a choice open (how the friction enters the
+ * integrator, which function gives the derivative of rho_j with several
+ * species, what a frozen atom does), the reading taken is stated next to the
+ * function that implements it.
  *
  * Build with -ffp-contract=off: the squared distance of the neighbour test is
  * (dx*dx + dy*dy) + dz*dz with every product and sum rounded separately.
