@@ -268,8 +268,14 @@ class System:
 
     def set_theta(self, theta):
         t = _dev_f64(theta, self.device).reshape(-1)
+        # the same coefficients as the last upload (e.g. the backward pass of
+        # the forward that set them): nothing to do
+        last = getattr(self, "_theta", None)
+        if last is not None and t is last[0] and t._version == last[1]:
+            return
         _check(lib().md_set_theta(self._h, _ptr(t), _stream()), "md_set_theta")
-        torch.cuda.current_stream().synchronize()
+        # the copy is stream ordered; holding t keeps its memory until the next upload
+        self._theta = (t, t._version)
 
     def build_neighbors(self):
         _check(lib().md_build_neighbors(self._h, _stream()), "md_build_neighbors")
