@@ -12,6 +12,9 @@
 namespace mdk {
 
 constexpr int kBlock = 256;        // threads per workgroup of the per-atom kernels
+// Threads per workgroup of the per-atom pair passes: one wavefront while the
+// atoms are too few to give every compute unit several 256-thread workgroups.
+inline int atom_block(int64_t n) { return n < 262144 ? 64 : kBlock; }
 constexpr int kChunk = 4096;       // atoms per partial sum of the energy reductions
 constexpr int kTileThreads = 1024; // threads of a tiled-pass workgroup (one tile)
 constexpr int kHaloCells = 512;    // halo cells a tile may have

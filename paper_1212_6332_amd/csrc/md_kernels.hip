@@ -922,7 +922,8 @@ inline int grid_for(int64_t n, int block = kBlock) { return (int)((n + block - 1
 template <int KIND, bool MULTI>
 void density_t(Ctx &c, hipStream_t s)
 {
-    k_density<KIND, MULTI><<<grid_for(c.N), kBlock, 0, s>>>(
+    int blk = atom_block(c.N);
+    k_density<KIND, MULTI><<<grid_for(c.N, blk), blk, 0, s>>>(
         (int)c.N, c.st, c.bx, c.nl, c.pot, c.box_len[0], 1.0 / c.box_len[0], c.dev.flags);
 }
 
@@ -931,16 +932,16 @@ void force_t(Ctx &c, bool energy, bool kick, hipStream_t s)
 {
     double k = 0.5 * c.dt * (1.602176634e-19 / 1.66053906660e-27 * 1e-10) / c.mass;
     double L = c.box_len[0], iL = 1.0 / c.box_len[0];
-    int g = grid_for(c.N);
+    int blk = atom_block(c.N), g = grid_for(c.N, blk);
     int N = (int)c.N;
     if (energy && kick)
-        k_force<KIND, MULTI, true, true><<<g, kBlock, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.thermo, c.dev.flags);
+        k_force<KIND, MULTI, true, true><<<g, blk, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.thermo, c.dev.flags);
     else if (energy)
-        k_force<KIND, MULTI, true, false><<<g, kBlock, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.thermo, c.dev.flags);
+        k_force<KIND, MULTI, true, false><<<g, blk, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.thermo, c.dev.flags);
     else if (kick)
-        k_force<KIND, MULTI, false, true><<<g, kBlock, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.thermo, c.dev.flags);
+        k_force<KIND, MULTI, false, true><<<g, blk, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.thermo, c.dev.flags);
     else
-        k_force<KIND, MULTI, false, false><<<g, kBlock, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.thermo, c.dev.flags);
+        k_force<KIND, MULTI, false, false><<<g, blk, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.thermo, c.dev.flags);
 }
 
 }  // namespace
@@ -996,7 +997,7 @@ void launch_build(Ctx &c, bool gated, hipStream_t s)
     if (c.tiled)
         launch_tile_nlist(c, gate, s);
     else
-        k_nlist<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.st, c.bx, c.bd, c.nl, c.dev.flags);
+        k_nlist<<<grid_for(N, atom_block(N)), atom_block(N), 0, s>>>(gate, N, c.st, c.bx, c.bd, c.nl, c.dev.flags);
     if (c.baro_on)
         k_baro_rebuilt<<<grid_for(c.B), kBlock, 0, s>>>(gate, c.B, c.pot.rc, c.d_boxd, c.d_baro);
     if (!gated) k_count_build<<<1, 1, 0, s>>>(c.dev.flags);

@@ -268,10 +268,13 @@ class System:
 
     def set_theta(self, theta):
         t = _dev_f64(theta, self.device).reshape(-1)
-        # the same coefficients as the last upload (e.g. the backward pass of
-        # the forward that set them): nothing to do
+        # the same memory at the same version as the last upload (e.g. the
+        # backward pass of the forward that set them): nothing to do.  Views
+        # share the version counter, so an in-place change through any of
+        # them is seen; the held tensor keeps the memory from being reused.
         last = getattr(self, "_theta", None)
-        if last is not None and t is last[0] and t._version == last[1]:
+        if (last is not None and t.data_ptr() == last[0].data_ptr()
+                and t.numel() == last[0].numel() and t._version == last[1]):
             return
         _check(lib().md_set_theta(self._h, _ptr(t), _stream()), "md_set_theta")
         # the copy is stream ordered; holding t keeps its memory until the next upload

@@ -181,6 +181,31 @@ def test_autograd_loss_gradient_matches_oracle():
     assert rel(grad, ref) < 1e-9
 
 
+def test_set_theta_sees_in_place_changes():
+    """A second upload of the same coefficient tensor is skipped only while
+    its contents are unchanged: an in-place update (as an optimiser makes)
+    reaches the device, and so does a view of the updated memory."""
+    import dataclasses
+    wl, S = adjoint_setup(2)
+    theta = torch.tensor(np.concatenate(wl.pot.tables), device="cuda")
+    S.set_theta(theta)
+    S.forces()
+    with torch.no_grad():
+        theta[64:128] *= 1.01  # rho(r)
+        theta[:64] -= 0.002    # V(r)
+    S.set_theta(theta)
+    f1, _, e1 = S.forces(energy=True)
+    S.set_theta(theta.view(3, 64))  # same memory and version: no upload needed
+    f2, _, e2 = S.forces(energy=True)
+    S.close()
+    tabs = theta.view(3, 64).cpu().numpy()
+    pot = O.Pot(dataclasses.replace(wl.pot, tables=tuple(np.array(t) for t in tabs)))
+    ref = O.forces_multi(wl, pot=pot)
+    assert rel(f1.cpu().numpy(), ref["f"]) < 1e-11
+    assert rel(e1.cpu().numpy(), ref["E_box"]) < 1e-11
+    assert torch.equal(f1, f2) and torch.equal(e1, e2)
+
+
 def test_autograd_matches_finite_differences():
     wl, S = adjoint_setup(2)
     w = wl.extra["w"]
