@@ -198,7 +198,7 @@ def bench_batched(steps=200, warmup=5):
 def bench_adjoint(evals=50, steps=100):
     import torch
     from paper_1212_6332_amd import md, workloads as W
-    from paper_1212_6332_amd.autograd import force_matching_loss
+    from paper_1212_6332_amd.autograd import GraphedLoss, force_matching_loss
 
     wl = W.adjoint64()
     T = md.System.from_workload(wl, wl.extra["target_pot"])
@@ -224,12 +224,23 @@ def bench_adjoint(evals=50, steps=100):
         one()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / evals
+    # the same evaluation captured once and replayed from a HIP graph
+    G = GraphedLoss(S, th, lambda: force_matching_loss(S, th[0], th[1], th[2], ft, et, w))
+    for _ in range(3):
+        G.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(4 * evals):
+        G.replay()
+    torch.cuda.synchronize()
+    dtg = (time.perf_counter() - t0) / (4 * evals)
     # the plain step on the same boxes and potential, for comparison
     S.set_state(wl.pos, None)
     wall, _, _ = timed_steps(S, steps, 5)
     S.close()
     return {"workload": "adjoint64: 64 BCC 5^3 boxes (16,000 atoms), 3x64 B-spline coefficients",
             "grad_evals_per_s": 1.0 / dt, "ms_per_grad_eval": dt * 1e3,
+            "graph_grad_evals_per_s": 1.0 / dtg, "graph_ms_per_grad_eval": dtg * 1e3,
             "atom_grads_per_s": wl.n_atoms / dt,
             "plain_step_atom_steps_per_s": wl.n_atoms * steps / wall}
 

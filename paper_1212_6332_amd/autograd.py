@@ -1,7 +1,11 @@
 """Autograd front end of form (3): gradients of any loss of the forces and
 per-box energies with respect to the B-spline coefficients of V(r), rho(r)
 and F(rho).  Forward runs md_set_theta + md_forces; backward runs the
-hand-written adjoint kernel (md_adjoint).  Argument marshalling only."""
+hand-written adjoint kernel (md_adjoint).  Argument marshalling only.
+
+GraphedLoss captures one loss evaluation with its backward pass in a HIP
+graph (through torch.cuda.graph) and replays it, which removes the host cost
+of the Python autograd engine and of some thirty launches per evaluation."""
 from __future__ import annotations
 
 import torch
@@ -44,3 +48,52 @@ def force_matching_loss(system, theta_phi, theta_f, theta_F, f_target, e_target,
     """sum |f - f_target|^2 + w sum_b (E_b - E_target_b)^2."""
     f, eb = SplineEAMFunction.apply(theta_phi, theta_f, theta_F, system)
     return ((f - f_target) ** 2).sum() + w * ((eb - e_target) ** 2).sum()
+
+
+class GraphedLoss:
+    """A loss of the forces and energies and its backward pass, captured once
+    in a HIP graph and replayed.
+
+    `loss_fn()` returns a scalar loss computed from the leaf tensors `params`
+    (float64 CUDA tensors with requires_grad) through SplineEAMFunction on
+    `system`.  The capture warms up on a side stream, then records the
+    forward pass, the adjoint and the loss arithmetic.  Between replays,
+    change the parameters in place only (`p.copy_(...)` under torch.no_grad,
+    or an optimiser step outside the graph); each replay leaves the loss in
+    `self.loss` and the gradients in `self.grads` (the same tensors every
+    time, overwritten).  The positions and settings of `system` are part of
+    the capture: once a call changes them (`System.epoch` moves on), replay
+    raises and the loss must be captured again.
+    """
+
+    def __init__(self, system, params, loss_fn, warmup=3):
+        self.system = system
+        self.params = list(params)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(warmup):
+                for p in self.params:
+                    p.grad = None
+                loss_fn().backward()
+        torch.cuda.current_stream().wait_stream(side)
+        for p in self.params:
+            p.grad = None
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph, stream=side):
+            loss = loss_fn()
+            loss.backward()
+        self.loss = loss.detach()
+        self.grads = [p.grad for p in self.params]
+        self._epoch = system.epoch
+
+    def replay(self):
+        """One loss and gradient evaluation on the current stream; returns
+        (loss, grads)."""
+        if self.system.epoch != self._epoch:
+            raise RuntimeError("the system changed since the capture: capture the loss again")
+        self.graph.replay()
+        # the device now holds the captured coefficients: the next eager
+        # upload must not be skipped as unchanged
+        self.system._theta = None
+        return self.loss, self.grads

@@ -11,10 +11,10 @@
 //   dL/dF_k   = sum_i [ e C_k(rho_i) - C'_k(rho_i) s_i ]
 // Every term is gathered on the side of atom i (full lists), so no atom
 // receives a scatter.  The only reduction is into the 3K coefficients: the
-// row of atom i is split over kAdjParts lanes, each lane accumulates its
-// share of the row into a private LDS column, the columns of a workgroup are
-// summed in lane order, and the workgroup partials by a fixed tree -- a fixed
-// order, so results are bitwise reproducible with no floating-point atomics.
+// lanes that share the row of atom i add its terms, in row order, to one LDS
+// column per atom, the columns of a workgroup are summed in atom order, and
+// the workgroup partials by a fixed tree -- a fixed order, so results are
+// bitwise reproducible with no floating-point atomics.
 // F'(rho) and F''(rho) are re-evaluated from the density once per atom, never
 // taken from the forward pass.
 #include <hip/hip_runtime.h>
@@ -81,17 +81,17 @@ __global__ void k_adj_gather(int N, const int *__restrict__ id, const double *__
     gs[2 * N + q] = g[o + 2];
 }
 
-// Lanes that share the neighbour row of one atom in the coefficient kernel.
-constexpr int kAdjParts = 4;
-
-// s_i, lambda_i and F'(rho_i).
+// s_i, lambda_i and F'(rho_i); P lanes share the row of atom i, taking the
+// rows congruent to their part modulo P, and are summed by a fixed butterfly.
+template <int P>
 __global__ __launch_bounds__(kBlock) void k_adj_s(int N, State st, Boxes bx, NList nl, Pot pot,
                                                   const double *__restrict__ gs,
                                                   const double *__restrict__ e,
                                                   double *__restrict__ sv, double *__restrict__ lam,
                                                   double *__restrict__ fpv)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = t / P, part = t % P;
     if (i >= N) return;
     int b = bx.box_of[i];
     double L = bx.L[b], invL = bx.invL[b];
@@ -101,8 +101,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_s(int N, State st, Boxes bx, NLi
     unsigned w = (unsigned)nl.count[i];
     int np = (int)(w & 0xffffu), n1 = nl.mn - (int)(w >> 16);
     double s = 0.0;
-    for (int n = 0; n < nl.mn; ++n) {
-        if (n == np) n = n1;  // skip to the boundary-crossing part of the row
+    for (int n = part; n < nl.mn; n += P) {
+        if (n >= np && n < n1) n = n1 + ((part - n1) & (P - 1));  // boundary-crossing part
         if (n >= nl.mn) break;
         int j = nl.idx[dev::nl_off(n, i, N)];
         double dx = min_image(st.x[j] - xi, L, invL);
@@ -117,6 +117,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_s(int N, State st, Boxes bx, NLi
         double proj = fma(gzi - gz[j], dz, fma(gyi - gy[j], dy, (gxi - gx[j]) * dx));
         s -= df * proj / r;
     }
+    for (int o = 1; o < P; o <<= 1) s += __shfl_xor(s, o);
+    if (part != 0) return;
     double F, Fp, Fpp;
     table_eval2(pot.tab[2], st.rho[i], F, Fp, Fpp);
     sv[i] = s;
@@ -124,71 +126,100 @@ __global__ __launch_bounds__(kBlock) void k_adj_s(int N, State st, Boxes bx, NLi
     fpv[i] = Fp;
 }
 
-// Coefficient gradients: W lanes per workgroup, each with an LDS column of
-// 3K; the kAdjParts lanes of one atom take every kAdjParts-th entry of its
-// row, the first of them also the embedding term.
-template <int W>
-__global__ __launch_bounds__(W) void k_adj_theta(int N, int K, State st, Boxes bx, NList nl,
-                                                 Pot pot, const double *__restrict__ gs,
-                                                 const double *__restrict__ e,
-                                                 const double *__restrict__ sv,
-                                                 const double *__restrict__ lam,
-                                                 const double *__restrict__ fpv,
-                                                 double *__restrict__ partial)
+// Coefficient gradients.  A workgroup is one wavefront: A = 64 / P atoms,
+// P lanes per atom, one LDS column of 3K per atom.  Lane `part` evaluates the
+// entries q = part, part + P, ... of its atom's row; the P lanes then add
+// their contributions to the column in P ordered phases, so the column
+// receives the row in entry order, exactly as one lane walking the row would.
+// Sharing a column keeps the LDS per workgroup small enough for several
+// workgroups per compute unit, and P lanes shorten each lane's chain of
+// dependent gathers P times.
+template <int P>
+__global__ __launch_bounds__(64) void k_adj_theta(int N, int K, State st, Boxes bx, NList nl,
+                                                  Pot pot, const double *__restrict__ gs,
+                                                  const double *__restrict__ e,
+                                                  const double *__restrict__ sv,
+                                                  const double *__restrict__ lam,
+                                                  const double *__restrict__ fpv,
+                                                  double *__restrict__ partial)
 {
-    extern __shared__ double acc[];  // [3K][W]
-    int lane = threadIdx.x;
-    for (int k = 0; k < 3 * K; ++k) acc[k * W + lane] = 0.0;
-    int part = lane % kAdjParts;
-    int i = blockIdx.x * (W / kAdjParts) + lane / kAdjParts;
-    if (i < N) {
-        int b = bx.box_of[i];
-        double L = bx.L[b], invL = bx.invL[b];
-        double eb = e[b];
-        const double *gx = gs, *gy = gs + N, *gz = gs + 2 * N;
-        double xi = st.x[i], yi = st.y[i], zi = st.z[i];
-        double gxi = gx[i], gyi = gy[i], gzi = gz[i];
-        double lami = lam[i], fpi = fpv[i];
+    constexpr int A = 64 / P;
+    extern __shared__ double acc[];  // [3K][A]
+    const int lane = threadIdx.x, a = lane / P, part = lane % P;
+    for (int k = lane; k < 3 * K * A; k += 64) acc[k] = 0.0;
+    const int i = blockIdx.x * A + a;
+    const bool atom = i < N;
+    int cnt = 0, np = 0, n1 = 0, b = 0;
+    double L = 1.0, invL = 1.0, eb = 0.0, xi = 0.0, yi = 0.0, zi = 0.0;
+    double gxi = 0.0, gyi = 0.0, gzi = 0.0, lami = 0.0, fpi = 0.0;
+    if (atom) {
+        b = bx.box_of[i];
+        L = bx.L[b];
+        invL = bx.invL[b];
+        eb = e[b];
+        xi = st.x[i];
+        yi = st.y[i];
+        zi = st.z[i];
+        gxi = gs[i];
+        gyi = gs[N + i];
+        gzi = gs[2 * N + i];
+        lami = lam[i];
+        fpi = fpv[i];
         unsigned cw = (unsigned)nl.count[i];
         // entries [0, np) and [n1, mn) of the row, numbered q = 0 .. np + ni - 1
-        int np = (int)(cw & 0xffffu), ni = (int)(cw >> 16), n1 = nl.mn - ni;
-        double bb[4], db[4];
-        for (int q = part; q < np + ni; q += kAdjParts) {
+        np = (int)(cw & 0xffffu);
+        int ni = (int)(cw >> 16);
+        n1 = nl.mn - ni;
+        cnt = np + ni;
+    }
+    __syncthreads();
+    double bb[4], db[4];
+    for (int q0 = 0; __syncthreads_or(q0 + part < cnt); q0 += P) {
+        const int q = q0 + part;
+        bool live = false;
+        int m0 = 0, m1 = 0;
+        double c0[4], c1[4];
+        if (q < cnt) {
             int n = q < np ? q : n1 + (q - np);
             int j = nl.idx[dev::nl_off(n, i, N)];
             double dx = min_image(st.x[j] - xi, L, invL);
             double dy = min_image(st.y[j] - yi, L, invL);
             double dz = min_image(st.z[j] - zi, L, invL);
             double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            if (r2 >= pot.rc2) continue;
-            double r = sqrt(r2);
-            double cij = -fma(gzi, dz, fma(gyi, dy, gxi * dx)) / r;
-            int m;
-            double t;
-            locate(pot.tab[0], r, m, t);
-            basis(t, pot.tab[0].inv_h, bb, db);
-            for (int l = 0; l < 4; ++l)
-                acc[(m + l) * W + lane] += fma(0.5 * eb, bb[l], -db[l] * cij);
-            locate(pot.tab[1], r, m, t);
-            basis(t, pot.tab[1].inv_h, bb, db);
-            double w = (fpi + fpv[j]) * cij;
-            for (int l = 0; l < 4; ++l)
-                acc[(K + m + l) * W + lane] += fma(lami, bb[l], -db[l] * w);
+            if (r2 < pot.rc2) {
+                live = true;
+                double r = sqrt(r2);
+                double cij = -fma(gzi, dz, fma(gyi, dy, gxi * dx)) / r;
+                double t;
+                locate(pot.tab[0], r, m0, t);
+                basis(t, pot.tab[0].inv_h, bb, db);
+                for (int l = 0; l < 4; ++l) c0[l] = fma(0.5 * eb, bb[l], -db[l] * cij);
+                locate(pot.tab[1], r, m1, t);
+                basis(t, pot.tab[1].inv_h, bb, db);
+                double w = (fpi + fpv[j]) * cij;
+                for (int l = 0; l < 4; ++l) c1[l] = fma(lami, bb[l], -db[l] * w);
+            }
         }
-        if (part == 0) {
-            int m;
-            double t;
-            locate(pot.tab[2], st.rho[i], m, t);
-            basis(t, pot.tab[2].inv_h, bb, db);
-            double si = sv[i];
-            for (int l = 0; l < 4; ++l)
-                acc[(2 * K + m + l) * W + lane] += fma(eb, bb[l], -db[l] * si);
+        for (int ph = 0; ph < P; ++ph) {
+            if (live && part == ph) {
+                for (int l = 0; l < 4; ++l) acc[(m0 + l) * A + a] += c0[l];
+                for (int l = 0; l < 4; ++l) acc[(K + m1 + l) * A + a] += c1[l];
+            }
+            __syncthreads();
         }
     }
+    if (atom && part == 0) {
+        int m;
+        double t;
+        locate(pot.tab[2], st.rho[i], m, t);
+        basis(t, pot.tab[2].inv_h, bb, db);
+        double si = sv[i];
+        for (int l = 0; l < 4; ++l) acc[(2 * K + m + l) * A + a] += fma(eb, bb[l], -db[l] * si);
+    }
     __syncthreads();
-    for (int k = lane; k < 3 * K; k += W) {
+    for (int k = lane; k < 3 * K; k += 64) {
         double s = 0.0;
-        for (int l = 0; l < W; ++l) s += acc[k * W + l];
+        for (int c = 0; c < A; ++c) s += acc[k * A + c];
         partial[(size_t)blockIdx.x * 3 * K + k] = s;
     }
 }
@@ -214,40 +245,47 @@ __global__ __launch_bounds__(kBlock) void k_adj_reduce(int nblk, int K3,
 
 }  // namespace
 
-// Lanes per workgroup of the coefficient kernel: 3K W doubles must fit in 64 KiB.
+// Lanes per atom of the coefficient kernel: the fewest (at least four) that
+// keep the columns of its 64 / P atoms within 32 KiB of LDS, else one atom
+// per workgroup with up to 64 KiB; 0 when even that does not fit.
 int adjoint_lanes(int K)
 {
-    for (int w = 32; w >= 8; w /= 2)
-        if ((size_t)3 * K * w * sizeof(double) <= 65536) return w;
-    return 0;
+    for (int p = 4; p <= 64; p *= 2)
+        if ((size_t)3 * K * (64 / p) * sizeof(double) <= 32768) return p;
+    return (size_t)3 * K * sizeof(double) <= 65536 ? 64 : 0;
 }
 
 // Workgroups of the coefficient kernel.
-static int64_t adjoint_blocks(int64_t N, int W) { return (N + W / kAdjParts - 1) / (W / kAdjParts); }
+static int64_t adjoint_blocks(int64_t N, int P) { return (N + 64 / P - 1) / (64 / P); }
 
 size_t adjoint_scratch_doubles(int64_t N, int K)
 {
-    int w = adjoint_lanes(K);
-    if (w == 0) return 0;
-    return 6 * (size_t)N + (size_t)adjoint_blocks(N, w) * 3 * (size_t)K;
+    int p = adjoint_lanes(K);
+    if (p == 0) return 0;
+    return 6 * (size_t)N + (size_t)adjoint_blocks(N, p) * 3 * (size_t)K;
 }
 
 void launch_adjoint(Ctx &c, const double *g, const double *e, double *gtheta, hipStream_t s)
 {
-    int N = (int)c.N, K = c.n_theta, W = adjoint_lanes(K);
+    int N = (int)c.N, K = c.n_theta, P = adjoint_lanes(K);
     double *gs = c.adj, *sv = c.adj + 3 * (size_t)N, *lam = c.adj + 4 * (size_t)N;
     double *fpv = c.adj + 5 * (size_t)N, *partial = c.adj + 6 * (size_t)N;
     int blk = atom_block(N), g1 = (N + blk - 1) / blk;
     k_adj_gather<<<g1, blk, 0, s>>>(N, c.st.id, g, gs);
-    k_adj_s<<<g1, blk, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, gs, e, sv, lam, fpv);
-    int nblk = (int)adjoint_blocks(N, W);
-    size_t lds = (size_t)3 * K * W * sizeof(double);
-    if (W == 32)
-        k_adj_theta<32><<<nblk, 32, lds, s>>>(N, K, c.st, c.bx, c.nl, c.pot, gs, e, sv, lam, fpv, partial);
-    else if (W == 16)
-        k_adj_theta<16><<<nblk, 16, lds, s>>>(N, K, c.st, c.bx, c.nl, c.pot, gs, e, sv, lam, fpv, partial);
+    if (row_lanes(N) == kRowLanes)
+        k_adj_s<kRowLanes><<<(int)(((int64_t)N * kRowLanes + blk - 1) / blk), blk, 0, s>>>(
+            N, c.st, c.bx, c.nl, c.pot, gs, e, sv, lam, fpv);
     else
-        k_adj_theta<8><<<nblk, 8, lds, s>>>(N, K, c.st, c.bx, c.nl, c.pot, gs, e, sv, lam, fpv, partial);
+        k_adj_s<1><<<g1, blk, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, gs, e, sv, lam, fpv);
+    int nblk = (int)adjoint_blocks(N, P);
+    size_t lds = (size_t)3 * K * (64 / P) * sizeof(double);
+    switch (P) {
+    case 4: k_adj_theta<4><<<nblk, 64, lds, s>>>(N, K, c.st, c.bx, c.nl, c.pot, gs, e, sv, lam, fpv, partial); break;
+    case 8: k_adj_theta<8><<<nblk, 64, lds, s>>>(N, K, c.st, c.bx, c.nl, c.pot, gs, e, sv, lam, fpv, partial); break;
+    case 16: k_adj_theta<16><<<nblk, 64, lds, s>>>(N, K, c.st, c.bx, c.nl, c.pot, gs, e, sv, lam, fpv, partial); break;
+    case 32: k_adj_theta<32><<<nblk, 64, lds, s>>>(N, K, c.st, c.bx, c.nl, c.pot, gs, e, sv, lam, fpv, partial); break;
+    default: k_adj_theta<64><<<nblk, 64, lds, s>>>(N, K, c.st, c.bx, c.nl, c.pot, gs, e, sv, lam, fpv, partial); break;
+    }
     k_adj_reduce<<<3 * K, kBlock, 0, s>>>(nblk, 3 * K, partial, gtheta);
 }
 

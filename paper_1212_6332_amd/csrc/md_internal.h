@@ -15,6 +15,12 @@ constexpr int kBlock = 256;        // threads per workgroup of the per-atom kern
 // Threads per workgroup of the per-atom pair passes: one wavefront while the
 // atoms are too few to give every compute unit several 256-thread workgroups.
 inline int atom_block(int64_t n) { return n < 262144 ? 64 : kBlock; }
+// Lanes that share the neighbour row of one atom in the per-atom pair passes:
+// several while the atoms alone are too few to keep every SIMD busy (each
+// lane then waits out a shorter chain of dependent gathers).
+constexpr int kRowLanes = 4;
+constexpr int64_t kRowSplitAtoms = 65536;
+inline int row_lanes(int64_t n) { return n < kRowSplitAtoms ? kRowLanes : 1; }
 constexpr int kChunk = 4096;       // atoms per partial sum of the energy reductions
 constexpr int kTileThreads = 1024; // threads of a tiled-pass workgroup (one tile)
 constexpr int kHaloCells = 512;    // halo cells a tile may have

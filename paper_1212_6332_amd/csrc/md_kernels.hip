@@ -78,25 +78,25 @@ __device__ __forceinline__ Row row_of(const NList &nl, int i)
     return Row{(int)(w & 0xffffu), (int)(w >> 16)};
 }
 
-// Visit rows [n0, n1) of the column of slot i.  Software pipelined: while
-// pair n is evaluated, the record of pair n+1 and the index of pair n+2 are
-// already in flight.  Each pair costs one coalesced index load and two
-// 16-byte loads from one 32-byte record.
-template <bool IMG, bool FPJ, class Body>
+// Visit rows n0, n0 + S, ... below n1 of the column of slot i.  Software
+// pipelined: while pair n is evaluated, the record of pair n+S and the index
+// of pair n+2S are already in flight.  Each pair costs one coalesced index
+// load and two 16-byte loads from one 32-byte record.
+template <bool IMG, bool FPJ, int S = 1, class Body>
 __device__ __forceinline__ void for_pairs(const int *__restrict__ idx, int i, int N, int n0, int n1,
                                           const double *__restrict__ pk, double xi, double yi,
                                           double zi, double L, double invL, Body &&body)
 {
     if (n0 >= n1) return;
     unsigned j = (unsigned)idx[nl_off(n0, i, N)];
-    unsigned jn = (n0 + 1 < n1) ? (unsigned)idx[nl_off(n0 + 1, i, N)] : j;
+    unsigned jn = (n0 + S < n1) ? (unsigned)idx[nl_off(n0 + S, i, N)] : j;
     double2 a = ldpk(pk, j, 0);
     double2 b;
     if constexpr (FPJ) b = ldpk(pk, j, 1);
     else b.x = ldpk_z(pk, j);
     unsigned jc = j;
-    for (int n = n0; n < n1; ++n) {
-        unsigned jnn = (n + 2 < n1) ? (unsigned)idx[nl_off(n + 2, i, N)] : jn;
+    for (int n = n0; n < n1; n += S) {
+        unsigned jnn = (n + 2 * S < n1) ? (unsigned)idx[nl_off(n + 2 * S, i, N)] : jn;
         double2 an = ldpk(pk, jn, 0);
         double2 bn;
         if constexpr (FPJ) bn = ldpk(pk, jn, 1);
@@ -113,6 +113,26 @@ __device__ __forceinline__ void for_pairs(const int *__restrict__ idx, int i, in
         a = an;
         b = bn;
     }
+}
+
+// P lanes share the row of one atom (P a power of two dividing 64, lanes of
+// an atom adjacent): lane `part` takes the rows congruent to part modulo P,
+// which keeps the four-entry groups of the list layout coalesced.
+template <int P>
+struct RowLanes {
+    int i, part;
+    __device__ __forceinline__ RowLanes(int t) : i(t / P), part(t % P) {}
+    // first row of this lane at or above n
+    __device__ __forceinline__ int first(int n) const { return n + ((part - n) & (P - 1)); }
+};
+
+// Sum over the P lanes of an atom by a fixed butterfly: every lane ends
+// with the same value, whatever the lane.
+template <int P>
+__device__ __forceinline__ double lanes_sum(double v)
+{
+    for (int o = 1; o < P; o <<= 1) v += __shfl_xor(v, o);
+    return v;
 }
 
 template <bool MULTI>
@@ -530,11 +550,12 @@ __global__ __launch_bounds__(kBlock) void k_nlist(const unsigned *gate, int N, S
 
 // Density pass with the embedding fused: rho_i over listed neighbours with
 // r < rc, then F(rho_i) and F'(rho_i).
-template <int KIND, bool MULTI>
+template <int KIND, bool MULTI, int P>
 __global__ __launch_bounds__(kBlock) void k_density(int N, State st, Boxes bx, NList nl, Pot pot,
                                                     double L1, double invL1, unsigned *flags)
 {
-    int i = atom_index();
+    const RowLanes<P> rl(atom_index());
+    const int i = rl.i;
     if (i >= N) return;
     double L, invL;
     box_geom<MULTI>(bx, i, L1, invL1, L, invL);
@@ -553,8 +574,14 @@ __global__ __launch_bounds__(kBlock) void k_density(int N, State st, Boxes bx, N
                 rho += dens<KIND>(pot, r2 * rsqrt_nr(r2), bad);
         }
     };
-    for_pairs<false, false>(nl.idx, i, N, 0, rw.np, pk, xi, yi, zi, L, invL, body);
-    for_pairs<true, false>(nl.idx, i, N, nl.mn - rw.ni, nl.mn, pk, xi, yi, zi, L, invL, body);
+    for_pairs<false, false, P>(nl.idx, i, N, rl.part, rw.np, pk, xi, yi, zi, L, invL, body);
+    for_pairs<true, false, P>(nl.idx, i, N, rl.first(nl.mn - rw.ni), nl.mn, pk, xi, yi, zi, L,
+                              invL, body);
+    rho = lanes_sum<P>(rho);
+    if (rl.part != 0) {
+        raise_flags(flags, bad);
+        return;
+    }
     double F, Fp;
     if constexpr (KIND == kTyped)
         embed_typed(pot, rho, ai, F, Fp, bad);
@@ -586,12 +613,13 @@ __global__ void k_embed(int N, State st, Pot pot, unsigned *flags)
 // Force pass (eq. 3) gathered per atom, optionally fused with the second
 // half kick of velocity Verlet (and after it the half-step friction flow of
 // eq. (4)).
-template <int KIND, bool MULTI, bool ENERGY, bool KICK>
+template <int KIND, bool MULTI, bool ENERGY, bool KICK, int P>
 __global__ __launch_bounds__(kBlock) void k_force(int N, State st, Boxes bx, NList nl, Pot pot,
                                                   double L1, double invL1, double kick,
                                                   Thermo th, unsigned *flags)
 {
-    int i = atom_index();
+    const RowLanes<P> rl(atom_index());
+    const int i = rl.i;
     if (i >= N) return;
     double L, invL;
     box_geom<MULTI>(bx, i, L1, invL1, L, invL);
@@ -628,8 +656,20 @@ __global__ __launch_bounds__(kBlock) void k_force(int N, State st, Boxes bx, NLi
             }
         }
     };
-    for_pairs<false, true>(nl.idx, i, N, 0, rw.np, pk, xi, yi, zi, L, invL, body);
-    for_pairs<true, true>(nl.idx, i, N, nl.mn - rw.ni, nl.mn, pk, xi, yi, zi, L, invL, body);
+    for_pairs<false, true, P>(nl.idx, i, N, rl.part, rw.np, pk, xi, yi, zi, L, invL, body);
+    for_pairs<true, true, P>(nl.idx, i, N, rl.first(nl.mn - rw.ni), nl.mn, pk, xi, yi, zi, L,
+                             invL, body);
+    ax = lanes_sum<P>(ax);
+    ay = lanes_sum<P>(ay);
+    az = lanes_sum<P>(az);
+    if constexpr (ENERGY) {
+        ep = lanes_sum<P>(ep);
+        wv = lanes_sum<P>(wv);
+    }
+    if (rl.part != 0) {
+        raise_flags(flags, bad);
+        return;
+    }
     st.fx[i] = ax;
     st.fy[i] = ay;
     st.fz[i] = az;
@@ -923,25 +963,41 @@ template <int KIND, bool MULTI>
 void density_t(Ctx &c, hipStream_t s)
 {
     int blk = atom_block(c.N);
-    k_density<KIND, MULTI><<<grid_for(c.N, blk), blk, 0, s>>>(
-        (int)c.N, c.st, c.bx, c.nl, c.pot, c.box_len[0], 1.0 / c.box_len[0], c.dev.flags);
+    int N = (int)c.N;
+    double L = c.box_len[0], iL = 1.0 / c.box_len[0];
+    if (row_lanes(c.N) == kRowLanes)
+        k_density<KIND, MULTI, kRowLanes><<<grid_for(c.N * kRowLanes, blk), blk, 0, s>>>(
+            N, c.st, c.bx, c.nl, c.pot, L, iL, c.dev.flags);
+    else
+        k_density<KIND, MULTI, 1><<<grid_for(c.N, blk), blk, 0, s>>>(N, c.st, c.bx, c.nl, c.pot,
+                                                                      L, iL, c.dev.flags);
+}
+
+template <int KIND, bool MULTI, int P>
+void force_p(Ctx &c, bool energy, bool kick, int blk, hipStream_t s)
+{
+    double k = 0.5 * c.dt * (1.602176634e-19 / 1.66053906660e-27 * 1e-10) / c.mass;
+    double L = c.box_len[0], iL = 1.0 / c.box_len[0];
+    int g = grid_for(c.N * P, blk);
+    int N = (int)c.N;
+    if (energy && kick)
+        k_force<KIND, MULTI, true, true, P><<<g, blk, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.thermo, c.dev.flags);
+    else if (energy)
+        k_force<KIND, MULTI, true, false, P><<<g, blk, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.thermo, c.dev.flags);
+    else if (kick)
+        k_force<KIND, MULTI, false, true, P><<<g, blk, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.thermo, c.dev.flags);
+    else
+        k_force<KIND, MULTI, false, false, P><<<g, blk, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.thermo, c.dev.flags);
 }
 
 template <int KIND, bool MULTI>
 void force_t(Ctx &c, bool energy, bool kick, hipStream_t s)
 {
-    double k = 0.5 * c.dt * (1.602176634e-19 / 1.66053906660e-27 * 1e-10) / c.mass;
-    double L = c.box_len[0], iL = 1.0 / c.box_len[0];
-    int blk = atom_block(c.N), g = grid_for(c.N, blk);
-    int N = (int)c.N;
-    if (energy && kick)
-        k_force<KIND, MULTI, true, true><<<g, blk, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.thermo, c.dev.flags);
-    else if (energy)
-        k_force<KIND, MULTI, true, false><<<g, blk, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.thermo, c.dev.flags);
-    else if (kick)
-        k_force<KIND, MULTI, false, true><<<g, blk, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.thermo, c.dev.flags);
+    int blk = atom_block(c.N);
+    if (row_lanes(c.N) == kRowLanes)
+        force_p<KIND, MULTI, kRowLanes>(c, energy, kick, blk, s);
     else
-        k_force<KIND, MULTI, false, false><<<g, blk, 0, s>>>(N, c.st, c.bx, c.nl, c.pot, L, iL, k, c.thermo, c.dev.flags);
+        force_p<KIND, MULTI, 1>(c, energy, kick, blk, s);
 }
 
 }  // namespace

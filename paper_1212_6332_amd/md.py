@@ -8,6 +8,7 @@ is missing, loading fails with an error.
 from __future__ import annotations
 
 import ctypes as C
+import functools
 import os
 
 import numpy as np
@@ -138,6 +139,17 @@ class _PotHolder:
         self.s = s
 
 
+def _mutates(fn):
+    """Methods that change the state, the list or the settings of a context
+    count up `System.epoch`: work captured in a graph before them no longer
+    describes the context."""
+    @functools.wraps(fn)
+    def wrap(self, *a, **k):
+        self.epoch = getattr(self, "epoch", 0) + 1
+        return fn(self, *a, **k)
+    return wrap
+
+
 class System:
     """One md_ctx: B periodic cubic boxes sharing a potential.
 
@@ -176,6 +188,7 @@ class System:
                    "md_create_in")
         self._workspace = workspace
         self._h = h
+        self.epoch = 0
 
     @staticmethod
     def workspace_size(box_offset, box_len, pot, mass, dt=1.0, skin=0.3, max_neighbors=0):
@@ -205,6 +218,7 @@ class System:
             s.set_types(W.types, W.type_mass)
         return s
 
+    @_mutates
     def autotune(self):
         """Pick the fastest workgroup size of the persistent multi-box stepper
         (md_autotune); returns it."""
@@ -212,6 +226,7 @@ class System:
         _check(lib().md_autotune(self._h, _stream(), C.byref(b)), "md_autotune")
         return int(b.value)
 
+    @_mutates
     def set_frozen(self, frozen):
         """Atom states: a nonzero entry (host array, original order) freezes that atom;
         None frees every atom."""
@@ -223,6 +238,7 @@ class System:
             raise ValueError("one flag per atom")
         _check(lib().md_set_frozen(self._h, f.ctypes.data_as(C.c_void_p)), "md_set_frozen")
 
+    @_mutates
     def set_types(self, types, type_mass=None):
         """Species of every atom (host array, original order) and per-species masses."""
         t = np.ascontiguousarray(np.asarray(types, dtype=np.int32))
@@ -234,6 +250,7 @@ class System:
                                   None if m is None else m.ctypes.data_as(C.c_void_p)),
                "md_set_types")
 
+    @_mutates
     def close(self):
         if getattr(self, "_h", None):
             torch.cuda.synchronize()
@@ -250,6 +267,7 @@ class System:
     def _f64(self, *shape):
         return torch.empty(*shape, dtype=torch.float64, device=self.device)
 
+    @_mutates
     def set_state(self, pos, vel=None):
         p = _dev_f64(pos, self.device)
         v = None if vel is None else _dev_f64(vel, self.device)
@@ -261,6 +279,7 @@ class System:
         _check(lib().md_get_state(self._h, _ptr(p), _ptr(v), _stream()), "md_get_state")
         return p, v
 
+    @_mutates
     def set_potential(self, pot):
         holder = _PotHolder(pot)
         _check(lib().md_set_potential(self._h, C.byref(holder.s), _stream()), "md_set_potential")
@@ -280,6 +299,7 @@ class System:
         # the copy is stream ordered; holding t keeps its memory until the next upload
         self._theta = (t, t._version)
 
+    @_mutates
     def build_neighbors(self):
         _check(lib().md_build_neighbors(self._h, _stream()), "md_build_neighbors")
 
@@ -300,6 +320,7 @@ class System:
         _check(lib().md_forces(self._h, _ptr(f), _ptr(e), _ptr(eb), _stream()), "md_forces")
         return (f, e, eb) if energy else f
 
+    @_mutates
     def step(self, nsteps):
         _check(lib().md_step(self._h, int(nsteps), _stream()), "md_step")
 
@@ -322,6 +343,7 @@ class System:
         _check(lib().md_max_neighbors(self._h, C.byref(v)), "md_max_neighbors")
         return v.value
 
+    @_mutates
     def set_max_neighbors(self, mn):
         _check(lib().md_set_max_neighbors(self._h, int(mn)), "md_set_max_neighbors")
 
@@ -347,11 +369,13 @@ class System:
         _check(lib().md_pressure(self._h, _ptr(p), _ptr(w), _stream()), "md_pressure")
         return p, w
 
+    @_mutates
     def set_barostat(self, p0, tau, beta):
         """Berendsen barostat of eq. (5) in md_step; tau <= 0 switches it off."""
         _check(lib().md_set_barostat(self._h, float(p0), float(tau), float(beta)),
                "md_set_barostat")
 
+    @_mutates
     def set_thermostat(self, t_e, tau_t):
         """Electron-gas friction of eq. (4) in md_step; tau_t <= 0 switches it off."""
         _check(lib().md_set_thermostat(self._h, float(t_e), float(tau_t)), "md_set_thermostat")
@@ -362,6 +386,7 @@ class System:
         _check(lib().md_get_box(self._h, out.ctypes.data_as(C.c_void_p), _stream()), "md_get_box")
         return out
 
+    @_mutates
     def time_pass(self, which, reps):
         """Mean duration (ms) of one launch of a pass, from HIP events on the stream."""
         ms = C.c_double()
@@ -369,6 +394,7 @@ class System:
                "md_time_pass")
         return ms.value
 
+    @_mutates
     def set_option(self, key, value):
         _check(lib().md_set_option(self._h, int(key), int(value)), "md_set_option")
 

@@ -206,6 +206,49 @@ def test_set_theta_sees_in_place_changes():
     assert torch.equal(f1, f2) and torch.equal(e1, e2)
 
 
+def test_graphed_loss_replays_match_eager_and_oracle():
+    """The loss and its backward pass captured in a graph and replayed with
+    new coefficients (eager evaluations between the replays) give the eager
+    loss and gradient bit for bit every time, and the last one matches the
+    oracle; once the system moves on, replay is refused."""
+    import dataclasses
+    from paper_1212_6332_amd.autograd import GraphedLoss
+    wl, S = adjoint_setup(4)
+    w = wl.extra["w"]
+    tgt = O.forces_multi(wl, pot=O.Pot(wl.extra["target_pot"]))
+    ft = torch.tensor(tgt["f"], device="cuda")
+    et = torch.tensor(tgt["E_box"], device="cuda")
+    th = [torch.tensor(t, device="cuda", requires_grad=True) for t in wl.pot.tables]
+    G = GraphedLoss(S, th, lambda: force_matching_loss(S, *th, ft, et, w))
+    rng = np.random.default_rng(5)
+    for rep in range(4):
+        vals = [np.asarray(t) * (1 + 0.01 * rng.normal(size=np.shape(t))) for t in wl.pot.tables]
+        with torch.no_grad():
+            for t, v in zip(th, vals):
+                t.copy_(torch.tensor(v, device="cuda"))
+        loss, grads = G.replay()
+        lg, gg = float(loss), torch.cat(grads).cpu().numpy()
+        ts = [torch.tensor(v, device="cuda", requires_grad=True) for v in vals]
+        le = force_matching_loss(S, *ts, ft, et, w)
+        le.backward()
+        assert lg == float(le), rep
+        assert np.array_equal(gg, torch.cat([t.grad for t in ts]).cpu().numpy()), rep
+    pot = O.Pot(dataclasses.replace(wl.pot, tables=tuple(vals)))
+    out = O.forces_multi(wl, pot=pot)
+    L0 = float(((out["f"] - tgt["f"]) ** 2).sum() + w * ((out["E_box"] - tgt["E_box"]) ** 2).sum())
+    assert abs(lg - L0) <= 1e-11 * L0
+    g = 2.0 * (out["f"] - tgt["f"])
+    e = 2.0 * w * (out["E_box"] - tgt["E_box"])
+    ref = np.zeros(192)
+    for b, s, L in O.boxes(wl):
+        O.adjoint(O.wrap(wl.pos[s], L), L, pot, g[s], e[b], gtheta=ref)
+    assert rel(gg, ref) < 1e-9
+    S.step(1)
+    with pytest.raises(RuntimeError):
+        G.replay()
+    S.close()
+
+
 def test_autograd_matches_finite_differences():
     wl, S = adjoint_setup(2)
     w = wl.extra["w"]
