@@ -245,12 +245,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_reduce(int nblk, int K3,
 
 }  // namespace
 
-// Lanes per atom of the coefficient kernel: the fewest (at least four) that
+// Lanes per atom of the coefficient kernel: the fewest (at least eight) that
 // keep the columns of its 64 / P atoms within 32 KiB of LDS, else one atom
 // per workgroup with up to 64 KiB; 0 when even that does not fit.
 int adjoint_lanes(int K)
 {
-    for (int p = 4; p <= 64; p *= 2)
+    for (int p = 8; p <= 64; p *= 2)
         if ((size_t)3 * K * (64 / p) * sizeof(double) <= 32768) return p;
     return (size_t)3 * K * sizeof(double) <= 65536 ? 64 : 0;
 }
@@ -280,7 +280,6 @@ void launch_adjoint(Ctx &c, const double *g, const double *e, double *gtheta, hi
     int nblk = (int)adjoint_blocks(N, P);
     size_t lds = (size_t)3 * K * (64 / P) * sizeof(double);
     switch (P) {
-    case 4: k_adj_theta<4><<<nblk, 64, lds, s>>>(N, K, c.st, c.bx, c.nl, c.pot, gs, e, sv, lam, fpv, partial); break;
     case 8: k_adj_theta<8><<<nblk, 64, lds, s>>>(N, K, c.st, c.bx, c.nl, c.pot, gs, e, sv, lam, fpv, partial); break;
     case 16: k_adj_theta<16><<<nblk, 64, lds, s>>>(N, K, c.st, c.bx, c.nl, c.pot, gs, e, sv, lam, fpv, partial); break;
     case 32: k_adj_theta<32><<<nblk, 64, lds, s>>>(N, K, c.st, c.bx, c.nl, c.pot, gs, e, sv, lam, fpv, partial); break;

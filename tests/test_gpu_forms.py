@@ -157,6 +157,32 @@ def test_adjoint_vjp_matches_oracle(n_boxes):
         assert rel(gt[sl], ref[sl]) < 1e-10, (blk, rel(gt[sl], ref[sl]))
 
 
+@pytest.mark.parametrize("ncoef", [200, 700])
+def test_adjoint_many_coefficients_matches_oracle(ncoef):
+    """Coefficient counts whose LDS columns leave room for fewer atoms per
+    workgroup (more lanes per atom: 16 lanes at 200, 64 at 700)."""
+    wl = W.adjoint64(n_boxes=3)
+    par = W.draw_fs(np.random.default_rng(21), "bcc", 2.8665, 5.3)
+    r, n = W.shells("bcc", 2.8665, 5.3)
+    rho0 = float((n * (r - 5.3) ** 2).sum())
+    pot = W.bspline_from_fs(par, 1.5, 5.3, 2.0 * rho0, ncoef=ncoef)
+    S = md.System.from_workload(wl, pot)
+    S.set_state(wl.pos)
+    rng = np.random.default_rng(12)
+    g = rng.normal(size=(wl.n_atoms, 3))
+    e = rng.normal(size=wl.n_boxes)
+    gt = S.adjoint(torch.tensor(g, device="cuda"), torch.tensor(e, device="cuda")).cpu().numpy()
+    assert S.status()[0] == 0
+    S.close()
+    opot = O.Pot(pot)
+    ref = np.zeros(3 * ncoef)
+    for b, s, L in O.boxes(wl):
+        O.adjoint(O.wrap(wl.pos[s], L), L, opot, g[s], e[b], gtheta=ref)
+    for blk in range(3):
+        sl = slice(ncoef * blk, ncoef * (blk + 1))
+        assert rel(gt[sl], ref[sl]) < 1e-10, (blk, rel(gt[sl], ref[sl]))
+
+
 def test_autograd_loss_gradient_matches_oracle():
     wl, S = adjoint_setup(4)
     w = wl.extra["w"]
