@@ -121,6 +121,24 @@ def timed_steps(S, steps, warmup):
     return t1 - t0, ev0.elapsed_time(ev1) / 1e3, b1 - b0
 
 
+def copy_gbs(nbytes=1 << 31, reps=5):
+    """HBM bandwidth of a plain device-to-device copy (bytes read plus
+    written per second), the practical ceiling beside the nominal 8 TB/s."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    t = ev0.elapsed_time(ev1) / 1e3 / reps
+    del src, dst
+    return 2 * nbytes / t / 1e9
+
+
 def bench_main(steps, warmup, reps):
     import torch
     from paper_1212_6332_amd import md, workloads as W
@@ -159,7 +177,8 @@ def bench_main(steps, warmup, reps):
                              "algorithmic_gbs": fbytes / (ms["force"] * 1e-3) / 1e9,
                              "measured_gbs": (traffic / (ms["force"] * 1e-3) / 1e9
                                               if traffic else None),
-                             "peak_gbs": HBM_PEAK_GBS},
+                             "peak_gbs": HBM_PEAK_GBS,
+                             "copy_kernel_gbs": copy_gbs()},
                      "density_pass": {"ops_per_launch": d_ops,
                                       "achieved": d_ops / (ms["density"] * 1e-3) / 1e12,
                                       "algorithmic_gbs": density_pass_bytes(n, mean_list)

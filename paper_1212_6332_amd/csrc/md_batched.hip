@@ -10,7 +10,9 @@
 // kick) are separated by workgroup barriers only, since no box spans two
 // workgroups.  The rebuild (wrap, bin, in-cell order by local index, stencil
 // scan) runs inside the workgroup on LDS data, and each box decides its own
-// rebuilds.  Neighbour rows hold 16-bit local indices, slot-fastest.
+// rebuilds.  Neighbour rows hold 16-bit local indices in groups of four per
+// atom (one 8-byte load per group, the next group in flight while the
+// current one is evaluated), slot-fastest.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -185,6 +187,34 @@ __device__ __forceinline__ int stencil_1d(int c, int nc, int out[3])
     return 3;
 }
 
+// Entry m of local atom i in a box of n atoms: group m / 4 of the atom,
+// groups of all atoms of the box contiguous (the capacity is a multiple of 4).
+__device__ __forceinline__ size_t row16_off(int m, int i, int n)
+{
+    return (((size_t)(m >> 2) * n + i) << 2) + (m & 3);
+}
+
+// Visit the c entries of local atom i: one 8-byte load per group of four,
+// group q + 1 in flight while group q is evaluated.
+template <class Body>
+__device__ __forceinline__ void for_row16(const uint16_t *__restrict__ lst, int i, int n, int c,
+                                          Body &&body)
+{
+    if (c <= 0) return;
+    const uint2 *g = reinterpret_cast<const uint2 *>(lst) + i;
+    const int ng = (c + 3) >> 2;
+    uint2 cur = g[0];
+    for (int q = 0; q < ng; ++q) {
+        const uint2 nxt = q + 1 < ng ? g[(size_t)(q + 1) * n] : cur;
+        const int m = min(4, c - 4 * q);
+        const unsigned e[4] = {cur.x & 0xffffu, cur.x >> 16, cur.y & 0xffffu, cur.y >> 16};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (u < m) body((int)e[u]);
+        cur = nxt;
+    }
+}
+
 template <int KIND, int T>
 __global__ __launch_bounds__(T) void k_batched(BArgs a)
 {
@@ -285,7 +315,7 @@ __global__ __launch_bounds__(T) void k_batched(BArgs a)
                                 dz = dz - rint(dz * invL) * L;
                                 double r2 = (dx * dx + dy * dy) + dz * dz;
                                 if (r2 < bx.rl2) {
-                                    if (m < a.mn) lst[(size_t)m * n + i] = (uint16_t)j;
+                                    if (m < a.mn) lst[row16_off(m, i, n)] = (uint16_t)j;
                                     ++m;
                                 }
                             }
@@ -301,15 +331,13 @@ __global__ __launch_bounds__(T) void k_batched(BArgs a)
                 double xi = X[i], yi = Y[i], zi = Z[i];
                 int c = min(cnt[i], a.mn);
                 double rho = 0.0;
-                const uint16_t *lp = lst + i;
-                for (int m = 0; m < c; ++m, lp += n) {
-                    int j = *lp;
+                for_row16(lst, i, n, c, [&](int j) {
                     double dx = min_image(X[j] - xi, L, invL);
                     double dy = min_image(Y[j] - yi, L, invL);
                     double dz = min_image(Z[j] - zi, L, invL);
                     double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
                     if (r2 < pot.rc2) rho += dens<KIND>(pot, r2 * dev::rsqrt_nr(r2), bad);
-                }
+                });
                 FP[i] = embed_fp<KIND>(pot, rho, bad);
             }
             __syncthreads();
@@ -320,9 +348,7 @@ __global__ __launch_bounds__(T) void k_batched(BArgs a)
                 double xi = X[i], yi = Y[i], zi = Z[i], fpi = FP[i];
                 int c = min(cnt[i], a.mn);
                 double ax = 0.0, ay = 0.0, az = 0.0;
-                const uint16_t *lp = lst + i;
-                for (int m = 0; m < c; ++m, lp += n) {
-                    int j = *lp;
+                for_row16(lst, i, n, c, [&](int j) {
                     double dx = min_image(X[j] - xi, L, invL);
                     double dy = min_image(Y[j] - yi, L, invL);
                     double dz = min_image(Z[j] - zi, L, invL);
@@ -335,7 +361,7 @@ __global__ __launch_bounds__(T) void k_batched(BArgs a)
                         ay = fma(coef, dy, ay);
                         az = fma(coef, dz, az);
                     }
-                }
+                });
                 fx[i] = ax;
                 fy[i] = ay;
                 fz[i] = az;
