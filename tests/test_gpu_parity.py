@@ -123,13 +123,18 @@ def test_perfect_lattice_zero_force():
         assert np.all(g["counts"] == g["counts"][0])
 
 
-@pytest.mark.parametrize("name,nsample", [("bcc128k", 96), ("fcc4m", 48)])
-def test_full_size_sampled(name, nsample):
+@pytest.mark.parametrize("name,nsample,tiled", [("bcc128k", 96, None), ("fcc4m", 48, None),
+                                                ("bcc128k", 48, 0), ("fcc4m", 24, 0)])
+def test_full_size_sampled(name, nsample, tiled):
     """Full-size workloads in the configuration the benchmark times, checked on
-    sampled atoms the oracle evaluates one by one."""
+    sampled atoms the oracle evaluates one by one; also through the per-atom
+    kernels, which at these sizes give each atom one lane (one-wavefront
+    workgroups at 128,000 atoms, 256-thread workgroups at 4,000,000)."""
     wl = W.WORKLOADS[name]()
     L = wl.box_len[0, 0]
     S = md.System.from_workload(wl)
+    if tiled is not None:
+        S.set_option(md.MD_OPT_TILED, tiled)
     S.set_state(wl.pos, wl.vel)
     S.build_neighbors()
     S.density()
