@@ -162,7 +162,9 @@ const char *md_strerror(int code);
 int md_set_potential(md_ctx *ctx, const md_potential *pot, void *stream);
 
 /* B-spline potentials only: upload 3K coefficients (device pointer, order
- * V, rho, F) and convert them on the device to per-interval cubics. */
+ * V, rho, F) and convert them on the device to per-interval cubics.  A
+ * stream-ordered device copy and two kernels, no allocation and no host
+ * synchronisation: the call may be captured in a HIP graph. */
 int md_set_theta(md_ctx *ctx, const double *theta, void *stream);
 
 /* Load positions pos[N][3] and velocities vel[N][3] (vel may be NULL: zero).
@@ -224,7 +226,12 @@ int md_status(md_ctx *ctx, void *stream, uint32_t *flags, int64_t *counters);
  * respect to the B-spline coefficients (MD_POT_BSPLINE only).  g[N][3] =
  * dL/df_i, e[B] = dL/dE_b (device); writes gtheta[3K] (device, order V, rho,
  * F).  Recomputes rho, F'(rho) and F''(rho) from the current positions and
- * list; the reduction order is fixed, so results are bitwise reproducible. */
+ * list; the reduction order is fixed, so results are bitwise reproducible.
+ * Contexts with more than 2,730 coefficients per function are refused by
+ * md_create (MD_ERR_ARG: the per-atom columns must fit in LDS).  Once the
+ * list is current (any earlier pass) the call only launches kernels on the
+ * stream, with no allocation or synchronisation, so a forward pass and this
+ * call may be captured together in a HIP graph. */
 int md_adjoint(md_ctx *ctx, const double *g, const double *e, double *gtheta, void *stream);
 
 /* Instantaneous pressure per box, eq. (6) of Section 2:

@@ -85,6 +85,8 @@ int check_potential(const md_potential *p)
         }
         if (p->kind == MD_POT_BSPLINE && (p->n_tab[0] != p->n_tab[1] || p->n_tab[0] != p->n_tab[2]))
             return MD_ERR_ARG;
+        // the adjoint keeps 3K coefficient sums per atom in LDS
+        if (p->kind == MD_POT_BSPLINE && adjoint_lanes(p->n_tab[0]) == 0) return MD_ERR_ARG;
         return MD_OK;
     }
     return MD_ERR_ARG;

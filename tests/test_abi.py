@@ -84,6 +84,25 @@ def test_several_species_descriptor_checks():
     assert not h.value
 
 
+def test_bspline_coefficient_limit_is_refused():
+    """B-spline potentials: up to 2,730 coefficients per function (the
+    adjoint's per-atom LDS column of 3K sums); one more is refused on the host
+    before any device call, while 2,730 passes the potential checks and then
+    meets the too-small box (MD_ERR_BOX)."""
+    from paper_1212_6332_amd import md, workloads as W
+    L = md.lib()
+    off = np.array([0, 16], dtype=np.int64)
+    bl = np.array([5.0])
+    s = md.md_system(n_boxes=1, max_neighbors=0, box_offset=off.ctypes.data,
+                     box_len=bl.ctypes.data, mass=55.845, dt=1.0, skin=0.3)
+    par = W.draw_fs(np.random.default_rng(21), "bcc", 2.8665, 5.3)
+    h = C.c_void_p()
+    for k, code in ((2730, md.MD_ERR_BOX), (2731, md.MD_ERR_ARG)):
+        pot = md._PotHolder(W.bspline_from_fs(par, 1.5, 5.3, 60.0, ncoef=k))
+        assert L.md_create(C.byref(s), C.byref(pot.s), C.byref(h)) == code, k
+    assert not h.value
+
+
 def test_empty_box_and_size_limit_are_refused():
     """A box with fewer than two atoms, and 2^27 atoms or more, are refused on
     the host (MD_ERR_ARG) before any device call."""

@@ -157,10 +157,11 @@ def test_adjoint_vjp_matches_oracle(n_boxes):
         assert rel(gt[sl], ref[sl]) < 1e-10, (blk, rel(gt[sl], ref[sl]))
 
 
-@pytest.mark.parametrize("ncoef", [200, 700])
+@pytest.mark.parametrize("ncoef", [200, 700, 2730])
 def test_adjoint_many_coefficients_matches_oracle(ncoef):
     """Coefficient counts whose LDS columns leave room for fewer atoms per
-    workgroup (more lanes per atom: 16 lanes at 200, 64 at 700)."""
+    workgroup (more lanes per atom: 16 lanes at 200, 64 at 700 and at the
+    largest count a context accepts, 2,730)."""
     wl = W.adjoint64(n_boxes=3)
     par = W.draw_fs(np.random.default_rng(21), "bcc", 2.8665, 5.3)
     r, n = W.shells("bcc", 2.8665, 5.3)
