@@ -298,16 +298,21 @@ int md_set_thermostat(md_ctx *ctx, double t_e, double tau_t);
 /* Current box edges (host box_len[B]; synchronises stream). */
 int md_get_box(md_ctx *ctx, double *box_len, void *stream);
 
-/* Autotuner of the persistent multi-box stepper (the md_step path of
- * contexts with several boxes): times the workgroup sizes 256, 512 and 1024
- * on the context's own boxes (20 steps each after a warm-up), keeps the
- * fastest as MD_OPT_BATCH_BLOCK and writes it to *block (host).  Positions
- * and velocities are restored afterwards, and the next md_step rebuilds the
+/* Autotuner.  Contexts whose md_step runs the persistent multi-box stepper
+ * (several boxes): times the workgroup sizes 256, 512 and 1024 on the
+ * context's own boxes (20 steps each after a warm-up), keeps the fastest as
+ * MD_OPT_BATCH_BLOCK and writes it to *block (host).  Other contexts that
+ * can be tiled (one box, or boxes stepped by the merged-box kernels; not
+ * with the barostat): times the passes of a step (density, force with the
+ * fused kicks, a tenth of a list build) with the tiled and with the
+ * per-atom kernels and keeps the faster as MD_OPT_TILED (small systems,
+ * with fewer tiles than the GPU has room for, are often faster per atom);
+ * *block is then the unchanged MD_OPT_BATCH_BLOCK.  Positions and
+ * velocities are restored afterwards, and the next md_step rebuilds the
  * lists and recomputes the forces from them: called between md_set_state
  * and the first md_step, the trajectory is bitwise that of an untuned
- * context with the chosen size.  Synchronises.  Contexts that do not step
- * with that kernel (one box, the merged-box kernels, the barostat) are left
- * unchanged and *block is the current setting. */
+ * context with the chosen setting.  Synchronises.  Other contexts are left
+ * unchanged. */
 int md_autotune(md_ctx *ctx, void *stream, int32_t *block);
 
 /* Benchmarking: launch one pass `reps` times on `stream`, bracketed by HIP

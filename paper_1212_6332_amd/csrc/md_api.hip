@@ -865,13 +865,40 @@ int md_step(md_ctx *h, int nsteps, void *stream)
     return MD_OK;
 }
 
+// Switch between the tiled and the per-atom passes (as MD_OPT_TILED does).
+static void set_tiled(Ctx &c, bool v)
+{
+    if (v == c.tiled) return;
+    c.tiled = v;
+    graph_reset(c);
+    c.list_valid = c.density_valid = c.forces_valid = false;
+}
+
 int md_autotune(md_ctx *h, void *stream, int32_t *block)
 {
     if (!h || !block) return MD_ERR_ARG;
     Ctx &c = h->c;
     if (!c.state_set) return MD_ERR_STATE;
     *block = c.batch_block;
-    if (!(c.B > 1 && c.batched && !c.baro_on)) return MD_OK;  // md_step would not use it
+    if (!(c.B > 1 && c.batched && !c.baro_on)) {
+        // md_step runs the single-box passes: keep the faster of the tiled
+        // and the per-atom passes for a step (density, force with the fused
+        // kicks, a tenth of a list build), timed on the current state
+        if (!c.tile_feasible || c.baro_on) return MD_OK;
+        double cost[2] = {0.0, 0.0};
+        for (int t = 0; t < 2; ++t) {
+            set_tiled(c, t == 1);
+            double b = 0.0, d = 0.0, f = 0.0;
+            int rc;
+            if ((rc = md_time_pass(h, MD_PASS_BUILD, 2, stream, &b)) != MD_OK ||
+                (rc = md_time_pass(h, MD_PASS_DENSITY, 10, stream, &d)) != MD_OK ||
+                (rc = md_time_pass(h, MD_PASS_FORCE_STEP, 10, stream, &f)) != MD_OK)
+                return rc;
+            cost[t] = d + f + 0.1 * b;
+        }
+        set_tiled(c, cost[1] <= cost[0]);
+        return MD_OK;
+    }
     hipStream_t s = as_stream(stream);
     const size_t nb = sizeof(double) * (size_t)c.N;
     double *keep[6] = {c.bd.sx, c.bd.sy, c.bd.sz, c.bd.svx, c.bd.svy, c.bd.svz};
@@ -1211,11 +1238,7 @@ int md_set_option(md_ctx *h, int32_t key, int64_t v)
         return MD_OK;
     case MD_OPT_TILED:
         if (v && !c.tile_feasible) return MD_ERR_ARG;
-        if ((v != 0) != c.tiled) {
-            c.tiled = v != 0;
-            graph_reset(c);
-            c.list_valid = c.density_valid = c.forces_valid = false;
-        }
+        set_tiled(c, v != 0);
         return MD_OK;
     }
     return MD_ERR_ARG;

@@ -19,7 +19,7 @@ inline int atom_block(int64_t n) { return n < 262144 ? 64 : kBlock; }
 // several while the atoms alone are too few to keep every SIMD busy (each
 // lane then waits out a shorter chain of dependent gathers).
 constexpr int kRowLanes = 8;
-constexpr int64_t kRowSplitAtoms = 65536;
+constexpr int64_t kRowSplitAtoms = 262144;
 inline int row_lanes(int64_t n) { return n < kRowSplitAtoms ? kRowLanes : 1; }
 constexpr int kChunk = 4096;       // atoms per partial sum of the energy reductions
 constexpr int kTileThreads = 1024; // threads of a tiled-pass workgroup (one tile)

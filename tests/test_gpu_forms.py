@@ -356,3 +356,42 @@ def test_autotune_and_graph_replay_keep_the_trajectory():
     one.set_state(W.fs256().pos, W.fs256().vel)
     assert one.autotune() == one.get_option(md.MD_OPT_BATCH_BLOCK)
     one.close()
+
+
+@pytest.mark.parametrize("name", ["bcc128k", "smtb5324"])
+def test_autotune_single_box_keeps_the_trajectory(name):
+    """For one box md_autotune chooses between the tiled and the per-atom
+    passes by timing them; the trajectory afterwards is bitwise that of an
+    untuned context with the chosen setting, and matches the oracle."""
+    wl = W.bcc128k() if name == "bcc128k" else W.fcc4m(ncell=11)
+    nsteps = 30
+
+    def run(tune, tiled=None):
+        S = md.System.from_workload(wl)
+        if tiled is not None:
+            S.set_option(md.MD_OPT_TILED, tiled)
+        S.set_state(wl.pos, wl.vel)
+        if tune:
+            S.autotune()
+        chosen = S.get_option(md.MD_OPT_TILED)
+        S.step(nsteps)
+        p, v = S.get_state()
+        st = S.status()
+        S.close()
+        return chosen, p.cpu().numpy(), v.cpu().numpy(), st
+
+    t, p1, v1, st1 = run(True)
+    assert t in (0, 1) and st1[0] == 0
+    other = 1 - t
+    _, p2, v2, _ = run(False, t)
+    assert np.array_equal(p1, p2) and np.array_equal(v1, v2)
+    _, p3, v3, _ = run(False, other)
+    L = wl.box_len[0, 0]
+    d = p1 - p3
+    assert np.abs(d - L * np.round(d / L)).max() < 1e-9
+    if name == "smtb5324":
+        x, v, *_ = O.vv(wl.pos, wl.vel, L, O.Pot(wl.pot), wl.mass, wl.dt, wl.skin, nsteps,
+                        energies=False)
+        d = p1 - x
+        assert np.abs(d - L * np.round(d / L)).max() < 1e-10
+        assert rel(v1, v) < 1e-9
