@@ -30,7 +30,7 @@ COUNTERS = os.path.join(ROOT, "profiles", "force_pass_fcc4m_counters.txt")
 CSRC = os.path.join(ROOT, "paper_1212_6332_amd", "csrc")
 # the sources the force kernel is compiled from
 KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("md_tiled.hip", "md_device.h", "md_internal.h")]
-FORCE_KERNEL = "k_tile_force<2, false, 1>"
+FORCE_KERNEL = "k_tile_force<2, false, 1, 1>"
 
 # Algorithmic FP64 work, in lane-operations (one VALU operation on one lane):
 # every list entry costs the separation (3 differences), r^2 (1 multiply,

@@ -341,22 +341,63 @@ int plan_tiles(Ctx &c, double per_cell, bool allow)
     size_t fixed = 8192;  // halo table and scan scratch (static LDS)
     c.hmax = max_lds > (int)fixed ? (int)((max_lds - fixed) / 32) : 0;
     c.tile_lds = (size_t)c.hmax * 32;
-    int best[3] = {0, 0, 0};
-    double best_atoms = 0.0;
-    for (int tz = 1; tz <= 6; ++tz)
-        for (int ty = tz; ty <= 6; ++ty)
-            for (int tx = ty; tx <= 6; ++tx) {
-                double atoms = tx * ty * tz * per_cell;
-                int halo_cells = (tx + 2) * (ty + 2) * (tz + 2);
-                double halo = halo_cells * per_cell;
-                if (atoms > 1100.0 || 1.3 * halo > c.hmax || halo_cells > kHaloCells) continue;
-                if (atoms > best_atoms) {
-                    best_atoms = atoms;
-                    best[0] = tx;
-                    best[1] = ty;
-                    best[2] = tz;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device) != hipSuccess)
+        return MD_ERR_DEVICE;
+    // the tile of at most max_atoms atoms (on average) and at most tlim cells
+    // per axis with the most atoms whose halo fits in LDS
+    auto pick = [&](double max_atoms, int tlim, int out[3]) {
+        double best_atoms = 0.0;
+        out[0] = out[1] = out[2] = 0;
+        for (int tz = 1; tz <= tlim; ++tz)
+            for (int ty = tz; ty <= tlim; ++ty)
+                for (int tx = ty; tx <= tlim; ++tx) {
+                    double atoms = tx * ty * tz * per_cell;
+                    int halo_cells = (tx + 2) * (ty + 2) * (tz + 2);
+                    double halo = halo_cells * per_cell;
+                    if (atoms > max_atoms || 1.3 * halo > c.hmax || halo_cells > kHaloCells)
+                        continue;
+                    if (atoms > best_atoms) {
+                        best_atoms = atoms;
+                        out[0] = tx;
+                        out[1] = ty;
+                        out[2] = tz;
+                    }
                 }
+    };
+    // tiles of all boxes for a tile shape (a box too small for it is one tile)
+    auto count = [&](const int t[3]) {
+        int tm = std::max(t[0], std::max(t[1], t[2]));
+        long long n = 0;
+        for (int b = 0; b < c.B; ++b) {
+            int nc = c.box_nc[b];
+            n += nc >= tm + 2 ? (long long)((nc + t[0] - 1) / t[0]) * ((nc + t[1] - 1) / t[1]) *
+                                    ((nc + t[2] - 1) / t[2])
+                              : 1;
+        }
+        return n;
+    };
+    int best[3];
+    pick(1100.0, 6, best);
+    // a system of fewer than two rounds of tiles (one per compute unit) runs
+    // half-size tiles, each atom's row shared by two lanes, when that takes
+    // fewer rounds of half the length: more compute units work on half rows.
+    // Half tiles are no longer along any axis, so no box loses its tiling;
+    // larger systems keep the full tiles (their halo overhead would grow).
+    c.tile_lanes = 1;
+    if (best[0] > 0 && count(best) < 2LL * cus) {
+        int half[3];
+        pick(550.0, best[0], half);
+        long long nf = count(best), nh = half[0] > 0 ? count(half) : nf;
+        if ((nh + cus - 1) / cus < 2 * ((nf + cus - 1) / cus)) {
+            if (half[0] > 0) {
+                best[0] = half[0];
+                best[1] = half[1];
+                best[2] = half[2];
             }
+            c.tile_lanes = 2;
+        }
+    }
     bool feasible = allow && best[0] > 0;
     int tmax = std::max(best[0], std::max(best[1], best[2]));
     for (int b = 0; b < c.B && feasible; ++b) {

@@ -236,6 +236,7 @@ struct Ctx {
     std::vector<int> box_tile;         // per box: tx ty tz gx gy gz tile_cells mode
     int ntiles = 0;
     int tile_grid = 1;                 // workgroups of the persistent tiled density pass
+    int tile_lanes = 1;                // lanes per atom in the tiled passes (2: few tiles)
     bool tiled = false, tile_feasible = false;
     int hmax = 0;                      // LDS records per tile
     size_t tile_lds = 0;               // dynamic LDS bytes of a tiled-pass workgroup

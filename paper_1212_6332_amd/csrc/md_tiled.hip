@@ -408,11 +408,12 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
 // ---------------------------------------------------------------- passes
 
 // Visit the row of slot i (record byte offsets) four entries at a time, one
-// 16-byte load per group.  While group q is evaluated, group q + 1 is already in
-// flight; the two registers alternate roles (the loop body is unrolled by
-// two) so that no register copy at the back edge waits for a load.
-template <bool IMG, bool TYPED, class Body>
-__device__ __forceinline__ void for_row(const int *__restrict__ idx, int i, int N, int n1,
+// 16-byte load per group: groups q0, q0 + S, ... (S lanes share a row).  While
+// one group is evaluated, the next is already in flight; the two registers
+// alternate roles (the loop body is unrolled by two) so that no register copy
+// at the back edge waits for a load.
+template <bool IMG, bool TYPED, int S, class Body>
+__device__ __forceinline__ void for_row(const int *__restrict__ idx, int i, int N, int n1, int q0,
                                         const double *rec, double xi, double yi, double zi,
                                         double L, double invL, Body &&body)
 {
@@ -447,14 +448,30 @@ __device__ __forceinline__ void for_row(const int *__restrict__ idx, int i, int 
     // row's last group, already in cache): with a fixed number of loads per
     // iteration the wait before a group can leave the later load in flight.
     auto load = [&](int q) { return g[(size_t)min(q, ng - 1) * N]; };
-    int4 a = load(0);
-    int4 b = load(1);
-    for (int q = 0; q < ng; q += 2) {
+    const int qa = S == 1 ? 0 : q0;  // one lane per row: the loop counter stays uniform
+    int4 a = load(qa);
+    int4 b = load(qa + S);
+    for (int q = qa; q < ng; q += 2 * S) {
         group(a, n1 - 4 * q);
-        a = load(q + 2);
-        group(b, n1 - 4 * (q + 1));
-        b = load(q + 3);
+        a = load(q + 2 * S);
+        group(b, n1 - 4 * (q + S));
+        b = load(q + 3 * S);
     }
+}
+
+// Sum over the P lanes (1 or 2, adjacent) that share the row of one atom: a
+// DPP quad permutation swaps the values of lanes 2k and 2k + 1, so both end
+// with the same sum.
+template <int P>
+__device__ __forceinline__ double lanes_sum(double v)
+{
+    if constexpr (P == 2) {
+        constexpr int swap_pairs = 0xB1;  // quad_perm [1, 0, 3, 2]
+        int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), swap_pairs, 0xf, 0xf, false);
+        int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), swap_pairs, 0xf, 0xf, false);
+        v += __hiloint2double(hi, lo);
+    }
+    return v;
 }
 
 // Tile m of persistent workgroup b (of P), or -1.  Workgroups are dispatched
@@ -542,7 +559,10 @@ __device__ __forceinline__ void run_tiles(int G, const State &st, const Boxes &b
     }
 }
 
-template <int KIND>
+// P lanes per atom (1, or 2 for systems of few tiles): lane `part` takes
+// the row groups part, part + P, ...; the sums are combined before the
+// epilogue, which the first lane alone performs.
+template <int KIND, int P>
 __global__ __launch_bounds__(kT) void k_tile_density(int N, int G, State st, Boxes bx, Build bd,
                                                      NList nl, Pot pot_arg, int hmax,
                                                      unsigned *flags)
@@ -550,9 +570,10 @@ __global__ __launch_bounds__(kT) void k_tile_density(int N, int G, State st, Box
     extern __shared__ __attribute__((aligned(256))) double rec[];
     const Pot pot = pinned(pot_arg);
     unsigned bad = 0;
+    const int part = P == 1 ? 0 : (int)threadIdx.x % P;
     run_tiles<false>(G, st, bx, bd, nl, rec, hmax, [&](const Tile &t) {
         const bool shifted = t.mode == kTileA;
-        for (int i = t.s0 + threadIdx.x; i < t.s1; i += kT) {
+        for (int i = t.s0 + (int)threadIdx.x / P; i < t.s1; i += kT / P) {
             double xi = st.x[i], yi = st.y[i], zi = st.z[i];
             int n1 = nl.count[i] & 0xffff;
             double rho = 0.0;
@@ -568,9 +589,11 @@ __global__ __launch_bounds__(kT) void k_tile_density(int N, int G, State st, Box
             };
             constexpr bool TY = KIND == kTyped;
             if (shifted)
-                for_row<false, TY>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
+                for_row<false, TY, P>(nl.idx, i, N, n1, part, rec, xi, yi, zi, t.L, t.invL, body);
             else
-                for_row<true, TY>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
+                for_row<true, TY, P>(nl.idx, i, N, n1, part, rec, xi, yi, zi, t.L, t.invL, body);
+            rho = lanes_sum<P>(rho);
+            if (P > 1 && part != 0) continue;
             double F, Fp;
             if constexpr (KIND == kTyped)
                 embed_typed(pot, rho, ai, F, Fp, bad);
@@ -587,7 +610,7 @@ __global__ __launch_bounds__(kT) void k_tile_density(int N, int G, State st, Box
 // MODE 0: forces only; 1: forces and the half kick v += kick f; 2: also the
 // next step's half kick and drift, x' = x + dt (v + kick f) into the other
 // position buffer, with the rebuild test of the kick-drift kernel.
-template <int KIND, bool ENERGY, int MODE>
+template <int KIND, bool ENERGY, int MODE, int P>
 __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes bx, Build bd,
                                                    NList nl, Pot pot_arg, int hmax, double kick,
                                                    double dt, Thermo th, unsigned *flags)
@@ -607,7 +630,8 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
         const bool shifted = t.mode == kTileA;
         stage_list<true>(g, t, st, nl, rec, hmax, shifted);
         const double thr2 = bx.thr2[t.b];
-        for (int i = t.s0 + threadIdx.x; i < t.s1; i += kT) {
+        const int part = P == 1 ? 0 : (int)threadIdx.x % P;
+        for (int i = t.s0 + (int)threadIdx.x / P; i < t.s1; i += kT / P) {
             double xi = st.x[i], yi = st.y[i], zi = st.z[i];
             double fpi = st.Fp[i];
             int n1 = nl.count[i] & 0xffff;
@@ -657,9 +681,17 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
             };
             constexpr bool TY = KIND == kTyped;
             if (shifted)
-                for_row<false, TY>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
+                for_row<false, TY, P>(nl.idx, i, N, n1, part, rec, xi, yi, zi, t.L, t.invL, body);
             else
-                for_row<true, TY>(nl.idx, i, N, n1, rec, xi, yi, zi, t.L, t.invL, body);
+                for_row<true, TY, P>(nl.idx, i, N, n1, part, rec, xi, yi, zi, t.L, t.invL, body);
+            ax = lanes_sum<P>(ax);
+            ay = lanes_sum<P>(ay);
+            az = lanes_sum<P>(az);
+            if constexpr (ENERGY) {
+                ep = lanes_sum<P>(ep);
+                wv = lanes_sum<P>(wv);
+            }
+            if (P > 1 && part != 0) continue;
             ax *= sg;
             ay *= sg;
             az *= sg;
@@ -736,14 +768,14 @@ __global__ __launch_bounds__(kT) void k_tile_get_neighbors(int N, State st, Boxe
     }
 }
 
-template <int KIND>
+template <int KIND, int P>
 void force_launch(Ctx &c, bool energy, int mode, double k, hipStream_t s)
 {
     const int N = (int)c.N, G = c.ntiles;
     size_t lds = c.tile_lds;
     double dt = c.dt;
 #define MDK_FORCE(E, M) \
-    k_tile_force<KIND, E, M><<<G, kT, lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, k, dt, c.thermo, c.dev.flags)
+    k_tile_force<KIND, E, M, P><<<G, kT, lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, k, dt, c.thermo, c.dev.flags)
     if (energy && mode > 0)
         MDK_FORCE(true, 1);
     else if (energy)
@@ -767,12 +799,32 @@ void allow(F *f, size_t lds)
 
 static constexpr double kKappaT = 1.602176634e-19 / 1.66053906660e-27 * 1e-10;
 
+template <int KIND, int P>
+static void allow_kind(size_t lds)
+{
+    allow(k_tile_density<KIND, P>, lds);
+    allow(k_tile_force<KIND, true, 1, P>, lds);
+    allow(k_tile_force<KIND, true, 0, P>, lds);
+    allow(k_tile_force<KIND, false, 1, P>, lds);
+    allow(k_tile_force<KIND, false, 0, P>, lds);
+    allow(k_tile_force<KIND, false, 2, P>, lds);
+}
+
+template <int P>
+static void allow_passes(size_t lds)
+{
+    allow_kind<MD_POT_FS, P>(lds);
+    allow_kind<MD_POT_SMTB, P>(lds);
+    allow_kind<MD_POT_SPLINE, P>(lds);
+    allow_kind<kTyped, P>(lds);
+}
+
 void tiled_prepare(Ctx &c)
 {
     size_t lds = c.tile_lds;
     // persistent grid of the density pass: as many workgroups as can be resident
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_density<MD_POT_SMTB>, kT,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_density<MD_POT_SMTB, 1>, kT,
                                                      lds) != hipSuccess || per_cu < 1)
         per_cu = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device) != hipSuccess ||
@@ -780,30 +832,8 @@ void tiled_prepare(Ctx &c)
         cus = 1;
     c.tile_grid = std::max(1, std::min(c.ntiles, per_cu * cus));
     allow(k_tile_nlist, lds);
-    allow(k_tile_density<MD_POT_FS>, lds);
-    allow(k_tile_density<MD_POT_SMTB>, lds);
-    allow(k_tile_density<MD_POT_SPLINE>, lds);
-    allow(k_tile_force<MD_POT_FS, true, 1>, lds);
-    allow(k_tile_force<MD_POT_FS, true, 0>, lds);
-    allow(k_tile_force<MD_POT_FS, false, 1>, lds);
-    allow(k_tile_force<MD_POT_FS, false, 0>, lds);
-    allow(k_tile_force<MD_POT_FS, false, 2>, lds);
-    allow(k_tile_force<MD_POT_SMTB, true, 1>, lds);
-    allow(k_tile_force<MD_POT_SMTB, true, 0>, lds);
-    allow(k_tile_force<MD_POT_SMTB, false, 1>, lds);
-    allow(k_tile_force<MD_POT_SMTB, false, 0>, lds);
-    allow(k_tile_force<MD_POT_SMTB, false, 2>, lds);
-    allow(k_tile_force<MD_POT_SPLINE, true, 1>, lds);
-    allow(k_tile_force<MD_POT_SPLINE, true, 0>, lds);
-    allow(k_tile_force<MD_POT_SPLINE, false, 1>, lds);
-    allow(k_tile_force<MD_POT_SPLINE, false, 0>, lds);
-    allow(k_tile_force<MD_POT_SPLINE, false, 2>, lds);
-    allow(k_tile_density<kTyped>, lds);
-    allow(k_tile_force<kTyped, true, 1>, lds);
-    allow(k_tile_force<kTyped, true, 0>, lds);
-    allow(k_tile_force<kTyped, false, 1>, lds);
-    allow(k_tile_force<kTyped, false, 0>, lds);
-    allow(k_tile_force<kTyped, false, 2>, lds);
+    allow_passes<1>(lds);
+    allow_passes<2>(lds);
 }
 
 void launch_tile_nlist(Ctx &c, const unsigned *gate, hipStream_t s)
@@ -812,26 +842,40 @@ void launch_tile_nlist(Ctx &c, const unsigned *gate, hipStream_t s)
                                                   c.dev.flags);
 }
 
-void launch_tile_density(Ctx &c, hipStream_t s)
+template <int L>
+static void tile_density_lanes(Ctx &c, hipStream_t s)
 {
     const int N = (int)c.N, P = c.tile_grid, G = c.ntiles;
     switch (c.pot.kind) {
-    case MD_POT_FS: k_tile_density<MD_POT_FS><<<P, kT, c.tile_lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
-    case MD_POT_SMTB: k_tile_density<MD_POT_SMTB><<<P, kT, c.tile_lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
-    case kTyped: k_tile_density<kTyped><<<P, kT, c.tile_lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
-    default: k_tile_density<MD_POT_SPLINE><<<P, kT, c.tile_lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
+    case MD_POT_FS: k_tile_density<MD_POT_FS, L><<<P, kT, c.tile_lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
+    case MD_POT_SMTB: k_tile_density<MD_POT_SMTB, L><<<P, kT, c.tile_lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
+    case kTyped: k_tile_density<kTyped, L><<<P, kT, c.tile_lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
+    default: k_tile_density<MD_POT_SPLINE, L><<<P, kT, c.tile_lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
+    }
+}
+
+void launch_tile_density(Ctx &c, hipStream_t s)
+{
+    if (c.tile_lanes == 2) tile_density_lanes<2>(c, s);
+    else tile_density_lanes<1>(c, s);
+}
+
+template <int L>
+static void tile_force_lanes(Ctx &c, bool energy, int mode, hipStream_t s)
+{
+    double k = 0.5 * c.dt * kKappaT / c.mass;
+    switch (c.pot.kind) {
+    case MD_POT_FS: force_launch<MD_POT_FS, L>(c, energy, mode, k, s); break;
+    case MD_POT_SMTB: force_launch<MD_POT_SMTB, L>(c, energy, mode, k, s); break;
+    case kTyped: force_launch<kTyped, L>(c, energy, mode, k, s); break;
+    default: force_launch<MD_POT_SPLINE, L>(c, energy, mode, k, s); break;
     }
 }
 
 void launch_tile_force(Ctx &c, bool energy, int mode, hipStream_t s)
 {
-    double k = 0.5 * c.dt * kKappaT / c.mass;
-    switch (c.pot.kind) {
-    case MD_POT_FS: force_launch<MD_POT_FS>(c, energy, mode, k, s); break;
-    case MD_POT_SMTB: force_launch<MD_POT_SMTB>(c, energy, mode, k, s); break;
-    case kTyped: force_launch<kTyped>(c, energy, mode, k, s); break;
-    default: force_launch<MD_POT_SPLINE>(c, energy, mode, k, s); break;
-    }
+    if (c.tile_lanes == 2) tile_force_lanes<2>(c, energy, mode, s);
+    else tile_force_lanes<1>(c, energy, mode, s);
 }
 
 void launch_tile_get_neighbors(Ctx &c, int32_t *counts, int32_t *ids, int32_t cols, hipStream_t s)

@@ -123,14 +123,22 @@ def test_perfect_lattice_zero_force():
         assert np.all(g["counts"] == g["counts"][0])
 
 
+SAMPLED = {"bcc128k": W.bcc128k, "fcc4m": W.fcc4m,
+           "bcc524k": lambda: W.bcc128k(ncell=64)}
+
+
 @pytest.mark.parametrize("name,nsample,tiled", [("bcc128k", 96, None), ("fcc4m", 48, None),
+                                                ("bcc524k", 48, None),
                                                 ("bcc128k", 48, 0), ("fcc4m", 24, 0)])
 def test_full_size_sampled(name, nsample, tiled):
     """Full-size workloads in the configuration the benchmark times, checked on
-    sampled atoms the oracle evaluates one by one; also through the per-atom
-    kernels, which at these sizes give each atom one lane (one-wavefront
-    workgroups at 128,000 atoms, 256-thread workgroups at 4,000,000)."""
-    wl = W.WORKLOADS[name]()
+    sampled atoms the oracle evaluates one by one: the 128,000-atom box runs
+    half-size tiles with two lanes per atom, the 524,288-atom spline box (512
+    tiles) and the 4,000,000-atom box full tiles with one lane; also through
+    the per-atom kernels, which at these sizes give each atom one lane
+    (one-wavefront workgroups at 128,000 atoms, 256-thread workgroups at
+    4,000,000)."""
+    wl = SAMPLED[name]()
     L = wl.box_len[0, 0]
     S = md.System.from_workload(wl)
     if tiled is not None:
