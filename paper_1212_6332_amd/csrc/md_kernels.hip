@@ -240,13 +240,6 @@ __global__ void k_fill_u32(unsigned *p, int n, unsigned v)
 
 // ---------------------------------------------------------------- list build
 
-__global__ void k_clear_cells(const unsigned *gate, int C, int *cell_count)
-{
-    if (skip(gate)) return;
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < C) cell_count[c] = 0;
-}
-
 // Binning: wrap into the box, find the cell (numbered tile by tile),
 // count atoms per cell.  Consecutive slots mostly share a cell (the state is
 // sorted from the previous build), so each run of equal cells in a
@@ -295,8 +288,8 @@ __global__ __launch_bounds__(kBlock) void k_bin(const unsigned *gate, int N, Sta
     if (valid) bd.slot[i] = base + (lane - leader);
 }
 
-// Exclusive scan of the per-cell counts in three passes: per-block scans
-// of kScanCells cells, a scan of the block totals, and the block offsets.
+// Exclusive scan of the per-cell counts in two passes: per-block scans of
+// kScanCells cells, then the offsets of the earlier blocks added.
 constexpr int kScanCells = 4096;  // cells per scan block (1024 threads x 4)
 
 // Exclusive scan of one value per thread over a 1024-thread block; returns
@@ -325,8 +318,10 @@ __device__ __forceinline__ int block_scan_1024(int v, int *total)
     return wsum[w] + incl - v;
 }
 
+// The counts are cleared once read, so that the next build starts from zero
+// (they are zero at creation) without a clearing pass of its own.
 __global__ __launch_bounds__(1024) void k_scan_local(const unsigned *gate, int C,
-                                                     const int *__restrict__ cnt,
+                                                     int *__restrict__ cnt,
                                                      int *__restrict__ start, int *__restrict__ bsum)
 {
     if (skip(gate)) return;
@@ -335,6 +330,7 @@ __global__ __launch_bounds__(1024) void k_scan_local(const unsigned *gate, int C
     int v[4], s = 0;
     for (int k = 0; k < 4; ++k) {
         v[k] = (c0 + k < C) ? cnt[c0 + k] : 0;
+        if (c0 + k < C) cnt[c0 + k] = 0;
         s += v[k];
     }
     int run = block_scan_1024(s, &tot);
@@ -345,31 +341,36 @@ __global__ __launch_bounds__(1024) void k_scan_local(const unsigned *gate, int C
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_top(const unsigned *gate, int nb, int *bsum)
-{
-    if (skip(gate)) return;
-    __shared__ int tot;
-    int per = (nb + 1023) / 1024;
-    int lo = threadIdx.x * per, hi = min(nb, lo + per);
-    int s = 0;
-    for (int k = lo; k < hi; ++k) s += bsum[k];
-    int run = block_scan_1024(s, &tot);
-    for (int k = lo; k < hi; ++k) {
-        int t = bsum[k];
-        bsum[k] = run;
-        run += t;
-    }
-    if (threadIdx.x == 0) bsum[nb] = tot;
-}
-
+// Each workgroup adds the totals of the scan blocks before its own cells
+// (a kBlock-cell workgroup lies inside one scan block), summed by its first
+// wavefront; the last workgroup also writes the grand total at start[C].
 __global__ __launch_bounds__(kBlock) void k_scan_add(const unsigned *gate, int C, int nb,
                                                      int *__restrict__ start,
                                                      const int *__restrict__ bsum)
 {
     if (skip(gate)) return;
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < C) start[c] += bsum[c / kScanCells];
-    if (c == 0) start[C] = bsum[nb];
+    __shared__ int off;
+    const int c0 = blockIdx.x * blockDim.x, c = c0 + threadIdx.x;
+    if (threadIdx.x < 64) {
+        const int j = c0 / kScanCells;
+        const bool last = blockIdx.x == gridDim.x - 1;
+        int before = 0, all = 0;
+        for (int k = threadIdx.x; k < nb; k += 64) {
+            int v = bsum[k];
+            if (k < j) before += v;
+            all += v;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            before += __shfl_xor(before, o);
+            all += __shfl_xor(all, o);
+        }
+        if (threadIdx.x == 0) {
+            off = before;
+            if (last) start[C] = all;
+        }
+    }
+    __syncthreads();
+    if (c < C) start[c] += off;
 }
 
 // Counting sort, first half: place every atom in its cell's segment (order inside a
@@ -1040,11 +1041,10 @@ void launch_build(Ctx &c, bool gated, hipStream_t s)
     const unsigned *gate = gated ? c.dev.flags : nullptr;
     int N = (int)c.N;
     int C = c.bd.n_cells;
-    k_clear_cells<<<grid_for(C), kBlock, 0, s>>>(gate, C, c.bd.cell_count);
+    // the per-cell counts are zero here: set at creation, cleared by every scan
     k_bin<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.st, c.bx, c.bd, c.dev.flags);
     int nb = (C + kScanCells - 1) / kScanCells;
     k_scan_local<<<nb, 1024, 0, s>>>(gate, C, c.bd.cell_count, c.bd.cell_start, c.bd.bsum);
-    k_scan_top<<<1, 1024, 0, s>>>(gate, nb, c.bd.bsum);
     k_scan_add<<<grid_for(C), kBlock, 0, s>>>(gate, C, nb, c.bd.cell_start, c.bd.bsum);
     k_scatter<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.bd);
     k_rank<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.st, c.bd);
