@@ -19,6 +19,7 @@
 // 27-cell stencil of Fig. 3.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "md_device.h"
@@ -248,7 +249,11 @@ __global__ __launch_bounds__(kBlock) void k_bin(const unsigned *gate, int N, Sta
                                                 Build bd, unsigned *flags)
 {
     if (skip(gate)) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    // grid-stride over blocks of atoms (a capped grid keeps the launch cheap
+    // in steps that skip the build); whole blocks iterate together, so the
+    // wavefront ballots below always see consecutive atoms
+    for (int b0 = blockIdx.x * blockDim.x; b0 < N; b0 += gridDim.x * blockDim.x) {
+    int i = b0 + threadIdx.x;
     bool valid = i < N;
     int cell = -1;
     if (valid) {
@@ -286,6 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_bin(const unsigned *gate, int N, Sta
     if (head) base = atomicAdd(&bd.cell_count[cell], end - lane);
     base = __shfl(base, leader);
     if (valid) bd.slot[i] = base + (lane - leader);
+    }
 }
 
 // Exclusive scan of the per-cell counts in two passes: per-block scans of
@@ -378,9 +384,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_add(const unsigned *gate, int C
 __global__ void k_scatter(const unsigned *gate, int N, Build bd)
 {
     if (skip(gate)) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    bd.tmp[bd.cell_start[bd.cell_of[i]] + bd.slot[i]] = i;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x)
+        bd.tmp[bd.cell_start[bd.cell_of[i]] + bd.slot[i]] = i;
 }
 
 // Counting sort, second half: order each cell by original index.  The rank of an atom
@@ -388,52 +393,52 @@ __global__ void k_scatter(const unsigned *gate, int N, Build bd)
 __global__ void k_rank(const unsigned *gate, int N, State st, Build bd)
 {
     if (skip(gate)) return;
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= N) return;
-    int p = bd.tmp[q];
-    int c = bd.cell_of[p];
-    int s = bd.cell_start[c], e = bd.cell_start[c + 1];
-    int mine = st.id[p];
-    int rank = 0;
-    for (int k = s; k < e; ++k) rank += st.id[bd.tmp[k]] < mine;
-    bd.perm[s + rank] = p;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < N; q += gridDim.x * blockDim.x) {
+        int p = bd.tmp[q];
+        int c = bd.cell_of[p];
+        int s = bd.cell_start[c], e = bd.cell_start[c + 1];
+        int mine = st.id[p];
+        int rank = 0;
+        for (int k = s; k < e; ++k) rank += st.id[bd.tmp[k]] < mine;
+        bd.perm[s + rank] = p;
+    }
 }
 
 __global__ void k_gather(const unsigned *gate, int N, State st, Build bd)
 {
     if (skip(gate)) return;
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= N) return;
-    int p = bd.perm[q];
-    bd.sx[q] = st.x[p];
-    bd.sy[q] = st.y[p];
-    bd.sz[q] = st.z[p];
-    bd.svx[q] = st.vx[p];
-    bd.svy[q] = st.vy[p];
-    bd.svz[q] = st.vz[p];
-    bd.sid[q] = st.id[p];
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < N; q += gridDim.x * blockDim.x) {
+        int p = bd.perm[q];
+        bd.sx[q] = st.x[p];
+        bd.sy[q] = st.y[p];
+        bd.sz[q] = st.z[p];
+        bd.svx[q] = st.vx[p];
+        bd.svy[q] = st.vy[p];
+        bd.svz[q] = st.vz[p];
+        bd.sid[q] = st.id[p];
+    }
 }
 
 __global__ void k_commit(const unsigned *gate, int N, State st, Build bd)
 {
     if (skip(gate)) return;
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= N) return;
-    double x = bd.sx[q], y = bd.sy[q], z = bd.sz[q];
-    st.x[q] = x;
-    st.y[q] = y;
-    st.z[q] = z;
-    reinterpret_cast<double2 *>(st.pk)[2 * (size_t)q] = make_double2(x, y);
-    st.pk[4 * (size_t)q + 2] = z;
-    st.xr[q] = x;
-    st.yr[q] = y;
-    st.zr[q] = z;
-    st.vx[q] = bd.svx[q];
-    st.vy[q] = bd.svy[q];
-    st.vz[q] = bd.svz[q];
-    st.id[q] = bd.sid[q];
-    if (st.type) st.type[q] = st.type0[bd.sid[q]];
-    if (st.frozen) st.frozen[q] = st.frozen0[bd.sid[q]];
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < N; q += gridDim.x * blockDim.x) {
+        double x = bd.sx[q], y = bd.sy[q], z = bd.sz[q];
+        st.x[q] = x;
+        st.y[q] = y;
+        st.z[q] = z;
+        reinterpret_cast<double2 *>(st.pk)[2 * (size_t)q] = make_double2(x, y);
+        st.pk[4 * (size_t)q + 2] = z;
+        st.xr[q] = x;
+        st.yr[q] = y;
+        st.zr[q] = z;
+        st.vx[q] = bd.svx[q];
+        st.vy[q] = bd.svy[q];
+        st.vz[q] = bd.svz[q];
+        st.id[q] = bd.sid[q];
+        if (st.type) st.type[q] = st.type0[bd.sid[q]];
+        if (st.frozen) st.frozen[q] = st.frozen0[bd.sid[q]];
+    }
 }
 
 // Full list of slot i.  r^2 = (dx*dx + dy*dy) + dz*dz with separate
@@ -960,6 +965,8 @@ __global__ void k_pair_tables(int n, int T, const double *__restrict__ V,
 
 inline int grid_for(int64_t n, int block = kBlock) { return (int)((n + block - 1) / block); }
 
+constexpr int kGatedBlocks = 2048;  // grid cap of the sort's atom loops (8 per CU)
+
 template <int KIND, bool MULTI>
 void density_t(Ctx &c, hipStream_t s)
 {
@@ -1042,14 +1049,17 @@ void launch_build(Ctx &c, bool gated, hipStream_t s)
     int N = (int)c.N;
     int C = c.bd.n_cells;
     // the per-cell counts are zero here: set at creation, cleared by every scan
-    k_bin<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.st, c.bx, c.bd, c.dev.flags);
+    // the atom loops of the sort are grid-stride over a capped grid: in the
+    // replayed steps that skip the build, launching them costs less
+    const int gN = std::min(grid_for(N), kGatedBlocks);
+    k_bin<<<gN, kBlock, 0, s>>>(gate, N, c.st, c.bx, c.bd, c.dev.flags);
     int nb = (C + kScanCells - 1) / kScanCells;
     k_scan_local<<<nb, 1024, 0, s>>>(gate, C, c.bd.cell_count, c.bd.cell_start, c.bd.bsum);
     k_scan_add<<<grid_for(C), kBlock, 0, s>>>(gate, C, nb, c.bd.cell_start, c.bd.bsum);
-    k_scatter<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.bd);
-    k_rank<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.st, c.bd);
-    k_gather<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.st, c.bd);
-    k_commit<<<grid_for(N), kBlock, 0, s>>>(gate, N, c.st, c.bd);
+    k_scatter<<<gN, kBlock, 0, s>>>(gate, N, c.bd);
+    k_rank<<<gN, kBlock, 0, s>>>(gate, N, c.st, c.bd);
+    k_gather<<<gN, kBlock, 0, s>>>(gate, N, c.st, c.bd);
+    k_commit<<<gN, kBlock, 0, s>>>(gate, N, c.st, c.bd);
     if (c.tiled)
         launch_tile_nlist(c, gate, s);
     else
