@@ -24,7 +24,7 @@ class SplineEAMFunction(torch.autograd.Function):
         theta = torch.cat([theta_phi.reshape(-1), theta_f.reshape(-1),
                            theta_F.reshape(-1)]).to(torch.float64).contiguous()
         system.set_theta(theta)
-        f, _, eb = system.forces(energy=True)
+        f, _, eb = system.forces(energy=True, atom_energy=False)
         ctx.system = system
         ctx.K = theta_phi.numel()
         ctx.save_for_backward(theta)

@@ -313,9 +313,11 @@ class System:
         _check(lib().md_embed(self._h, _ptr(F), _ptr(Fp), _stream()), "md_embed")
         return F, Fp
 
-    def forces(self, energy=True):
+    def forces(self, energy=True, atom_energy=True):
+        """Forces [N, 3]; with `energy` also per-atom energies (None unless
+        `atom_energy`) and per-box energies."""
         f = self._f64(self.n_atoms, 3)
-        e = self._f64(self.n_atoms) if energy else None
+        e = self._f64(self.n_atoms) if energy and atom_energy else None
         eb = self._f64(self.n_boxes) if energy else None
         _check(lib().md_forces(self._h, _ptr(f), _ptr(e), _ptr(eb), _stream()), "md_forces")
         return (f, e, eb) if energy else f
