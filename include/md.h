@@ -193,13 +193,19 @@ int md_embed(md_ctx *ctx, double *F_out, double *Fp_out, void *stream);
 
 /* Force pass (Fig. 6, eq. 3) after md_density: forces f_out[N][3], per-atom
  * energies e_atom[N] = F(rho_i) + 1/2 sum_j V(r_ij), and per-box energies
- * e_box[B] (deterministic sums).  Any output may be NULL. */
+ * e_box[B] (deterministic sums).  Any output may be NULL.  When no energy is
+ * asked for and the forces of the current state are already computed (after
+ * md_step, including md_step(ctx, 0, ...)), no pass runs: f_out receives the
+ * forces as the kernel that computed them left them (for several boxes
+ * stepped by the persistent multi-box stepper, that stepper's own force
+ * evaluation). */
 int md_forces(md_ctx *ctx, double *f_out, double *e_atom, double *e_box, void *stream);
 
 /* nsteps of velocity Verlet: half kick, drift, conditional list rebuild
  * decided on the device, density + embedding, force, half kick.  Brings the
- * list and forces up to date first if needed.  The step sequence is captured
- * once in a HIP graph and replayed. */
+ * list and forces up to date first if needed (nsteps = 0 does only that,
+ * with the kernels that would take the steps).  The step sequence is
+ * captured once in a HIP graph and replayed. */
 int md_step(md_ctx *ctx, int nsteps, void *stream);
 
 /* Kinetic energy per box, ke_box[B] = sum m v^2 / 2 (eV). */

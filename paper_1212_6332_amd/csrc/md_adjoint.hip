@@ -28,10 +28,7 @@ namespace mdk {
 
 namespace {
 
-__device__ __forceinline__ double min_image(double d, double L, double invL)
-{
-    return fma(-L, rint(d * invL), d);
-}
+using dev::min_image;
 
 // Interval m and local t of x on a table grid (same grid as the B-spline).
 __device__ __forceinline__ void locate(const Table &t, double x, int &m, double &tt)
@@ -108,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_s(int N, State st, Boxes bx, NLi
         double dx = min_image(st.x[j] - xi, L, invL);
         double dy = min_image(st.y[j] - yi, L, invL);
         double dz = min_image(st.z[j] - zi, L, invL);
-        double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        double r2 = dev::dist2(dx, dy, dz);
         if (r2 >= pot.rc2) continue;
         double r = sqrt(r2);
         double f, df, ddf;
@@ -185,7 +182,7 @@ __global__ __launch_bounds__(64) void k_adj_theta(int N, int K, State st, Boxes 
             double dx = min_image(st.x[j] - xi, L, invL);
             double dy = min_image(st.y[j] - yi, L, invL);
             double dz = min_image(st.z[j] - zi, L, invL);
-            double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            double r2 = dev::dist2(dx, dy, dz);
             if (r2 < pot.rc2) {
                 live = true;
                 double r = sqrt(r2);

@@ -796,6 +796,9 @@ int md_set_state(md_ctx *h, const double *pos, const double *vel, void *stream)
     c.state_set = true;
     c.list_valid = c.density_valid = c.forces_valid = false;
     c.baro_mu_valid = false;
+    // the persistent stepper's per-box lists and reference positions
+    // describe the previous state
+    batched_invalidate(c);
     return MD_OK;
 }
 
@@ -852,8 +855,13 @@ int md_forces(md_ctx *h, double *f_out, double *e_atom, double *e_box, void *str
     Ctx &c = h->c;
     if (!c.state_set) return MD_ERR_STATE;
     hipStream_t s = as_stream(stream);
-    ensure_density(c, s);
     bool energy = e_atom || e_box;
+    if (!energy && c.forces_valid) {
+        // forces of the current state, as the last force evaluation left them
+        if (f_out) launch_scatter_vec3(c, c.st.fx, c.st.fy, c.st.fz, f_out, s);
+        return MD_OK;
+    }
+    ensure_density(c, s);
     launch_force(c, energy, 0, s);
     c.forces_valid = true;
     if (f_out) launch_scatter_vec3(c, c.st.fx, c.st.fy, c.st.fz, f_out, s);
@@ -867,10 +875,10 @@ int md_step(md_ctx *h, int nsteps, void *stream)
     if (!h || nsteps < 0) return MD_ERR_ARG;
     Ctx &c = h->c;
     if (!c.state_set) return MD_ERR_STATE;
-    if (nsteps == 0) return MD_OK;
     hipStream_t s = as_stream(stream);
     if (c.B > 1 && c.batched && !c.baro_on) {
-        launch_batched_steps(c, nsteps, s);
+        int rc = launch_batched_steps(c, nsteps, s);
+        if (rc != MD_OK) return rc;
         c.host_steps += nsteps;
         // forces in the state arrays match the new positions; the merged-box
         // list and densities do not
@@ -965,9 +973,9 @@ int md_autotune(md_ctx *h, void *stream, int32_t *block)
     for (int T : candidates) {
         if ((rc = restore()) != MD_OK) break;
         c.batch_block = T;
-        launch_batched_steps(c, 5, s);  // lists, forces, first steps
+        if ((rc = launch_batched_steps(c, 5, s)) != MD_OK) break;  // lists, forces, first steps
         if (hipEventRecord(e0, s) != hipSuccess) { rc = MD_ERR_DEVICE; break; }
-        launch_batched_steps(c, reps, s);
+        if ((rc = launch_batched_steps(c, reps, s)) != MD_OK) break;
         if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
             rc = MD_ERR_DEVICE;
             break;

@@ -69,123 +69,7 @@ struct Batch {
     int graph_block = 0;             // workgroup size it was captured with
 };
 
-__device__ __forceinline__ double min_image(double d, double L, double invL)
-{
-    return fma(-L, rint(d * invL), d);
-}
-
-__device__ __forceinline__ double wrap1(double x, double L)
-{
-    while (x < 0.0) x += L;
-    while (x >= L) x -= L;
-    return x;
-}
-
-__device__ __forceinline__ int cell_coord(double x, double ncL, int nc)
-{
-    int c = (int)(x * ncL);
-    return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
-}
-
-__device__ __forceinline__ void table_eval(const Table &t, double x, double &s, double &ds,
-                                           unsigned &bad)
-{
-    double u = (x - t.lo) * t.inv_h;
-    int m = (int)floor(u);
-    if (!(x >= t.lo && x <= t.hi)) bad |= MD_FLAG_TABLE_RANGE;
-    m = m < 0 ? 0 : (m > t.n - 1 ? t.n - 1 : m);
-    double tt = u - (double)m;
-    const double2 *p = reinterpret_cast<const double2 *>(t.c + 4 * m);
-    double2 ab = p[0], cd = p[1];
-    s = fma(tt, fma(tt, fma(tt, cd.y, cd.x), ab.y), ab.x);
-    ds = fma(tt, fma(tt, 3.0 * cd.y, 2.0 * cd.x), ab.y) * t.inv_h;
-}
-
-template <int KIND>
-__device__ __forceinline__ double dens(const Pot &p, double r, unsigned &bad)
-{
-    if constexpr (KIND == MD_POT_FS) {
-        double u = r - p.d;
-        return r < p.d ? u * u : 0.0;
-    } else if constexpr (KIND == MD_POT_SMTB) {
-        // the SMTB constants are stored in base 2: rho = 2^(af r + bf)
-        return exp2(fma(p.af, r, p.bf));
-    } else {
-        double s, ds;
-        table_eval(p.tab[1], r, s, ds, bad);
-        return s;
-    }
-}
-
-template <int KIND>
-__device__ __forceinline__ void pair_terms(const Pot &p, double r, double &dfr, double &v,
-                                           double &dv, unsigned &bad)
-{
-    if constexpr (KIND == MD_POT_FS) {
-        double u = r - p.d;
-        dfr = r < p.d ? 2.0 * u : 0.0;
-        double w = r - p.c;
-        double poly = fma(r, fma(r, p.c2, p.c1), p.c0);
-        double dpoly = fma(2.0 * p.c2, r, p.c1);
-        bool in = r < p.c;
-        v = in ? w * w * poly : 0.0;
-        dv = in ? w * fma(w, dpoly, 2.0 * poly) : 0.0;
-    } else if constexpr (KIND == MD_POT_SMTB) {
-        // base-2 exponents; afn, avn are the slopes of ln rho and ln V
-        double ef = exp2(fma(p.af, r, p.bf));
-        double ev = exp2(fma(p.av, r, p.bv));
-        dfr = p.afn * ef;
-        v = ev;
-        dv = p.avn * ev;
-    } else if (p.pair) {
-        // V and rho of one interval, 64 contiguous bytes (interleaved table)
-        const Table &t = p.tab[0];
-        double u = (r - t.lo) * t.inv_h;
-        int m = (int)floor(u);
-        if (!(r >= t.lo && r <= t.hi)) bad |= MD_FLAG_TABLE_RANGE;
-        m = m < 0 ? 0 : (m > t.n - 1 ? t.n - 1 : m);
-        double tt = u - (double)m;
-        const double2 *c = reinterpret_cast<const double2 *>(p.pair + 8 * (size_t)m);
-        double2 va = c[0], vb = c[1], fa = c[2], fb = c[3];
-        v = fma(tt, fma(tt, fma(tt, vb.y, vb.x), va.y), va.x);
-        dv = fma(tt, fma(tt, 3.0 * vb.y, 2.0 * vb.x), va.y) * t.inv_h;
-        dfr = fma(tt, fma(tt, 3.0 * fb.y, 2.0 * fb.x), fa.y) * t.inv_h;
-    } else {
-        double s;
-        table_eval(p.tab[1], r, s, dfr, bad);
-        table_eval(p.tab[0], r, v, dv, bad);
-    }
-}
-
-template <int KIND>
-__device__ __forceinline__ double embed_fp(const Pot &p, double rho, unsigned &bad)
-{
-    if constexpr (KIND == MD_POT_FS || KIND == MD_POT_SMTB) {
-        double A = (KIND == MD_POT_FS) ? p.A : 1.0;
-        return rho > 0.0 ? -0.5 * A / sqrt(rho) : 0.0;
-    } else {
-        double F, Fp;
-        table_eval(p.tab[2], rho, F, Fp, bad);
-        return Fp;
-    }
-}
-
-__device__ __forceinline__ int stencil_1d(int c, int nc, int out[3])
-{
-    if (nc == 1) {
-        out[0] = 0;
-        return 1;
-    }
-    if (nc == 2) {
-        out[0] = 0;
-        out[1] = 1;
-        return 2;
-    }
-    out[0] = c == 0 ? nc - 1 : c - 1;
-    out[1] = c;
-    out[2] = c == nc - 1 ? 0 : c + 1;
-    return 3;
-}
+using namespace dev;
 
 // Entry m of local atom i in a box of n atoms: group m / 4 of the atom,
 // groups of all atoms of the box contiguous (the capacity is a multiple of 4).
@@ -335,10 +219,12 @@ __global__ __launch_bounds__(T) void k_batched(BArgs a)
                     double dx = min_image(X[j] - xi, L, invL);
                     double dy = min_image(Y[j] - yi, L, invL);
                     double dz = min_image(Z[j] - zi, L, invL);
-                    double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                    if (r2 < pot.rc2) rho += dens<KIND>(pot, r2 * dev::rsqrt_nr(r2), bad);
+                    double r2 = dist2(dx, dy, dz);
+                    if (r2 < pot.rc2) rho += dens<KIND>(pot, r2 * rsqrt_nr(r2), bad);
                 });
-                FP[i] = embed_fp<KIND>(pot, rho, bad);
+                double F, Fp;
+                embed<KIND>(pot, rho, F, Fp, bad);
+                FP[i] = Fp;
             }
             __syncthreads();
         };
@@ -352,9 +238,9 @@ __global__ __launch_bounds__(T) void k_batched(BArgs a)
                     double dx = min_image(X[j] - xi, L, invL);
                     double dy = min_image(Y[j] - yi, L, invL);
                     double dz = min_image(Z[j] - zi, L, invL);
-                    double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                    double r2 = dist2(dx, dy, dz);
                     if (r2 < pot.rc2) {
-                        double inv_r = dev::rsqrt_nr(r2), dfr, v, dv;
+                        double inv_r = rsqrt_nr(r2), dfr, v, dv;
                         pair_terms<KIND>(pot, r2 * inv_r, dfr, v, dv, bad);
                         double coef = fma(fpi + FP[j], dfr, dv) * inv_r;
                         ax = fma(coef, dx, ax);
@@ -579,7 +465,7 @@ void batched_release(Ctx &c)
     c.batch = nullptr;
 }
 
-void launch_batched_steps(Ctx &c, int nsteps, hipStream_t s)
+int launch_batched_steps(Ctx &c, int nsteps, hipStream_t s)
 {
     Batch &b = *static_cast<Batch *>(c.batch);
     int T = c.batch_block;
@@ -637,14 +523,17 @@ void launch_batched_steps(Ctx &c, int nsteps, hipStream_t s)
             b.graph_block = b.graph ? T : 0;
         }
         if (b.graph)
-            for (; done + kMaxSteps <= nsteps; done += kMaxSteps) (void)hipGraphLaunch(b.graph, s);
+            for (; done + kMaxSteps <= nsteps; done += kMaxSteps)
+                if (hipGraphLaunch(b.graph, s) != hipSuccess) return MD_ERR_DEVICE;
     }
     while (done < nsteps) {
         int k = std::min(kMaxSteps, nsteps - done);
         launch(k, 0, s);
         done += k;
     }
+    if (hipGetLastError() != hipSuccess) return MD_ERR_DEVICE;
     b.list_valid = true;
+    return MD_OK;
 }
 
 }  // namespace mdk

@@ -20,6 +20,16 @@ __device__ __forceinline__ double min_image(double d, double L, double invL)
     return fma(-L, rint(d * invL), d);
 }
 
+// Squared distance of a pair as the cutoff tests take it: (dx dx + dy dy) +
+// dz dz with every product and sum rounded separately.  Every pass decides
+// r < rc (and the list build r < r_list) from this value, so the set of
+// interacting pairs does not depend on which kernel evaluates a pair.
+__device__ __forceinline__ double dist2(double dx, double dy, double dz)
+{
+#pragma clang fp contract(off)
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
 // 1/sqrt(a), a > 0: the hardware estimate y (relative error about 5e-8)
 // refined by one third-order step: with e = 1 - a y^2,
 // 1/sqrt(a) = y (1 - e)^(-1/2) = y (1 + e/2 + 3 e^2/8 + O(e^3)).

@@ -147,13 +147,15 @@ struct Build {
 };
 
 struct NList {
-    int *count;                        // [N]: plain pairs | (boundary pairs << 16)
+    // [N] per-atom rows: np | ni << 16, pairs without periodic correction at
+    // [0, np), pairs across a face at [mn - ni, mn); tiled rows: n | np << 16,
+    // the pairs across a face at [np, n)
+    int *count;
     int *total;                        // [N]: neighbours found (may exceed mn)
     int *idx;                          // [MN][N], column major (slot-fastest)
     int mn;
-    // tiled contexts: the halo records of tile g, in LDS order, as
-    // tsrc[g * hmax + k] = slot | image << 27 (image = (sx+1) + 3 (sy+1) + 9 (sz+1)),
-    // and their number ttotal[g]; written by each list build
+    // tiled contexts: the slots of the halo records of tile g, in LDS order,
+    // tsrc[g * hmax + k], and their number ttotal[g]; written by each list build
     unsigned *tsrc;
     int *ttotal;
 };
@@ -207,7 +209,7 @@ void launch_pack_positions(Ctx &c, hipStream_t s);
 
 // Form (2), md_batched.hip.
 int batched_prepare(Ctx &c);
-void launch_batched_steps(Ctx &c, int nsteps, hipStream_t s);
+int launch_batched_steps(Ctx &c, int nsteps, hipStream_t s);
 void batched_invalidate(Ctx &c);
 void batched_release(Ctx &c);
 // Form (3), md_adjoint.hip.

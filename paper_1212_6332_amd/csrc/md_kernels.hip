@@ -572,7 +572,7 @@ __global__ __launch_bounds__(kBlock) void k_density(int N, State st, Boxes bx, N
     double rho = 0.0;
     const int ai = KIND == kTyped ? st.type[i] : 0;
     auto body = [&](double dx, double dy, double dz, double, unsigned j) {
-        double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        double r2 = dev::dist2(dx, dy, dz);
         if (r2 < pot.rc2) {
             if constexpr (KIND == kTyped)
                 rho += dens_typed(pot, r2 * rsqrt_nr(r2), ai, st.type[j], bad);
@@ -637,7 +637,7 @@ __global__ __launch_bounds__(kBlock) void k_force(int N, State st, Boxes bx, NLi
     double ax = 0.0, ay = 0.0, az = 0.0, ep = 0.0, wv = 0.0;
     const int ai = KIND == kTyped ? st.type[i] : 0;
     auto body = [&](double dx, double dy, double dz, double fpj, unsigned j) {
-        double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        double r2 = dev::dist2(dx, dy, dz);
         if (r2 < pot.rc2) {
             double inv_r = rsqrt_nr(r2);
             double coef, v;

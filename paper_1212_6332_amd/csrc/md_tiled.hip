@@ -12,13 +12,17 @@
 //
 // Two halo modes, fixed per box:
 //  A  (boxes with at least max(t)+2 cells per axis): the halo is the tile
-//     grown by one cell, with cells that wrap around the box staged at the
-//     periodic image next to the tile.  The list build applies the image
-//     shift per halo cell as one exact addition, (x_j - x_i) + s, as the
-//     minimum image does; the passes stage pre-shifted coordinates and need
-//     no minimum image at all.
-//  B  (small boxes): one tile is the whole box, staged once without shifts;
-//     the list build and the passes take the minimum image per pair.
+//     grown by one cell; a halo cell past a face of the box is the cell on
+//     the far side of the box, whose pairs with the tile's atoms cross that
+//     face.
+//  B  (small boxes): one tile is the whole box, staged once.
+// Records hold the wrapped coordinates in both modes.  The list build puts
+// the pairs that need no periodic correction at the front of a row and the
+// pairs that cross a face at its back (as the per-atom rows do); the passes
+// take the minimum image for the back part only.  Every kernel therefore
+// forms x_j - x_i first and adds the periodic shift after it, and tests the
+// cutoff on the separately rounded square of that separation, so the set of
+// interacting pairs is the same whichever kernel evaluates a pair.
 // Rows hold the byte offsets of halo records in the LDS record array
 // (record index times 32), so the passes address a record with no
 // arithmetic; with several species the neighbour's species rides in the
@@ -160,22 +164,14 @@ __device__ __forceinline__ double shift_of(int code, int axis, double L)
     return (double)(((code >> (2 * axis)) & 3) - 1) * L;
 }
 
-// Stage the halo records: x, y, z (+ F') at 32 bytes per record.  With
-// `shifted`, coordinates are moved to the periodic image next to the tile.
-// Every thread copies records k = tid, tid + 1024, ...; its loads are all
-// issued before the first LDS store, so a tile pays about one memory round
-// trip for its whole halo.
-constexpr unsigned kSlotBits = 27;  // slots below 2^27 (the host caps N)
-constexpr unsigned kSlotMask = (1u << kSlotBits) - 1u;
-
-__device__ __forceinline__ unsigned image_code(int code)
-{
-    return (unsigned)((code & 3) + 3 * ((code >> 2) & 3) + 9 * ((code >> 4) & 3));
-}
-
+// Stage the halo records: x, y, z (+ F') at 32 bytes per record, at the
+// wrapped coordinates.  Every thread copies records k = tid, tid + 1024, ...;
+// its loads are all issued before the first LDS store, so a tile pays about
+// one memory round trip for its whole halo.  The slot of each record goes to
+// src_out, from which the passes stage the same records again.
 template <bool WITH_FP>
 __device__ __forceinline__ void stage(const Tile &t, const State &st, const HaloLds &H,
-                                      double *rec, int hmax, bool shifted, unsigned *flags,
+                                      double *rec, int hmax, unsigned *flags,
                                       unsigned *src_out = nullptr)
 {
     constexpr int R = 6;  // records per thread per round (hmax <= R * 1024 per round)
@@ -195,11 +191,10 @@ __device__ __forceinline__ void stage(const Tile &t, const State &st, const Halo
                     else hi = mid - 1;
                 }
                 int j = H.start[lo] + (k - H.off[lo]);
-                int code = H.shift[lo];
-                if (src_out) src_out[k] = (unsigned)j | image_code(code) << kSlotBits;
-                vx[u] = st.x[j] + (shifted ? shift_of(code, 0, t.L) : 0.0);
-                vy[u] = st.y[j] + (shifted ? shift_of(code, 1, t.L) : 0.0);
-                vz[u] = st.z[j] + (shifted ? shift_of(code, 2, t.L) : 0.0);
+                if (src_out) src_out[k] = (unsigned)j;
+                vx[u] = st.x[j];
+                vy[u] = st.y[j];
+                vz[u] = st.z[j];
                 if constexpr (WITH_FP) vf[u] = st.Fp[j];
                 else ty[u] = st.type ? st.type[j] : 0;
             }
@@ -221,11 +216,10 @@ __device__ __forceinline__ void stage(const Tile &t, const State &st, const Halo
 }
 
 // Stage the halo records of tile g from its source list (written by the list
-// build): one coalesced load of the list, then the gathers.  With `shifted`,
-// coordinates are moved to the periodic image the list records.
+// build): one coalesced load of the list, then the gathers.
 template <bool WITH_FP>
-__device__ __forceinline__ void stage_list(int g, const Tile &t, const State &st, const NList &nl,
-                                           double *rec, int hmax, bool shifted)
+__device__ __forceinline__ void stage_list(int g, const State &st, const NList &nl, double *rec,
+                                           int hmax)
 {
     constexpr int R = 6;  // records per thread per round (hmax <= R * 1024 per round)
     const int total = min(nl.ttotal[g], hmax);
@@ -238,19 +232,11 @@ __device__ __forceinline__ void stage_list(int g, const Tile &t, const State &st
             int k = base + u * kT + (int)threadIdx.x;
             kk[u] = k;
             if (k < total) {
-                unsigned e = src[k];
-                int j = (int)(e & kSlotMask);
+                int j = (int)src[k];
                 vx[u] = st.x[j];
                 vy[u] = st.y[j];
                 vz[u] = st.z[j];
                 if constexpr (WITH_FP) vf[u] = st.Fp[j];
-                if (shifted) {
-                    int c = (int)(e >> kSlotBits), cz = c / 9, cy = (c - 9 * cz) / 3;
-                    int cx = c - 9 * cz - 3 * cy;
-                    vx[u] += (double)(cx - 1) * t.L;
-                    vy[u] += (double)(cy - 1) * t.L;
-                    vz[u] += (double)(cz - 1) * t.L;
-                }
             }
         }
 #pragma unroll
@@ -275,13 +261,32 @@ __device__ __forceinline__ int halo_index(const Tile &t, int ix, int iy, int iz)
 
 // ---------------------------------------------------------------- list build
 
+// Row layout: the pairs that need no periodic correction at entries [0, np),
+// then the pairs that cross a face of the box at [np, n); count = n | np << 16.
+// While the row is built the crossing pairs go to its back, [mn - nb, mn);
+// `close` moves them behind the others.
+struct RowFill {
+    int np = 0, nb = 0, total = 0;
+    __device__ __forceinline__ void put(int *__restrict__ idx, int i, int N, int mn, bool plain,
+                                        int e)
+    {
+        if (np + nb < mn) idx[nl_off(plain ? np++ : mn - 1 - nb++, i, N)] = e;
+    }
+    // entries move down (np <= mn - nb), so each is read before it is overwritten
+    __device__ __forceinline__ int close(int *__restrict__ idx, int i, int N, int mn)
+    {
+        for (int k = 0; k < nb; ++k) idx[nl_off(np + k, i, N)] = idx[nl_off(mn - nb + k, i, N)];
+        return (np + nb) | (np << 16);
+    }
+};
+
 // Candidates [k0, k1) of one stencil cell against atom i, 32 at a time: first
 // a hit mask with no branch per candidate, then one store per hit, in
-// ascending record order (the order of the rows the passes sum in).  The
-// record kself (the atom itself) is never listed.  SHIFT adds the cell's
-// periodic image shift to the difference, (x_j - x_i) + s, as the minimum
-// image convention rounds it.  An entry is the record's byte offset, with
-// the record's species (staged in its fourth slot) in the five low bits when
+// ascending record order.  The record kself (the atom itself) is never
+// listed.  SHIFT adds the cell's periodic image shift to the difference,
+// (x_j - x_i) + s, as the minimum image convention rounds it; its pairs go to
+// the back of the row.  An entry is the record's byte offset, with the
+// record's species (staged in its fourth slot) in the five low bits when
 // `typed`.
 __device__ __forceinline__ int row_entry(const double *rec, int k, bool typed)
 {
@@ -294,7 +299,7 @@ template <bool SHIFT>
 __device__ __forceinline__ void list_cell(const double *rec, int k0, int k1, int kself,
                                           double xi, double yi, double zi, double sx, double sy,
                                           double sz, double rl2, int *__restrict__ idx, int i,
-                                          int N, int mn, bool typed, int &n, int &total)
+                                          int N, int mn, bool typed, RowFill &row)
 {
 #pragma clang fp contract(off)
     for (int c0 = k0; c0 < k1; c0 += 32) {
@@ -309,16 +314,15 @@ __device__ __forceinline__ void list_cell(const double *rec, int k0, int k1, int
                 dy = dy + sy;
                 dz = dz + sz;
             }
-            double r2 = (dx * dx + dy * dy) + dz * dz;
-            mask |= (r2 < rl2 ? 1u : 0u) << q;
+            mask |= (dist2(dx, dy, dz) < rl2 ? 1u : 0u) << q;
         }
         unsigned d = (unsigned)(kself - c0);
         if (d < 32u) mask &= ~(1u << d);
-        total += __popc(mask);
+        row.total += __popc(mask);
         while (mask) {
             int q = __ffs(mask) - 1;
             mask &= mask - 1u;
-            if (n < mn) idx[nl_off(n++, i, N)] = row_entry(rec, c0 + q, typed);
+            row.put(idx, i, N, mn, !SHIFT, row_entry(rec, c0 + q, typed));
         }
     }
 }
@@ -334,7 +338,7 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
     const int g = xcd_tile(blockIdx.x, gridDim.x);
     tile_setup(bx, bd, g, t);
     halo_table(t, bx, bd, H);
-    stage<false>(t, st, H, rec, hmax, false, flags, nl.tsrc + (size_t)g * hmax);
+    stage<false>(t, st, H, rec, hmax, flags, nl.tsrc + (size_t)g * hmax);
     if (threadIdx.x == 0) nl.ttotal[g] = H.total;
     const double L = t.L, invL = t.invL, rl2 = bx.rl2[t.b];
     const int mn = nl.mn, nc = t.nc;
@@ -344,7 +348,7 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
     for (int i = t.s0 + threadIdx.x; i < t.s1; i += kT) {
         double xi = st.x[i], yi = st.y[i], zi = st.z[i];
         int cx = cell_coord(xi, ncL, nc), cy = cell_coord(yi, ncL, nc), cz = cell_coord(zi, ncL, nc);
-        int n = 0, total = 0;
+        RowFill row;
         if (t.mode == kTileA) {
             int lx = cx - t.ox, ly = cy - t.oy, lz = cz - t.oz;
             int hs = halo_index(t, lx, ly, lz);
@@ -368,11 +372,11 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
                         int k0 = H.off[h], k1 = min(H.off[h + 1], hmax);
                         if (code == kNoShift)
                             list_cell<false>(rec, k0, k1, kself, xi, yi, zi, 0.0, 0.0, 0.0, rl2,
-                                             nl.idx, i, N, mn, typed, n, total);
+                                             nl.idx, i, N, mn, typed, row);
                         else
                             list_cell<true>(rec, k0, k1, -1, xi, yi, zi, shift_of(code, 0, L),
                                             shift_of(code, 1, L), shift_of(code, 2, L), rl2,
-                                            nl.idx, i, N, mn, typed, n, total);
+                                            nl.idx, i, N, mn, typed, row);
                     }
         } else {
             int kself = H.off[(cz * nc + cy) * nc + cx] + (i - H.start[(cz * nc + cy) * nc + cx]);
@@ -387,76 +391,116 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
                             if (k == kself) continue;
                             const double *r = rec + 4 * k;
                             double dx = r[0] - xi, dy2 = r[1] - yi, dz2 = r[2] - zi;
-                            dx = dx - rint(dx * invL) * L;
-                            dy2 = dy2 - rint(dy2 * invL) * L;
-                            dz2 = dz2 - rint(dz2 * invL) * L;
-                            double r2 = (dx * dx + dy2 * dy2) + dz2 * dz2;
-                            if (r2 < rl2) {
-                                if (n < mn) nl.idx[nl_off(n++, i, N)] = row_entry(rec, k, typed);
-                                ++total;
+                            double kx_ = rint(dx * invL), ky_ = rint(dy2 * invL),
+                                   kz_ = rint(dz2 * invL);
+                            dx = dx - kx_ * L;
+                            dy2 = dy2 - ky_ * L;
+                            dz2 = dz2 - kz_ * L;
+                            if (dist2(dx, dy2, dz2) < rl2) {
+                                row.put(nl.idx, i, N, mn, kx_ == 0.0 && ky_ == 0.0 && kz_ == 0.0,
+                                        row_entry(rec, k, typed));
+                                ++row.total;
                             }
                         }
                     }
         }
-        nl.count[i] = n;
-        nl.total[i] = total;
-        if (total > mn) bad |= MD_FLAG_NLIST_OVERFLOW;
+        nl.count[i] = row.close(nl.idx, i, N, mn);
+        nl.total[i] = row.total;
+        if (row.total > mn) bad |= MD_FLAG_NLIST_OVERFLOW;
     }
     raise_flags(flags, bad);
 }
 
 // ---------------------------------------------------------------- passes
 
-// Visit the row of slot i (record byte offsets) four entries at a time, one
-// 16-byte load per group: groups q0, q0 + S, ... (S lanes share a row).  While
-// one group is evaluated, the next is already in flight; the two registers
-// alternate roles (the loop body is unrolled by two) so that no register copy
-// at the back edge waits for a load.
-template <bool IMG, bool TYPED, int S, class Body>
-__device__ __forceinline__ void for_row(const int *__restrict__ idx, int i, int N, int n1, int q0,
-                                        const double *rec, double xi, double yi, double zi,
-                                        double L, double invL, Body &&body)
+// Visit the n1 entries of the row of slot i (record byte offsets) four at a
+// time, one 16-byte load per group: groups part, part + S, ... (S lanes share
+// a row).  While one group is evaluated, the next is already in flight; the
+// two registers alternate roles (the loop body is unrolled by two) so that no
+// register copy at the back edge waits for a load.  The four records of a
+// group are read from LDS together (entries past the end of the row read
+// record 0 and are dropped), then each pair inside the cutoff goes to
+// body(dx, dy, dz, r2, F'_j, type_j).  With IMG, entries from np on (pairs
+// across a face of the box) take the minimum image.  WITH_FP reads F'_j.
+template <bool IMG, bool TYPED, bool WITH_FP, int S, class Body>
+__device__ __forceinline__ void for_row(const int *__restrict__ idx, int i, int N, int n1, int np,
+                                        int part, const double *rec, double xi, double yi,
+                                        double zi, double L, double invL, double rc2,
+                                        Body &&body)
 {
     if (n1 <= 0) return;
     const int4 *g = reinterpret_cast<const int4 *>(idx) + i;
     const int ng = (n1 + 3) >> 2;
-    auto group = [&](const int4 &c, int m) {
-        int kk[4] = {c.x, c.y, c.z, c.w};
+    const char *base = reinterpret_cast<const char *>(rec);
+    auto group = [&](const int4 &c, int q) {
+        const int m = n1 - 4 * q, mp = np - 4 * q;
+        const int kk[4] = {c.x, c.y, c.z, c.w};
+        unsigned off[4];
+        int tj[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            if (u < m) {
-                unsigned off = (unsigned)kk[u];
-                int tj = 0;
-                if constexpr (TYPED) {
-                    tj = (int)(off & 31u);
-                    off &= ~31u;
-                }
-                const double2 *r = reinterpret_cast<const double2 *>(
-                    reinterpret_cast<const char *>(rec) + off);
-                double2 a = r[0], b2 = r[1];
-                double dx = a.x - xi, dy = a.y - yi, dz = b2.x - zi;
-                if constexpr (IMG) {
-                    dx = min_image(dx, L, invL);
-                    dy = min_image(dy, L, invL);
-                    dz = min_image(dz, L, invL);
-                }
-                body(dx, dy, dz, b2.y, tj);
+            unsigned o = (unsigned)kk[u];
+            tj[u] = TYPED ? (int)(o & 31u) : 0;
+            if constexpr (TYPED) o &= ~31u;
+            off[u] = u < m ? o : 0u;
+        }
+        double2 A[4];
+        double zj[4], fj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double2 *r = reinterpret_cast<const double2 *>(base + off[u]);
+            A[u] = r[0];
+            if constexpr (WITH_FP) {
+                double2 B = r[1];
+                zj[u] = B.x;
+                fj[u] = B.y;
+            } else {
+                zj[u] = reinterpret_cast<const double *>(r + 1)[0];
+                fj[u] = 0.0;
             }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            double dx = A[u].x - xi, dy = A[u].y - yi, dz = zj[u] - zi;
+            if (IMG && u >= mp) {
+                dx = min_image(dx, L, invL);
+                dy = min_image(dy, L, invL);
+                dz = min_image(dz, L, invL);
+            }
+            const double r2 = dist2(dx, dy, dz);
+            if (u < m && r2 < rc2) body(dx, dy, dz, r2, fj[u], tj[u]);
         }
     };
     // Every load is unconditional (past the end of the row it re-reads the
     // row's last group, already in cache): with a fixed number of loads per
     // iteration the wait before a group can leave the later load in flight.
     auto load = [&](int q) { return g[(size_t)min(q, ng - 1) * N]; };
-    const int qa = S == 1 ? 0 : q0;  // one lane per row: the loop counter stays uniform
+    const int qa = S == 1 ? 0 : part;  // one lane per row: the loop counter stays uniform
     int4 a = load(qa);
     int4 b = load(qa + S);
     for (int q = qa; q < ng; q += 2 * S) {
-        group(a, n1 - 4 * q);
+        group(a, q);
         a = load(q + 2 * S);
-        group(b, n1 - 4 * (q + S));
+        group(b, q + S);
         b = load(q + 3 * S);
     }
+}
+
+// The whole row of slot i.  The minimum image is compiled in only for the
+// wavefronts that hold an atom with pairs across a face of the box.
+template <bool TYPED, bool WITH_FP, int S, class Body>
+__device__ __forceinline__ void for_row_all(const NList &nl, int i, int N, int part,
+                                            const double *rec, double xi, double yi, double zi,
+                                            double L, double invL, double rc2, Body &&body)
+{
+    const unsigned w = (unsigned)nl.count[i];
+    const int n1 = (int)(w & 0xffffu), np = (int)(w >> 16);
+    if (__any(np < n1))
+        for_row<true, TYPED, WITH_FP, S>(nl.idx, i, N, n1, np, part, rec, xi, yi, zi, L, invL,
+                                         rc2, body);
+    else
+        for_row<false, TYPED, WITH_FP, S>(nl.idx, i, N, n1, np, part, rec, xi, yi, zi, L, invL,
+                                          rc2, body);
 }
 
 // Sum over the P lanes (1 or 2, adjacent) that share the row of one atom: a
@@ -506,7 +550,7 @@ __device__ __forceinline__ void run_tiles(int G, const State &st, const Boxes &b
     if (g < 0) return;
     Tile t;
     tile_setup(bx, bd, g, t);
-    stage_list<WITH_FP>(g, t, st, nl, rec, hmax, t.mode == kTileA);
+    stage_list<WITH_FP>(g, st, nl, rec, hmax);
     while (true) {
         const int gn = tile_at(blockIdx.x, m + 1, P, G);
         Tile tn = t;
@@ -521,23 +565,15 @@ __device__ __forceinline__ void run_tiles(int G, const State &st, const Boxes &b
 #pragma unroll
         for (int u = 0; u < R; ++u) e[u] = src[min(u * kT + tid, hmax - 1)];
         double px[R], py[R], pz[R], pf[R];
-        const bool shn = tn.mode == kTileA;
 #pragma unroll
         for (int u = 0; u < R; ++u) {
             int k = u * kT + tid;
             if (k < totn) {
-                int j = (int)(e[u] & kSlotMask);
+                int j = (int)e[u];
                 px[u] = st.x[j];
                 py[u] = st.y[j];
                 pz[u] = st.z[j];
                 if constexpr (WITH_FP) pf[u] = st.Fp[j];
-                if (shn) {
-                    int c = (int)(e[u] >> kSlotBits), cz = c / 9, cy = (c - 9 * cz) / 3;
-                    int cx = c - 9 * cz - 3 * cy;
-                    px[u] += (double)(cx - 1) * tn.L;
-                    py[u] += (double)(cy - 1) * tn.L;
-                    pz[u] += (double)(cz - 1) * tn.L;
-                }
             }
         }
         __syncthreads();
@@ -572,26 +608,18 @@ __global__ __launch_bounds__(kT) void k_tile_density(int N, int G, State st, Box
     unsigned bad = 0;
     const int part = P == 1 ? 0 : (int)threadIdx.x % P;
     run_tiles<false>(G, st, bx, bd, nl, rec, hmax, [&](const Tile &t) {
-        const bool shifted = t.mode == kTileA;
         for (int i = t.s0 + (int)threadIdx.x / P; i < t.s1; i += kT / P) {
             double xi = st.x[i], yi = st.y[i], zi = st.z[i];
-            int n1 = nl.count[i] & 0xffff;
             double rho = 0.0;
             const int ai = KIND == kTyped ? st.type[i] : 0;
-            auto body = [&](double dx, double dy, double dz, double, int tj) {
-                double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                if (r2 < pot.rc2) {
-                    if constexpr (KIND == kTyped)
-                        rho += dens_typed(pot, r2 * rsqrt_nr(r2), ai, tj, bad);
-                    else
-                        rho += dens<KIND>(pot, r2 * rsqrt_nr(r2), bad);
-                }
+            auto body = [&](double, double, double, double r2, double, int tj) {
+                if constexpr (KIND == kTyped)
+                    rho += dens_typed(pot, r2 * rsqrt_nr(r2), ai, tj, bad);
+                else
+                    rho += dens<KIND>(pot, r2 * rsqrt_nr(r2), bad);
             };
-            constexpr bool TY = KIND == kTyped;
-            if (shifted)
-                for_row<false, TY, P>(nl.idx, i, N, n1, part, rec, xi, yi, zi, t.L, t.invL, body);
-            else
-                for_row<true, TY, P>(nl.idx, i, N, n1, part, rec, xi, yi, zi, t.L, t.invL, body);
+            for_row_all<KIND == kTyped, false, P>(nl, i, N, part, rec, xi, yi, zi, t.L, t.invL,
+                                                  pot.rc2, body);
             rho = lanes_sum<P>(rho);
             if (P > 1 && part != 0) continue;
             double F, Fp;
@@ -627,14 +655,12 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
         const int g = xcd_tile(blockIdx.x, gridDim.x);
         Tile t;
         tile_setup(bx, bd, g, t);
-        const bool shifted = t.mode == kTileA;
-        stage_list<true>(g, t, st, nl, rec, hmax, shifted);
+        stage_list<true>(g, st, nl, rec, hmax);
         const double thr2 = bx.thr2[t.b];
         const int part = P == 1 ? 0 : (int)threadIdx.x % P;
         for (int i = t.s0 + (int)threadIdx.x / P; i < t.s1; i += kT / P) {
             double xi = st.x[i], yi = st.y[i], zi = st.z[i];
             double fpi = st.Fp[i];
-            int n1 = nl.count[i] & 0xffff;
             // the epilogue's inputs are loaded before the row, so their
             // latency hides behind it
             double v0x = 0.0, v0y = 0.0, v0z = 0.0, rx = 0.0, ry = 0.0, rz = 0.0;
@@ -650,9 +676,8 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
             }
             double ax = 0.0, ay = 0.0, az = 0.0, ep = 0.0, wv = 0.0;
             const int ai = KIND == kTyped ? st.type[i] : 0;
-            auto body = [&](double dx, double dy, double dz, double fpj, int tj) {
-                double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                if (r2 < pot.rc2) {
+            auto body = [&](double dx, double dy, double dz, double r2, double fpj, int tj) {
+                {
                     double inv_r = rsqrt_nr(r2);
                     // f_i += [(F'_i + F'_j) rho'(r) + V'(r)] (x_j - x_i) / r; with
                     // several species [F'_i rho^(ab)'(r) + F'_j rho^(ba)'(r) + V^(ab)'(r)]
@@ -679,11 +704,8 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
                     az = fma(coef, dz, az);
                 }
             };
-            constexpr bool TY = KIND == kTyped;
-            if (shifted)
-                for_row<false, TY, P>(nl.idx, i, N, n1, part, rec, xi, yi, zi, t.L, t.invL, body);
-            else
-                for_row<true, TY, P>(nl.idx, i, N, n1, part, rec, xi, yi, zi, t.L, t.invL, body);
+            for_row_all<KIND == kTyped, true, P>(nl, i, N, part, rec, xi, yi, zi, t.L, t.invL,
+                                                 pot.rc2, body);
             ax = lanes_sum<P>(ax);
             ay = lanes_sum<P>(ay);
             az = lanes_sum<P>(az);
@@ -754,8 +776,8 @@ __global__ __launch_bounds__(kT) void k_tile_get_neighbors(int N, State st, Boxe
         int o = st.id[i];
         counts[o] = nl.total[i];
         int m = min(min(nl.count[i] & 0xffff, nl.mn), cols);
-        for (int n = 0; n < m; ++n) {
-            int k = nl.idx[nl_off(n, i, N)] >> 5;
+        for (int q = 0; q < m; ++q) {
+            int k = nl.idx[nl_off(q, i, N)] >> 5;
             int lo = 0, hi = t.nh - 1;
             while (lo < hi) {
                 int mid = (lo + hi + 1) >> 1;
@@ -763,7 +785,7 @@ __global__ __launch_bounds__(kT) void k_tile_get_neighbors(int N, State st, Boxe
                 else hi = mid - 1;
             }
             int j = H.start[lo] + (k - H.off[lo]);
-            ids[(size_t)o * cols + n] = st.id[j];
+            ids[(size_t)o * cols + q] = st.id[j];
         }
     }
 }
