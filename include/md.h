@@ -137,8 +137,10 @@ typedef struct {
 int md_create(const md_system *sys, const md_potential *pot, md_ctx **out);
 
 /* Device bytes a context for these descriptors holds (*bytes): the size of
- * the workspace md_create_in needs.  Computed by creating and destroying
- * such a context (synchronous; needs that much free device memory). */
+ * the workspace md_create_in needs.  Host arithmetic only: the descriptors
+ * are validated as md_create does and every buffer of such a context is
+ * counted, but nothing is allocated, copied or launched on the device, so
+ * the query also answers for systems larger than the free device memory. */
 int md_workspace_size(const md_system *sys, const md_potential *pot, size_t *bytes);
 
 /* As md_create, but every device buffer of the context (state in cell

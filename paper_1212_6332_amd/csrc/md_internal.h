@@ -174,6 +174,13 @@ void launch_pair_tables(Ctx &c, hipStream_t s);
 void launch_refresh_types(Ctx &c, hipStream_t s);
 void batched_graph_reset(Ctx &c);
 
+// Context set-up (md_api.hip).  kMeasure counts the workspace bytes only
+// (nothing is allocated, copied or launched); kOneShot builds the context in
+// `workspace` for one evaluation on `stream` (no capture stream, no graph).
+constexpr int kNormal = 0, kMeasure = 1, kOneShot = 2;
+int create_context(const md_system *sys, const md_potential *pot, md_ctx **out, void *workspace,
+                   size_t workspace_bytes, int mode, hipStream_t stream);
+
 // Device memory of a context (md_api.hip): from hipMalloc, or carved from the
 // caller's workspace; sizes are rounded up to 256 bytes.
 int ctx_alloc(Ctx &c, void **p, size_t bytes);
@@ -303,6 +310,8 @@ struct Ctx {
     size_t alloc_bytes = 0;            // bytes handed out by ctx_alloc (256-byte granules)
     char *arena = nullptr;             // caller's workspace (md_create_in): blocks are carved
     size_t arena_size = 0, arena_used = 0;  // from it and never freed
+    bool measure = false;              // sizes only: nothing allocated, copied or launched
+    bool oneshot = false;              // one evaluation in the static scratch (md_forces_static)
 };
 
 }  // namespace mdk

@@ -72,3 +72,19 @@ def test_workspace_too_small_and_capacity_growth():
     b = trajectory(ref, wl, 15)
     for u, v in zip(a[:4], b[:4]):
         assert np.array_equal(u, v)
+
+
+def test_size_query_allocates_nothing():
+    """md_workspace_size only counts: it answers for a system whose workspace
+    exceeds the whole device memory, and the free memory does not move."""
+    wl = W.fcc4m(ncell=72)                   # 1,492,992 atoms
+    torch.cuda.synchronize()
+    free0, total = torch.cuda.mem_get_info()
+    size = md.System.workspace_size(wl.box_offset, wl.box_len, wl.pot, wl.mass, wl.dt,
+                                    wl.skin, max_neighbors=65532)
+    free1, _ = torch.cuda.mem_get_info()
+    assert size > total
+    assert free1 == free0
+    # and the count is the one md_create_in consumes (the smaller system above
+    # needs exactly its measured size: see test_workspace_too_small_...)
+    assert size >= 4 * 65532 * wl.n_atoms
