@@ -29,12 +29,25 @@
  *     arrays they reference are read during the call only.
  *   - Return value: MD_OK or a negative MD_ERR_* code.  Argument, capacity
  *     and state errors are detected on the host and returned at once.
- *     Conditions found by kernels (list overflow, table range, non-finite
- *     coordinates) set bits in a device status word read by md_status().
+ *     Conditions found by kernels set bits in a device status word.  List
+ *     capacity is never left short: a list build that finds a row longer
+ *     than the capacity (or a tile whose halo exceeds its LDS) is noticed
+ *     before any pass reads that list -- builds started by a call
+ *     (md_build_neighbors, or the first pass after md_set_state) are waited
+ *     for and checked; builds decided on the device inside md_step halt the
+ *     step sequence there -- and the library then raises the capacity
+ *     (taking memory as md_set_max_neighbors does; on a tile overflow the
+ *     context moves to the per-atom passes), builds again, and goes on
+ *     (md_step completes the halted step and takes the rest), returning
+ *     MD_ERR_NLIST_OVERFLOW only when the capacity cannot be raised.
+ *     MD_FLAG_NLIST_OVERFLOW then stays set for md_status.  Table-range and
+ *     non-finite conditions are returned by the next md_step (as
+ *     MD_ERR_TABLE_RANGE, MD_ERR_NONFINITE, once) or read by md_status().
  *   - A context belongs to the device that was current at md_create(); it
  *     allocates its device workspace there, once (or takes it from the
  *     caller's block, md_create_in).  No entry point allocates device memory
- *     after md_create() except md_set_max_neighbors().
+ *     after md_create() except md_set_max_neighbors() and the capacity
+ *     increase after a list overflow (see above).
  *   - One context must not be used from two host threads at once.
  */
 #ifndef MD_H
@@ -119,7 +132,8 @@ typedef struct {
 
 typedef struct {
     int32_t n_boxes;            /* B >= 1 independent periodic cubic boxes          */
-    int32_t max_neighbors;      /* list capacity per atom; 0 = estimate from density */
+    int32_t max_neighbors;      /* list capacity per atom (rounded up to a multiple
+                                   of 8, at most 65528); 0 = estimate from density   */
     const int64_t *box_offset;  /* host [B+1]: atoms of box b are
                                    box_offset[b] .. box_offset[b+1]-1; [0] = 0       */
     const double *box_len;      /* host [B]: edge length of each cubic box           */
@@ -173,6 +187,17 @@ int md_set_theta(md_ctx *ctx, const double *theta, void *stream);
  * The next pass rebuilds the neighbour list first. */
 int md_set_state(md_ctx *ctx, const double *pos, const double *vel, void *stream);
 
+/* Bind caller-owned device buffers pos[N][3] and vel[N][3] (original atom
+ * order) as the state of record (the paper's device-resident position and
+ * velocity arrays of Section 3.1, owned by the caller): the state is loaded
+ * from them now, as by md_set_state (vel NULL: zero velocities), and every
+ * md_step writes the new positions and velocities back into them (vel NULL:
+ * positions only), stream ordered, before it returns; between calls the
+ * caller reads them in place.  A caller who writes to the bound buffers binds
+ * them again (or calls md_set_state) so that the context takes the change.
+ * The buffers must stay valid while bound; pos = vel = NULL unbinds. */
+int md_bind(md_ctx *ctx, double *pos, double *vel, void *stream);
+
 /* Copy the current positions and velocities out (either may be NULL).
  * Positions are wrapped into the box at each list build and integrated
  * without wrapping in between. */
@@ -181,8 +206,11 @@ int md_get_state(md_ctx *ctx, double *pos, double *vel, void *stream);
 /* List build (Section 3.2): wrap positions into each box, bin atoms into
  * cells of edge >= list radius, sort them by (cell, original index) with a
  * counting sort, and build the full neighbour list of every atom (all j != i
- * of the same box within the list radius under the minimum image; squared
- * distance (dx dx + dy dy) + dz dz without fused multiply-add, strict <). */
+ * of the same box within the list radius under the minimum image: x_j - x_i,
+ * then the periodic shift, then (dx dx + dy dy) + dz dz with every product
+ * and sum rounded on its own, strict <; every pass tests r < rc on the same
+ * arithmetic).  Waits for the build; raises the capacity and builds again
+ * when a row did not fit. */
 int md_build_neighbors(md_ctx *ctx, void *stream);
 
 /* Density pass (Fig. 5) with the embedding fused: rho_i = sum of rho(r_ij)
@@ -207,7 +235,12 @@ int md_forces(md_ctx *ctx, double *f_out, double *e_atom, double *e_box, void *s
  * decided on the device, density + embedding, force, half kick.  Brings the
  * list and forces up to date first if needed (nsteps = 0 does only that,
  * with the kernels that would take the steps).  The step sequence is
- * captured once in a HIP graph and replayed. */
+ * captured once in a HIP graph and replayed.  Waits for the steps and reads
+ * the device status word at the end: a list that outgrew its capacity
+ * inside the steps is handled as described at the top (with several boxes
+ * in the persistent stepper, the call is taken again from its start state
+ * with the larger capacity); MD_ERR_TABLE_RANGE or MD_ERR_NONFINITE report
+ * those conditions (the state is then the one the kernels reached). */
 int md_step(md_ctx *ctx, int nsteps, void *stream);
 
 /* Kinetic energy per box, ke_box[B] = sum m v^2 / 2 (eV). */

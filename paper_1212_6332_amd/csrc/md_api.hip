@@ -229,8 +229,12 @@ int upload_potential(Ctx &c, const md_potential *p, hipStream_t s, bool first)
 // the new one exists, so a failure leaves the context as it was.
 int alloc_list(Ctx &c, int mn)
 {
-    mn = (mn + 3) / 4 * 4;  // rows are stored in groups of four
-    if (mn > 65532) return MD_ERR_ARG;
+    // rows are stored in groups of four; a multiple of eight also keeps the
+    // split of a row's entries over the lanes that share it (entry index
+    // modulo the lane count, at most eight) independent of the capacity, so
+    // results do not depend on it
+    mn = (mn + 7) / 8 * 8;
+    if (mn > kMaxCapacity) return MD_ERR_ARG;
     int *idx = nullptr;
     ALLOC(idx, (size_t)mn * c.N);
     int rz = zero(c, idx, sizeof(int) * (size_t)mn * c.N);
@@ -262,25 +266,97 @@ int upload_type_coef(Ctx &c)
     return MD_OK;
 }
 
-// Bring the list, density and forces up to date on stream s.
-void ensure_list(Ctx &c, hipStream_t s)
+// Switch between the tiled and the per-atom passes (as MD_OPT_TILED does).
+void set_tiled(Ctx &c, bool v)
 {
-    if (!c.list_valid) {
-        launch_build(c, false, s);
-        c.list_valid = true;
-        c.density_valid = c.forces_valid = false;
-        batched_invalidate(c);
-    }
+    if (v == c.tiled) return;
+    c.tiled = v;
+    graph_reset(c);
+    c.list_valid = c.density_valid = c.forces_valid = false;
 }
 
-void ensure_density(Ctx &c, hipStream_t s)
+// The device status words after the work enqueued on s (waits for it).
+int read_flags(Ctx &c, hipStream_t s, unsigned *w)
 {
-    ensure_list(c, s);
+    HIP_TRY(hipMemcpyAsync(w, c.dev.flags, kFlagWords * sizeof(unsigned), hipMemcpyDeviceToHost,
+                           s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MD_OK;
+}
+
+// A list build ran out of capacity (status words w): lift the halt and raise
+// the capacity -- the row capacity to the longest row found plus an eighth,
+// or, when a tile's halo did not fit LDS, the per-atom passes for the rest of
+// the context's life.  The list must then be built again.  MD_FLAG_NLIST_OVERFLOW
+// stays set for md_status; MD_FLAG_TILE_OVERFLOW is cleared once handled.
+int regrow(Ctx &c, const unsigned *w, hipStream_t s)
+{
+    launch_fill_u32(c.dev.flags + kHaltWord, 2, 0u, s);
+    c.list_valid = c.density_valid = c.forces_valid = false;
+    batched_invalidate(c);
+    if (w[0] & MD_FLAG_TILE_OVERFLOW) {
+        launch_clear_bits(c, MD_FLAG_TILE_OVERFLOW, s);
+        set_tiled(c, false);
+        c.tile_feasible = false;
+    }
+    const int need = (int)w[kMaxRowWord];
+    if (need > c.nl.mn) {
+        if (need > kMaxCapacity) return MD_ERR_NLIST_OVERFLOW;
+        int want = std::min(kMaxCapacity, need + need / 8 + 8);
+        HIP_TRY(hipStreamSynchronize(s));
+        if (alloc_list(c, want) != MD_OK) return MD_ERR_NLIST_OVERFLOW;
+        graph_reset(c);
+        if (c.B > 1) {
+            int rc = batched_prepare(c);
+            if (rc != MD_OK) return rc;
+        }
+    }
+    return MD_OK;
+}
+
+// A list build from the host: waits for it and, when a row or a tile ran out
+// of capacity, raises the capacity and builds again, so that no pass ever
+// runs on truncated rows.
+int build_checked(Ctx &c, hipStream_t s)
+{
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        launch_build(c, false, s);
+        unsigned w[kFlagWords];
+        int rc = read_flags(c, s, w);
+        if (rc != MD_OK) return rc;
+        if (!w[kHaltWord]) {
+            c.list_valid = true;
+            c.density_valid = c.forces_valid = false;
+            batched_invalidate(c);
+            return MD_OK;
+        }
+        if ((rc = regrow(c, w, s)) != MD_OK) return rc;
+    }
+    return MD_ERR_NLIST_OVERFLOW;
+}
+
+// Bring the list, density and forces up to date on stream s.
+int ensure_list(Ctx &c, hipStream_t s)
+{
+    return c.list_valid ? MD_OK : build_checked(c, s);
+}
+
+int ensure_density(Ctx &c, hipStream_t s)
+{
+    int rc = ensure_list(c, s);
+    if (rc != MD_OK) return rc;
     if (!c.density_valid) {
         launch_density(c, s);
         c.density_valid = true;
     }
+    return MD_OK;
 }
+
+#define ENSURE(call)                    \
+    do {                                \
+        int rc_ = (call);               \
+        if (rc_ != MD_OK) return rc_;   \
+    } while (0)
 
 // One velocity-Verlet step on stream s.  kick_drift: the step starts with
 // the half kick and drift (false when the previous force pass performed
@@ -333,6 +409,7 @@ int capture_steps(Ctx &c, int nsteps)
         launch_step(c, c.cap_stream, k == 0 || k > fused, k < fused ? 2 : 1);
     }
     c.st = prim;
+    c.graph_fused = fused;
     HIP_TRY(hipStreamEndCapture(c.cap_stream, &g));
     hipError_t e = hipGraphInstantiate(&c.graph_exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
@@ -341,6 +418,119 @@ int capture_steps(Ctx &c, int nsteps)
         return MD_ERR_DEVICE;
     }
     c.graph_len = nsteps;
+    return MD_OK;
+}
+
+// nsteps steps of the captured graphs and then single steps; *graphs: the
+// graphs launched.
+int run_steps(Ctx &c, int nsteps, hipStream_t s, int *graphs)
+{
+    int done = 0;
+    *graphs = 0;
+    if (c.use_graph && nsteps >= c.graph_steps) {
+        if (!c.graph_exec || c.graph_len != c.graph_steps) {
+            int rc = capture_steps(c, c.graph_steps);
+            if (rc != MD_OK) return rc;
+        }
+        for (; done + c.graph_len <= nsteps; done += c.graph_len, ++*graphs)
+            HIP_TRY(hipGraphLaunch(c.graph_exec, s));
+    }
+    for (; done < nsteps; ++done) launch_step(c, s, true, 1);
+    return MD_OK;
+}
+
+// Steps of one box, or of boxes through the merged-box kernels.  A list
+// build inside the steps that runs out of capacity halts the step sequence
+// on the device (every later kernel of it does nothing); at the end the host
+// reads the status, and if the steps halted it raises the capacity, builds
+// the list again, completes the halted step (density, force and second half
+// kick, and with the barostat the next pressure and scale factor) and takes
+// the remaining steps.  The trajectory is the one a context with enough
+// capacity from the start would have taken.
+int steps_merged(Ctx &c, int nsteps, hipStream_t s)
+{
+    ENSURE(ensure_list(c, s));
+    if (c.baro_on && !c.baro_mu_valid) {
+        // pressure of the current state: the first step's scale factor
+        ENSURE(ensure_density(c, s));
+        launch_force(c, true, 0, s);
+        launch_pressure_eval(c, s);
+        launch_baro_mu(c, s);
+        c.forces_valid = c.baro_mu_valid = true;
+    } else if (!c.forces_valid) {
+        ENSURE(ensure_density(c, s));
+        launch_force(c, false, 0, s);
+        c.forces_valid = true;
+    }
+    int left = nsteps;
+    for (int round = 0; left > 0; ++round) {
+        if (round > 8) return MD_ERR_NLIST_OVERFLOW;
+        launch_step_mark(c, s);
+        int graphs = 0;
+        ENSURE(run_steps(c, left, s, &graphs));
+        unsigned w[kFlagWords];
+        ENSURE(read_flags(c, s, w));
+        if (!w[kHaltWord]) break;
+        // step k of this run halted at its list build (after its drift)
+        const uint64_t now = ((uint64_t)w[5] << 32) | w[3];
+        const uint64_t mark = ((uint64_t)w[kMarkWord + 1] << 32) | w[kMarkWord];
+        const int k = (int)(now - mark);
+        if (k >= left) return MD_ERR_STATE;
+        if (k < graphs * c.graph_len) {
+            // inside a graph, odd fused steps run on the other position buffer
+            const int j = k % c.graph_len;
+            if (j < c.graph_fused && j % 2 == 1) {
+                const size_t nb = sizeof(double) * (size_t)c.N;
+                HIP_TRY(hipMemcpyAsync(c.st.x, c.st.xo, nb, hipMemcpyDeviceToDevice, s));
+                HIP_TRY(hipMemcpyAsync(c.st.y, c.st.yo, nb, hipMemcpyDeviceToDevice, s));
+                HIP_TRY(hipMemcpyAsync(c.st.z, c.st.zo, nb, hipMemcpyDeviceToDevice, s));
+            }
+        }
+        launch_fill_u32(c.dev.flags + 1, 1, 0u, s);  // its rebuild request
+        ENSURE(regrow(c, w, s));
+        ENSURE(build_checked(c, s));
+        launch_density(c, s);
+        if (c.baro_on) {
+            launch_force(c, true, 1, s);
+            launch_pressure_eval(c, s);
+            launch_baro_mu(c, s);
+        } else {
+            launch_force(c, false, 1, s);
+        }
+        launch_step_end(c, s);
+        left -= k + 1;
+    }
+    c.list_valid = c.density_valid = c.forces_valid = true;
+    batched_invalidate(c);
+    return MD_OK;
+}
+
+// Steps of several boxes by the persistent stepper.  The start state is kept
+// in the merged-box sort scratch (which the stepper does not use); when a
+// box's list outgrew the capacity, the state is restored and the call is
+// taken again with a capacity for the longest row found.
+int steps_batched(Ctx &c, int nsteps, hipStream_t s)
+{
+    const size_t nb = sizeof(double) * (size_t)c.N;
+    double *keep[6] = {c.bd.sx, c.bd.sy, c.bd.sz, c.bd.svx, c.bd.svy, c.bd.svz};
+    double *live[6] = {c.st.x, c.st.y, c.st.z, c.st.vx, c.st.vy, c.st.vz};
+    for (int k = 0; k < 6; ++k)
+        HIP_TRY(hipMemcpyAsync(keep[k], live[k], nb, hipMemcpyDeviceToDevice, s));
+    for (int attempt = 0;; ++attempt) {
+        ENSURE(launch_batched_steps(c, nsteps, s));
+        unsigned w[kFlagWords];
+        ENSURE(read_flags(c, s, w));
+        if (!w[kMaxRowWord]) break;
+        if (attempt == 3) return MD_ERR_NLIST_OVERFLOW;
+        for (int k = 0; k < 6; ++k)
+            HIP_TRY(hipMemcpyAsync(live[k], keep[k], nb, hipMemcpyDeviceToDevice, s));
+        ENSURE(regrow(c, w, s));
+    }
+    c.host_steps += nsteps;
+    // forces in the state arrays match the new positions; the merged-box
+    // list and densities do not
+    c.list_valid = c.density_valid = false;
+    c.forces_valid = true;
     return MD_OK;
 }
 
@@ -546,7 +736,7 @@ int create_impl(const md_system *sys, const md_potential *pot, md_ctx **out, voi
     c.bd.n_cells = (int)cells;
     int mn = sys->max_neighbors > 0 ? sys->max_neighbors : ((int)mn_est + 7) / 8 * 8;
     if (mn < 1) mn = 1;
-    if (mn > 65535) return fail(MD_ERR_ARG);
+    if (mn > kMaxCapacity) return fail(MD_ERR_ARG);
 
     if (mode == kNormal &&
         hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking) != hipSuccess)
@@ -628,7 +818,7 @@ int create_impl(const md_system *sys, const md_potential *pot, md_ctx **out, voi
     if ((rc = dev_alloc(c, &c.bd.bsum, (size_t)cells / 4096 + 2)) != MD_OK) return fail(rc);
     if ((rc = zero(c, c.bd.cell_count, sizeof(int) * (size_t)cells)) != MD_OK) return fail(rc);
     if ((rc = alloc_list(c, mn)) != MD_OK) return fail(rc);
-    if ((rc = dev_alloc(c, &c.dev.flags, 8)) != MD_OK) return fail(rc);
+    if ((rc = dev_alloc(c, &c.dev.flags, kFlagWords)) != MD_OK) return fail(rc);
     {
         // barostat state per box: mu = 1, strain = 1, list radius, then results
         std::vector<double> hb(7 * (size_t)B, 0.0);
@@ -641,7 +831,7 @@ int create_impl(const md_system *sys, const md_potential *pot, md_ctx **out, voi
         if ((rc = h2d(c, c.d_baro, hb.data(), hb.size() * sizeof(double))) != MD_OK)
             return fail(rc);
     }
-    if ((rc = zero(c, c.dev.flags, 8 * sizeof(unsigned))) != MD_OK ||
+    if ((rc = zero(c, c.dev.flags, kFlagWords * sizeof(unsigned))) != MD_OK ||
         (rc = zero(c, c.nl.count, sizeof(int) * N)) != MD_OK ||
         (rc = zero(c, c.nl.total, sizeof(int) * N)) != MD_OK)
         return fail(rc);
@@ -835,6 +1025,22 @@ int md_set_state(md_ctx *h, const double *pos, const double *vel, void *stream)
     return MD_OK;
 }
 
+int md_bind(md_ctx *h, double *pos, double *vel, void *stream)
+{
+    if (!h) return MD_ERR_ARG;
+    Ctx &c = h->c;
+    if (!pos) {
+        if (vel) return MD_ERR_ARG;
+        c.bound_pos = c.bound_vel = nullptr;
+        return MD_OK;
+    }
+    int rc = md_set_state(h, pos, vel, stream);
+    if (rc != MD_OK) return rc;
+    c.bound_pos = pos;
+    c.bound_vel = vel;
+    return MD_OK;
+}
+
 int md_get_state(md_ctx *h, double *pos, double *vel, void *stream)
 {
     if (!h) return MD_ERR_ARG;
@@ -848,11 +1054,7 @@ int md_build_neighbors(md_ctx *h, void *stream)
     if (!h) return MD_ERR_ARG;
     Ctx &c = h->c;
     if (!c.state_set) return MD_ERR_STATE;
-    launch_build(c, false, as_stream(stream));
-    c.list_valid = true;
-    c.density_valid = c.forces_valid = false;
-    batched_invalidate(c);
-    return MD_OK;
+    return build_checked(c, as_stream(stream));
 }
 
 int md_density(md_ctx *h, double *rho_out, void *stream)
@@ -861,7 +1063,7 @@ int md_density(md_ctx *h, double *rho_out, void *stream)
     Ctx &c = h->c;
     if (!c.state_set) return MD_ERR_STATE;
     hipStream_t s = as_stream(stream);
-    ensure_list(c, s);
+    ENSURE(ensure_list(c, s));
     launch_density(c, s);
     c.density_valid = true;
     c.forces_valid = false;
@@ -875,7 +1077,7 @@ int md_embed(md_ctx *h, double *F_out, double *Fp_out, void *stream)
     Ctx &c = h->c;
     if (!c.state_set) return MD_ERR_STATE;
     hipStream_t s = as_stream(stream);
-    ensure_density(c, s);
+    ENSURE(ensure_density(c, s));
     launch_embed(c, s);
     if (F_out) launch_scatter_scalar(c, c.st.Femb, F_out, s);
     if (Fp_out) launch_scatter_scalar(c, c.st.Fp, Fp_out, s);
@@ -894,7 +1096,7 @@ int md_forces(md_ctx *h, double *f_out, double *e_atom, double *e_box, void *str
         if (f_out) launch_scatter_vec3(c, c.st.fx, c.st.fy, c.st.fz, f_out, s);
         return MD_OK;
     }
-    ensure_density(c, s);
+    ENSURE(ensure_density(c, s));
     launch_force(c, energy, 0, s);
     c.forces_valid = true;
     if (f_out) launch_scatter_vec3(c, c.st.fx, c.st.fy, c.st.fz, f_out, s);
@@ -909,51 +1111,20 @@ int md_step(md_ctx *h, int nsteps, void *stream)
     Ctx &c = h->c;
     if (!c.state_set) return MD_ERR_STATE;
     hipStream_t s = as_stream(stream);
-    if (c.B > 1 && c.batched && !c.baro_on) {
-        int rc = launch_batched_steps(c, nsteps, s);
-        if (rc != MD_OK) return rc;
-        c.host_steps += nsteps;
-        // forces in the state arrays match the new positions; the merged-box
-        // list and densities do not
-        c.list_valid = c.density_valid = false;
-        c.forces_valid = true;
-        return MD_OK;
+    int rc = (c.B > 1 && c.batched && !c.baro_on) ? steps_batched(c, nsteps, s)
+                                                  : steps_merged(c, nsteps, s);
+    if (rc != MD_OK) return rc;
+    if (c.bound_pos) launch_get_state(c, c.bound_pos, c.bound_vel, s);
+    // other conditions the kernels found: reported once, here
+    unsigned w[kFlagWords];
+    ENSURE(read_flags(c, s, w));
+    const unsigned report = w[0] & (MD_FLAG_NONFINITE | MD_FLAG_TABLE_RANGE);
+    if (report) {
+        launch_clear_bits(c, report, s);
+        HIP_TRY(hipStreamSynchronize(s));
+        return (report & MD_FLAG_NONFINITE) ? MD_ERR_NONFINITE : MD_ERR_TABLE_RANGE;
     }
-    ensure_list(c, s);
-    if (c.baro_on && !c.baro_mu_valid) {
-        // pressure of the current state: the first step's scale factor
-        ensure_density(c, s);
-        launch_force(c, true, 0, s);
-        launch_pressure_eval(c, s);
-        launch_baro_mu(c, s);
-        c.forces_valid = c.baro_mu_valid = true;
-    } else if (!c.forces_valid) {
-        ensure_density(c, s);
-        launch_force(c, false, 0, s);
-        c.forces_valid = true;
-    }
-    int done = 0;
-    if (c.use_graph && nsteps >= c.graph_steps) {
-        if (!c.graph_exec || c.graph_len != c.graph_steps) {
-            int rc = capture_steps(c, c.graph_steps);
-            if (rc != MD_OK) return rc;
-        }
-        for (; done + c.graph_len <= nsteps; done += c.graph_len)
-            HIP_TRY(hipGraphLaunch(c.graph_exec, s));
-    }
-    for (; done < nsteps; ++done) launch_step(c, s, true, 1);
-    c.list_valid = c.density_valid = c.forces_valid = true;
-    batched_invalidate(c);
     return MD_OK;
-}
-
-// Switch between the tiled and the per-atom passes (as MD_OPT_TILED does).
-static void set_tiled(Ctx &c, bool v)
-{
-    if (v == c.tiled) return;
-    c.tiled = v;
-    graph_reset(c);
-    c.list_valid = c.density_valid = c.forces_valid = false;
 }
 
 int md_autotune(md_ctx *h, void *stream, int32_t *block)
@@ -1035,7 +1206,7 @@ int md_pressure(md_ctx *h, double *p_box, double *w_box, void *stream)
     Ctx &c = h->c;
     if (!c.state_set) return MD_ERR_STATE;
     hipStream_t s = as_stream(stream);
-    ensure_density(c, s);
+    ENSURE(ensure_density(c, s));
     launch_force(c, true, 0, s);
     c.forces_valid = true;
     launch_pressure_eval(c, s);
@@ -1185,7 +1356,7 @@ int md_get_neighbors(md_ctx *h, int32_t *counts, int32_t *ids, int32_t max_cols,
     Ctx &c = h->c;
     if (!c.state_set) return MD_ERR_STATE;
     hipStream_t s = as_stream(stream);
-    ensure_list(c, s);
+    ENSURE(ensure_list(c, s));
     launch_get_neighbors(c, counts, ids, max_cols, s);
     HIP_TRY(hipStreamSynchronize(s));
     return MD_OK;
@@ -1238,7 +1409,7 @@ int md_adjoint(md_ctx *h, const double *g, const double *e, double *gtheta, void
     if (c.kind_user != MD_POT_BSPLINE) return MD_ERR_ARG;
     if (!c.state_set) return MD_ERR_STATE;
     hipStream_t s = as_stream(stream);
-    ensure_density(c, s);
+    ENSURE(ensure_density(c, s));
     launch_adjoint(c, g, e, gtheta, s);
     return MD_OK;
 }
@@ -1250,7 +1421,7 @@ int md_time_pass(md_ctx *h, int32_t pass, int32_t reps, void *stream, double *av
     Ctx &c = h->c;
     if (!c.state_set) return MD_ERR_STATE;
     hipStream_t s = as_stream(stream);
-    ensure_density(c, s);
+    ENSURE(ensure_density(c, s));
     if (!c.forces_valid) {
         launch_force(c, false, 0, s);
         c.forces_valid = true;
@@ -1284,9 +1455,10 @@ int md_time_pass(md_ctx *h, int32_t pass, int32_t reps, void *stream, double *av
     (void)hipEventDestroy(e1);
     *avg_ms = ms / reps;
     if (pass == MD_PASS_BUILD) {
-        // the build scratch held the saved state; rebuild on the unchanged positions
+        // the build scratch held the saved state; the next pass builds (with
+        // the capacity check) on the unchanged positions
         batched_invalidate(c);
-        c.density_valid = c.forces_valid = false;
+        c.list_valid = c.density_valid = c.forces_valid = false;
         return MD_OK;
     }
     for (int k = 0; k < 6; ++k) HIP_TRY(hipMemcpyAsync(live[k], save[k], nb, hipMemcpyDeviceToDevice, s));

@@ -205,7 +205,12 @@ __global__ __launch_bounds__(T) void k_batched(BArgs a)
                             }
                         }
                 cnt[i] = m;
-                if (m > a.mn) bad |= MD_FLAG_NLIST_OVERFLOW;
+                if (m > a.mn) {
+                    // recorded for the host, which redoes the call with a
+                    // larger capacity (the merged-box halt word stays clear)
+                    bad |= MD_FLAG_NLIST_OVERFLOW;
+                    atomicMax(a.flags + kMaxRowWord, (unsigned)m);
+                }
             }
             __syncthreads();
         };

@@ -319,8 +319,24 @@ __device__ __forceinline__ size_t nl_off(int r, int i, int N)
 }
 
 // Build kernels run unconditionally (gate == nullptr) or only when the device
-// rebuild request is set (inside replayed steps).
-__device__ __forceinline__ bool skip(const unsigned *gate) { return gate && gate[1] == 0u; }
+// rebuild request is set and the step sequence is not halted (inside
+// replayed steps).
+__device__ __forceinline__ bool skip(const unsigned *gate)
+{
+    return gate && (gate[1] == 0u || gate[kHaltWord] != 0u);
+}
+
+// The step sequence is halted: a list build ran out of capacity.
+__device__ __forceinline__ bool halted(const unsigned *flags) { return flags[kHaltWord] != 0u; }
+
+// A list build found a row of `total` entries beyond the capacity (or a tile
+// beyond its LDS): record it and halt the step sequence.
+__device__ __forceinline__ void raise_overflow(unsigned *flags, unsigned bit, int total)
+{
+    atomicOr(flags, bit);
+    if (total > 0) atomicMax(flags + kMaxRowWord, (unsigned)total);
+    atomicOr(flags + kHaltWord, 1u);
+}
 
 __device__ __forceinline__ void raise_flags(unsigned *flags, unsigned bad)
 {

@@ -22,6 +22,7 @@ constexpr int kRowLanes = 8;
 constexpr int64_t kRowSplitAtoms = 262144;
 inline int row_lanes(int64_t n) { return n < kRowSplitAtoms ? kRowLanes : 1; }
 constexpr int kChunk = 4096;       // atoms per partial sum of the energy reductions
+constexpr int kMaxCapacity = 65528; // list entries per atom: a multiple of 8 below 2^16
 constexpr int kTileThreads = 1024; // threads of a tiled-pass workgroup (one tile)
 constexpr int kHaloCells = 512;    // halo cells a tile may have
 constexpr int kTileGlobal = 0, kTileA = 1, kTileB = 2;  // halo modes of a box
@@ -161,7 +162,13 @@ struct NList {
 };
 
 // Device words: flags[0] status bits, flags[1] rebuild request,
-// flags[2] builds (low), flags[3] steps (low), flags[4] builds (high), flags[5] steps (high).
+// flags[2] builds (low), flags[3] steps (low), flags[4] builds (high), flags[5] steps (high),
+// flags[6] halt: a list build ran out of row or tile capacity, and every kernel
+// of the step sequence does nothing until the host has raised the capacity
+// and rebuilt; flags[7] the longest row such a build found; flags[8..9] the
+// step counter when md_step began (to tell which step halted).
+constexpr int kFlagWords = 16;
+constexpr int kHaltWord = 6, kMaxRowWord = 7, kMarkWord = 8;
 struct Dev {
     unsigned *flags;
 };
@@ -198,6 +205,7 @@ void launch_baro_mu(Ctx &c, hipStream_t s);
 void launch_baro_box_scale(Ctx &c, hipStream_t s);
 void launch_kick_drift(Ctx &c, hipStream_t s);
 void launch_step_end(Ctx &c, hipStream_t s);
+void launch_step_mark(Ctx &c, hipStream_t s);
 void launch_scatter_scalar(Ctx &c, const double *src, double *dst, hipStream_t s);
 void launch_scatter_vec3(Ctx &c, const double *sx, const double *sy, const double *sz,
                          double *dst, hipStream_t s);
@@ -206,6 +214,7 @@ void launch_get_neighbors(Ctx &c, int32_t *counts, int32_t *ids, int32_t max_col
                           hipStream_t s);
 void launch_bspline_tables(Ctx &c, const double *theta, hipStream_t s);
 void launch_fill_u32(unsigned *p, int n, unsigned v, hipStream_t s);
+void launch_clear_bits(Ctx &c, unsigned mask, hipStream_t s);  // status bits off
 // Tiled passes (md_tiled.hip).
 void tiled_prepare(Ctx &c);
 void launch_tile_nlist(Ctx &c, const unsigned *gate, hipStream_t s);
@@ -277,6 +286,8 @@ struct Ctx {
 
     // host-side state machine
     bool state_set = false, list_valid = false, density_valid = false, forces_valid = false;
+    // caller's buffers bound as the state of record (md_bind): md_step writes back
+    double *bound_pos = nullptr, *bound_vel = nullptr;
 
     // pressure (eq. 6) and Berendsen barostat (eq. 5)
     bool baro_on = false;              // md_step scales coordinates and boxes
@@ -304,6 +315,7 @@ struct Ctx {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     int graph_len = 0;
+    int graph_fused = 0;               // leading steps of the graph with the fused kick and drift
 
     // allocations to free
     std::vector<void *> allocs;        // device blocks of the context (hipMalloc)

@@ -549,7 +549,7 @@ __global__ __launch_bounds__(kBlock) void k_nlist(const unsigned *gate, int N, S
     }
     nl.count[i] = np | (ni << 16);
     nl.total[i] = total;
-    if (total > mn) atomicOr(flags, (unsigned)MD_FLAG_NLIST_OVERFLOW);
+    if (total > mn) raise_overflow(flags, MD_FLAG_NLIST_OVERFLOW, total);
 }
 
 // ---------------------------------------------------------------- passes
@@ -560,6 +560,7 @@ template <int KIND, bool MULTI, int P>
 __global__ __launch_bounds__(kBlock) void k_density(int N, State st, Boxes bx, NList nl, Pot pot,
                                                     double L1, double invL1, unsigned *flags)
 {
+    if (halted(flags)) return;
     const RowLanes<P> rl(atom_index());
     const int i = rl.i;
     if (i >= N) return;
@@ -624,6 +625,7 @@ __global__ __launch_bounds__(kBlock) void k_force(int N, State st, Boxes bx, NLi
                                                   double L1, double invL1, double kick,
                                                   Thermo th, unsigned *flags)
 {
+    if (halted(flags)) return;
     const RowLanes<P> rl(atom_index());
     const int i = rl.i;
     if (i >= N) return;
@@ -705,6 +707,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(int N, State st, Boxes bx
                                                        double dt, double thr2_1, Thermo th,
                                                        unsigned *flags)
 {
+    if (halted(flags)) return;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     bool need = false, bad = false;
     if (i < N) {
@@ -744,6 +747,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(int N, State st, Boxes bx
 // End of a replayed step: count the build if one happened, clear the request.
 __global__ void k_step_end(unsigned *flags)
 {
+    if (halted(flags)) return;
     unsigned b = flags[1] ? 1u : 0u;
     unsigned lo = flags[2] + b;
     if (lo < flags[2]) flags[4] += 1u;
@@ -752,6 +756,13 @@ __global__ void k_step_end(unsigned *flags)
     if (s == 0u) flags[5] += 1u;
     flags[3] = s;
     flags[1] = 0u;
+}
+
+// Step counter at the start of md_step.
+__global__ void k_step_mark(unsigned *flags)
+{
+    flags[kMarkWord] = flags[3];
+    flags[kMarkWord + 1] = flags[5];
 }
 
 __global__ void k_count_build(unsigned *flags)
@@ -835,6 +846,7 @@ __global__ void k_baro_mu(int B, double p0, double beta_dt_tau, double *__restri
 __global__ void k_baro_box(int B, double rc, double *__restrict__ boxd, const int *__restrict__ nc,
                            double *__restrict__ baro, unsigned *flags)
 {
+    if (halted(flags)) return;
     int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b == 0) flags[1] = 0u;
     if (b >= B) return;
@@ -861,6 +873,7 @@ __global__ __launch_bounds__(kBlock) void k_baro_scale(int N, State st, Boxes bx
                                                        const double *__restrict__ baro,
                                                        unsigned *flags)
 {
+    if (halted(flags)) return;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     bool need = false;
     if (i < N) {
@@ -1013,6 +1026,13 @@ void force_t(Ctx &c, bool energy, bool kick, hipStream_t s)
 // Acceleration unit (eV/Angstrom)/amu -> Angstrom/fs^2.
 static constexpr double kKappa = 1.602176634e-19 / 1.66053906660e-27 * 1e-10;
 
+__global__ void k_clear_bits(unsigned *flags, unsigned mask) { flags[0] &= ~mask; }
+
+void launch_clear_bits(Ctx &c, unsigned mask, hipStream_t s)
+{
+    k_clear_bits<<<1, 1, 0, s>>>(c.dev.flags, mask);
+}
+
 void launch_fill_u32(unsigned *p, int n, unsigned v, hipStream_t s)
 {
     k_fill_u32<<<grid_for(n), kBlock, 0, s>>>(p, n, v);
@@ -1130,6 +1150,8 @@ void launch_kick_drift(Ctx &c, hipStream_t s)
 }
 
 void launch_step_end(Ctx &c, hipStream_t s) { k_step_end<<<1, 1, 0, s>>>(c.dev.flags); }
+
+void launch_step_mark(Ctx &c, hipStream_t s) { k_step_mark<<<1, 1, 0, s>>>(c.dev.flags); }
 
 void launch_scatter_scalar(Ctx &c, const double *src, double *dst, hipStream_t s)
 {

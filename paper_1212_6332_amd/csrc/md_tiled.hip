@@ -211,7 +211,7 @@ __device__ __forceinline__ void stage(const Tile &t, const State &st, const Halo
             }
         }
     }
-    if (threadIdx.x == 0 && H.total > hmax) atomicOr(flags, (unsigned)MD_FLAG_TILE_OVERFLOW);
+    if (threadIdx.x == 0 && H.total > hmax) raise_overflow(flags, MD_FLAG_TILE_OVERFLOW, 0);
     __syncthreads();
 }
 
@@ -345,6 +345,7 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
     const double ncL = nc * invL;
     const bool typed = st.type != nullptr;
     unsigned bad = 0;
+    int worst = 0;  // longest row of this thread's atoms
     for (int i = t.s0 + threadIdx.x; i < t.s1; i += kT) {
         double xi = st.x[i], yi = st.y[i], zi = st.z[i];
         int cx = cell_coord(xi, ncL, nc), cy = cell_coord(yi, ncL, nc), cz = cell_coord(zi, ncL, nc);
@@ -406,8 +407,9 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
         }
         nl.count[i] = row.close(nl.idx, i, N, mn);
         nl.total[i] = row.total;
-        if (row.total > mn) bad |= MD_FLAG_NLIST_OVERFLOW;
+        worst = max(worst, row.total);
     }
+    if (worst > mn) raise_overflow(flags, MD_FLAG_NLIST_OVERFLOW, worst);
     raise_flags(flags, bad);
 }
 
@@ -604,6 +606,7 @@ __global__ __launch_bounds__(kT) void k_tile_density(int N, int G, State st, Box
                                                      unsigned *flags)
 {
     extern __shared__ __attribute__((aligned(256))) double rec[];
+    if (halted(flags)) return;
     const Pot pot = pinned(pot_arg);
     unsigned bad = 0;
     const int part = P == 1 ? 0 : (int)threadIdx.x % P;
@@ -644,6 +647,7 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
                                                    double dt, Thermo th, unsigned *flags)
 {
     extern __shared__ __attribute__((aligned(256))) double rec[];
+    if (halted(flags)) return;
     const Pot pot = pinned(pot_arg);
     // without the energy, SMTB accumulates the negated force (see pair_coef)
     constexpr double sg = ENERGY ? 1.0 : kForceSign<KIND>;

@@ -56,6 +56,7 @@ _SIGS = {
     "md_set_theta": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "md_set_state": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "md_get_state": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "md_bind": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "md_build_neighbors": ([C.c_void_p, C.c_void_p], C.c_int),
     "md_density": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "md_embed": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
@@ -273,6 +274,21 @@ class System:
         v = None if vel is None else _dev_f64(vel, self.device)
         _check(lib().md_set_state(self._h, _ptr(p), _ptr(v), _stream()), "md_set_state")
         torch.cuda.current_stream().synchronize()
+
+    @_mutates
+    def bind(self, pos, vel=None):
+        """md_bind: float64 CUDA tensors [N, 3] (contiguous) become the state
+        of record; md_step writes back into them.  bind(None) unbinds."""
+        if pos is None:
+            _check(lib().md_bind(self._h, None, None, _stream()), "md_bind")
+            self._bound = None
+            return
+        for t in (pos, vel):
+            if t is not None and not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                                      and tuple(t.shape) == (self.n_atoms, 3)):
+                raise ValueError("bound buffers: contiguous float64 CUDA tensors [N, 3]")
+        _check(lib().md_bind(self._h, _ptr(pos), _ptr(vel), _stream()), "md_bind")
+        self._bound = (pos, vel)   # keeps the memory alive while bound
 
     def get_state(self):
         p, v = self._f64(self.n_atoms, 3), self._f64(self.n_atoms, 3)
