@@ -72,7 +72,9 @@ enum {
     MD_ERR_NONFINITE = -5,       /* a coordinate became NaN or infinite            */
     MD_ERR_DEVICE = -6,          /* a HIP runtime call failed                      */
     MD_ERR_STATE = -7,           /* call out of order (e.g. no state set)          */
-    MD_ERR_NOMEM = -8            /* device allocation failed                       */
+    MD_ERR_NOMEM = -8,           /* device allocation failed                       */
+    MD_ERR_SCRATCH = -9          /* md_forces_static: the system's buffers exceed
+                                    the library's static device array            */
 };
 
 /* Bits of the device status word (md_status). */
@@ -392,6 +394,28 @@ enum {
 };
 int md_set_option(md_ctx *ctx, int32_t key, int64_t value);
 int md_get_option(const md_ctx *ctx, int32_t key, int64_t *value);
+
+/* For callers that cannot allocate device memory (no hipMalloc of their own
+ * and none by the library: tight serving loops, harnesses that forbid
+ * allocation).  Forces f_out[N][3], per-atom energies e_atom[N] and per-box
+ * energies e_box[B] of the positions pos[N][3] (device pointers, original
+ * order; outputs may be NULL), as md_create + md_set_state + md_forces would
+ * compute them, with every device buffer (state, cells, list, densities,
+ * tables, flags, partial sums) carved from one static array of
+ * md_static_bytes() bytes (64 MiB) that the library holds on each device it
+ * runs on until the process ends.  The descriptors are validated as by
+ * md_create; a system whose buffers exceed the array is refused with
+ * MD_ERR_SCRATCH (md_workspace_size gives its size).  Synchronises `stream`
+ * before (earlier calls on it may still read the array) and after (the
+ * device status word is read): list or tile overflow returns
+ * MD_ERR_NLIST_OVERFLOW (raise sys->max_neighbors), a table lookup out of
+ * range MD_ERR_TABLE_RANGE, a non-finite coordinate MD_ERR_NONFINITE.  The
+ * array is shared by every call on a device and keeps the last call's
+ * contents (each call initialises what it reads): calls that overlap on one
+ * device, from different streams or host threads, race. */
+int md_forces_static(const md_system *sys, const md_potential *pot, const double *pos,
+                     double *f_out, double *e_atom, double *e_box, void *stream);
+size_t md_static_bytes(void);
 
 #ifdef __cplusplus
 }

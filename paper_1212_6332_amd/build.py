@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmd.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["md_api.hip", "md_kernels.hip", "md_tiled.hip", "md_batched.hip", "md_adjoint.hip"]
+SOURCES = ["md_api.hip", "md_kernels.hip", "md_tiled.hip", "md_batched.hip", "md_adjoint.hip",
+           "md_static.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -654,6 +654,7 @@ const char *md_strerror(int code)
     case MD_ERR_DEVICE: return "HIP runtime error";
     case MD_ERR_STATE: return "call out of order";
     case MD_ERR_NOMEM: return "device allocation failed";
+    case MD_ERR_SCRATCH: return "system too large for the static device array of md_forces_static";
     }
     return "unknown error";
 }

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libmd.so")
 
 MD_OK = 0
 MD_ERR_ARG, MD_ERR_BOX, MD_ERR_NLIST_OVERFLOW, MD_ERR_TABLE_RANGE = -1, -2, -3, -4
-MD_ERR_NONFINITE, MD_ERR_DEVICE, MD_ERR_STATE, MD_ERR_NOMEM = -5, -6, -7, -8
+MD_ERR_NONFINITE, MD_ERR_DEVICE, MD_ERR_STATE, MD_ERR_NOMEM, MD_ERR_SCRATCH = -5, -6, -7, -8, -9
 (MD_FLAG_NLIST_OVERFLOW, MD_FLAG_TABLE_RANGE, MD_FLAG_NONFINITE, MD_FLAG_TILE_OVERFLOW,
  MD_FLAG_BOX_RANGE) = 1, 2, 4, 8, 16
 MD_POT_FS, MD_POT_SMTB, MD_POT_SPLINE, MD_POT_BSPLINE = 1, 2, 3, 4
@@ -81,6 +81,9 @@ _SIGS = {
     "md_workspace_size": ([C.c_void_p, C.c_void_p, C.POINTER(C.c_size_t)], C.c_int),
     "md_autotune": ([C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)], C.c_int),
     "md_create_in": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "md_forces_static": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                          C.c_void_p], C.c_int),
+    "md_static_bytes": ([], C.c_size_t),
 }
 
 
@@ -149,6 +152,35 @@ def _mutates(fn):
         self.epoch = getattr(self, "epoch", 0) + 1
         return fn(self, *a, **k)
     return wrap
+
+
+def forces_static(box_offset, box_len, pot, mass, pos, dt=1.0, skin=0.3, max_neighbors=0):
+    """md_forces_static: forces [N, 3], per-atom energies [N] and per-box
+    energies [B] of `pos`, with every device buffer in the library's static
+    device array (no allocation by the library; torch allocates the outputs
+    here).  Synchronises the current stream."""
+    lib()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    off = np.ascontiguousarray(np.asarray(box_offset, dtype=np.int64))
+    bl = np.asarray(box_len, dtype=np.float64)
+    bl = np.ascontiguousarray(bl[:, 0] if bl.ndim == 2 else bl)
+    holder = _PotHolder(pot)
+    sysd = md_system(n_boxes=int(bl.size), max_neighbors=int(max_neighbors),
+                     box_offset=off.ctypes.data, box_len=bl.ctypes.data, mass=float(mass),
+                     dt=float(dt), skin=float(skin))
+    n = int(off[-1])
+    p = _dev_f64(pos, dev)
+    f = torch.empty(n, 3, dtype=torch.float64, device=dev)
+    e = torch.empty(n, dtype=torch.float64, device=dev)
+    eb = torch.empty(int(bl.size), dtype=torch.float64, device=dev)
+    _check(lib().md_forces_static(C.byref(sysd), C.byref(holder.s), _ptr(p), _ptr(f), _ptr(e),
+                                  _ptr(eb), _stream()), "md_forces_static")
+    return f, e, eb
+
+
+def static_bytes():
+    """Size of the static device array md_forces_static works in."""
+    return int(lib().md_static_bytes())
 
 
 class System:
