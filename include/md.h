@@ -128,8 +128,14 @@ typedef struct {
                                 of type a contributed by an atom of type b), tab[2]
                                 T tables F^(a); the V and rho tables share one
                                 grid (lo[0] = lo[1], hi[0] = hi[1], n_tab[0] =
-                                n_tab[1]); one cutoff rc for every pair.  Atom
-                                types come from md_set_types (default: all 0).   */
+                                n_tab[1]).  Atom types come from md_set_types
+                                (default: all 0).                                 */
+    const double *rc_pair;   /* host [T*T] or NULL: the cutoff RCUT(a, b) of each
+                                pair of types (Sections 3.2-3.3), index a*T + b,
+                                symmetric, each in (0, rc]; a pair interacts
+                                while r < RCUT(a, b) and is listed while r <
+                                min(RCUT(a, b) + skin, box_len/2 - 1e-9).  NULL:
+                                rc for every pair.  Several species only.        */
 } md_potential;
 
 typedef struct {

@@ -346,7 +346,7 @@ def vv_thermo(pos, vel, L, pot: Pot, mass, dt, skin, nsteps, te, tau, maxn=256, 
 class _Alloy(C.Structure):
     _fields_ = [("ntypes", C.c_int), ("rc", C.c_double), ("V", C.c_void_p), ("rho", C.c_void_p),
                 ("F", C.c_void_p), ("nint", C.c_int * 3), ("lo", C.c_double * 3),
-                ("hi", C.c_double * 3)]
+                ("hi", C.c_double * 3), ("rcp", C.c_void_p)]
 
 
 class Alloy:
@@ -366,6 +366,9 @@ class Alloy:
             s.nint[k] = self._t[k].shape[1]
             s.lo[k] = float(pot.lo[k])
             s.hi[k] = float(pot.hi[k])
+        rcp = getattr(pot, "rc_pair", None)
+        self._rcp = None if rcp is None else np.ascontiguousarray(rcp, dtype=np.float64).ravel()
+        s.rcp = None if self._rcp is None else self._rcp.ctypes.data
         self._s = s
 
     @property
@@ -385,6 +388,9 @@ def _alloy_lib():
                                    C.c_void_p, _i32p, _f64p, dbl, dbl, i32, i32, dbl, dbl,
                                    C.c_void_p, C.c_void_p]
         L.orc_alloy_vv.restype = i32
+        L.orc_alloy_list.argtypes = [i64, _f64p, _f64p, _f64p, dbl, C.c_void_p, _i32p, dbl, i32,
+                                     _i32p, _i32p]
+        L.orc_alloy_list.restype = i32
         L._alloy_ready = True
     return L
 
@@ -411,6 +417,22 @@ def alloy_eval(pos, L, pot: Alloy, types, count=None, ids=None):
     out["E"] = float(out["e_atom"].sum())
     out["W"] = float(W)
     return out
+
+
+def alloy_list(pos, L, pot: Alloy, types, skin, maxn=256):
+    """Neighbour list of one box with the list radius taken per pair of types
+    (RCUT(a, b) + skin, clamped below L/2): (count, ids[n, maxn]), rows ascending."""
+    x, y, z = _xyz(pos)
+    n = x.size
+    count = np.zeros(n, dtype=np.int32)
+    ids = np.full((n, maxn), -1, dtype=np.int32)
+    t = np.ascontiguousarray(types, dtype=np.int32)
+    worst = _alloy_lib().orc_alloy_list(n, x, y, z, float(L), pot.ref, t, float(skin),
+                                        int(maxn), count, ids)
+    if worst > maxn:
+        raise ValueError(f"neighbour row overflow: {worst} > {maxn}")
+    ids[np.arange(maxn)[None, :] >= count[:, None]] = -1
+    return count, ids
 
 
 def alloy_vv(pos, vel, L, pot: Alloy, types, type_mass, dt, skin, nsteps, te=0.0, tau=0.0,

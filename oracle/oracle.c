@@ -1069,6 +1069,12 @@ int orc_vv_baro(int64_t n, double *x, double *y, double *z, double *vx, double *
  * which is the same function when there is one species.  The embedding
  * function is taken per type of the embedded atom.  V^(ab) = V^(ba).
  * Tables are per-interval cubics on grids shared by all tables of one kind.
+ *
+ * Cutoffs per pair of types (Sections 3.2 and 3.3: RCUT(ity, jty)): a pair
+ * of types a, b interacts while r < RCUT(a, b) (symmetric, at most rc), and
+ * the neighbour list of an atom of type a holds the atoms j of type b with
+ * r < RCUT(a, b) + skin (the list radius of the box, min(. + skin, L/2 -
+ * 1e-9), taken per pair).  Without per-pair cutoffs every pair uses rc.
  */
 typedef struct {
     int ntypes;
@@ -1078,7 +1084,13 @@ typedef struct {
     const double *F;   /* [T][nint[2]][4] */
     int nint[3];
     double lo[3], hi[3];
+    const double *rcp; /* [T*T] RCUT(a, b), index a*T + b, or NULL: rc for every pair */
 } orc_alloy;
+
+static double alloy_rc(const orc_alloy *p, int a, int b)
+{
+    return p->rcp ? p->rcp[a * p->ntypes + b] : p->rc;
+}
 
 static void alloy_fn(const orc_alloy *p, int which, int idx, double x, double *s, double *ds,
                      double *dds)
@@ -1105,7 +1117,6 @@ double orc_alloy_eval(int64_t n, const double *x, const double *y, const double 
                       double *fx, double *fy, double *fz, double *e_atom)
 {
     const int T = p->ntypes;
-    double rc2 = p->rc * p->rc;
     double *rho = malloc(sizeof(double) * (n > 0 ? n : 1));
     double *Fe = malloc(sizeof(double) * (n > 0 ? n : 1));
 #pragma omp parallel for schedule(static)
@@ -1116,7 +1127,8 @@ double orc_alloy_eval(int64_t n, const double *x, const double *y, const double 
             int64_t j = alloy_nb(ids, maxn, i, k);
             double dx, dy, dz;
             double r2 = sep2(x, y, z, i, j, L, &dx, &dy, &dz);
-            if (r2 < rc2) {
+            double rc = alloy_rc(p, type[i], type[j]);
+            if (r2 < rc * rc) {
                 double f, df, dd;
                 alloy_fn(p, 1, type[i] * T + type[j], sqrt(r2), &f, &df, &dd);
                 s += f;
@@ -1137,7 +1149,8 @@ double orc_alloy_eval(int64_t n, const double *x, const double *y, const double 
             int b = type[j];
             double dx, dy, dz;
             double r2 = sep2(x, y, z, i, j, L, &dx, &dy, &dz);
-            if (r2 < rc2) {
+            double rc = alloy_rc(p, a, b);
+            if (r2 < rc * rc) {
                 double r = sqrt(r2), dd;
                 double v, dv, fab, dfab, fba, dfba;
                 alloy_fn(p, 0, a * T + b, r, &v, &dv, &dd);
@@ -1162,6 +1175,44 @@ double orc_alloy_eval(int64_t n, const double *x, const double *y, const double 
     free(rho);
     free(Fe);
     return -0.5 * W;
+}
+
+/* Neighbour list of one box with the list radius taken per pair of types:
+ * the cell list at the largest radius (that of rc), then each row keeps, in
+ * ascending order, the j with r^2 < rl(a, b)^2, rl(a, b) = min(RCUT(a, b) +
+ * skin, L/2 - 1e-9).  Returns the longest row before the filter (> maxn:
+ * overflow). */
+int orc_alloy_list(int64_t n, const double *x, const double *y, const double *z, double L,
+                   const orc_alloy *p, const int32_t *type, double skin, int maxn, int32_t *count,
+                   int32_t *ids)
+{
+    int worst = orc_list_cells(n, x, y, z, L, orc_rlist(p->rc, skin, L), maxn, count, ids);
+    if (worst > maxn || !p->rcp) return worst;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t *row = ids + i * maxn;
+        int k = 0;
+        for (int m = 0; m < count[i]; ++m) {
+            int64_t j = row[m];
+            double rl = orc_rlist(alloy_rc(p, type[i], type[j]), skin, L);
+            double dx, dy, dz;
+            if (sep2(x, y, z, i, j, L, &dx, &dy, &dz) < rl * rl) row[k++] = (int32_t)j;
+        }
+        count[i] = k;
+    }
+    return worst;
+}
+
+static int alloy_rebuild(orc_md *s, const orc_alloy *p, const int32_t *type, int32_t *count,
+                         int32_t *ids, double *xr, double *yr, double *zr)
+{
+    orc_wrap(s->n, s->x, s->y, s->z, s->L);
+    int worst = orc_alloy_list(s->n, s->x, s->y, s->z, s->L, p, type, s->skin, s->maxn, count,
+                               ids);
+    memcpy(xr, s->x, sizeof(double) * s->n);
+    memcpy(yr, s->y, sizeof(double) * s->n);
+    memcpy(zr, s->z, sizeof(double) * s->n);
+    return worst > s->maxn ? -1 : 0;
 }
 
 static double alloy_kinetic(int64_t n, const double *vx, const double *vy, const double *vz,
@@ -1216,7 +1267,7 @@ int orc_alloy_vv(int64_t n, double *x, double *y, double *z, double *vx, double 
     }
     int on = tau > 0.0;
     int rebuilds = 0, bad = 0;
-    bad |= md_rebuild(&s, rlist, count, ids, xr, yr, zr);
+    bad |= alloy_rebuild(&s, p, type, count, ids, xr, yr, zr);
     orc_alloy_eval(n, x, y, z, L, p, type, count, ids, maxn, NULL, NULL, Fp, fx, fy, fz, e);
     if (epot) {
         epot[0] = 0.0;
@@ -1238,7 +1289,7 @@ int orc_alloy_vv(int64_t n, double *x, double *y, double *z, double *vx, double 
             if (d2 > worst) worst = d2;
         }
         if (worst > half_skin * half_skin) {
-            bad |= md_rebuild(&s, rlist, count, ids, xr, yr, zr);
+            bad |= alloy_rebuild(&s, p, type, count, ids, xr, yr, zr);
             ++rebuilds;
         }
         orc_alloy_eval(n, x, y, z, L, p, type, count, ids, maxn, NULL, NULL, Fp, fx, fy, fz, e);

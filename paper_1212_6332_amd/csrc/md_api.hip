@@ -73,6 +73,7 @@ int check_potential(const md_potential *p)
 {
     if (!p || !(p->rc > 0.0)) return MD_ERR_ARG;
     if (p->n_types < 0 || p->n_types > kMaxTypes) return MD_ERR_ARG;
+    if (p->rc_pair && p->n_types < 2) return MD_ERR_ARG;
     if (p->n_types > 1) {
         // several species: spline tables, V and rho on one grid
         if (p->kind != MD_POT_SPLINE) return MD_ERR_ARG;
@@ -81,6 +82,12 @@ int check_potential(const md_potential *p)
         if (!p->tab[0] || p->n_tab[0] < 1) return MD_ERR_ARG;
         // V^(ab) = V^(ba), coefficient for coefficient
         const int T = p->n_types;
+        if (p->rc_pair)
+            for (int a = 0; a < T; ++a)
+                for (int b = 0; b < T; ++b) {
+                    double v = p->rc_pair[a * T + b];
+                    if (!(v > 0.0 && v <= p->rc) || v != p->rc_pair[b * T + a]) return MD_ERR_ARG;
+                }
         const size_t n0 = 4 * (size_t)p->n_tab[0];
         for (int a = 0; a < T; ++a)
             for (int b = a + 1; b < T; ++b)
@@ -202,6 +209,23 @@ int upload_potential(Ctx &c, const md_potential *p, hipStream_t s, bool first)
         // sized at creation for the V grid, so a later potential with shared grids fits
         if (first) ALLOC(c.pair_tab, (size_t)(T > 1 ? 16 : 8) * T * T * q.tab[0].n);
         q.pair = shared ? c.pair_tab : nullptr;
+        // cutoffs per pair of types: RCUT^2 and (RCUT + skin)^2
+        if (first && T > 1) ALLOC(c.cut_tab, 2 * (size_t)T * T);
+        c.rc_pair.clear();
+        q.cut2 = nullptr;
+        if (p->rc_pair) {
+            c.rc_pair.assign(p->rc_pair, p->rc_pair + (size_t)T * T);
+            std::vector<double> h(2 * (size_t)T * T);
+            for (int k = 0; k < T * T; ++k) {
+                double r = p->rc_pair[k], rl = r + c.skin;
+                h[k] = r * r;
+                h[(size_t)T * T + k] = rl * rl;
+            }
+            if (!c.measure) HIP_TRY(hipStreamSynchronize(s));
+            int rh = h2d(c, c.cut_tab, h.data(), h.size() * sizeof(double));
+            if (rh != MD_OK) return rh;
+            q.cut2 = c.cut_tab;
+        }
         if (c.measure) {
             // sizes only
         } else if (p->kind == MD_POT_SPLINE) {

@@ -66,6 +66,9 @@ struct Pot {
     const double *pair;
     int nt;                            // species; with nt > 1 each Table holds nt*nt (V, rho)
                                        // or nt (F) tables back to back, table a*nt + b
+    // cutoffs per pair of types (null: rc for every pair): cut2[a nt + b] =
+    // RCUT(a, b)^2, cut2[nt nt + a nt + b] = (RCUT(a, b) + skin)^2
+    const double *cut2;
 };
 
 // Electron-gas friction of eq. (4) as the kick kernels see it: over half a
@@ -246,6 +249,8 @@ struct Ctx {
     double *tables = nullptr;          // device, 3 tables back to back
     double *theta = nullptr;           // device copy of B-spline coefficients [3K]
     double *pair_tab = nullptr;        // interleaved r-grid tables (Pot::pair)
+    double *cut_tab = nullptr;         // Pot::cut2 (several species)
+    std::vector<double> rc_pair;       // host copy of RCUT(a, b) (empty: rc for every pair)
 
     // host mirrors of the box geometry
     std::vector<int64_t> box_off;

@@ -449,7 +449,8 @@ __global__ void k_commit(const unsigned *gate, int N, State st, Build bd)
 // taken per pair.  Pairs without correction go to the front of the row, the
 // others to its back.
 __global__ __launch_bounds__(kBlock) void k_nlist(const unsigned *gate, int N, State st, Boxes bx,
-                                                  Build bd, NList nl, unsigned *flags)
+                                                  Build bd, NList nl, const double *rl2p, int nt,
+                                                  unsigned *flags)
 {
 #pragma clang fp contract(off)
     if (skip(gate)) return;
@@ -466,6 +467,12 @@ __global__ __launch_bounds__(kBlock) void k_nlist(const unsigned *gate, int N, S
     int cx = cell_coord(xi, ncL, nc), cy = cell_coord(yi, ncL, nc), cz = cell_coord(zi, ncL, nc);
     const int mn = nl.mn;
     int np = 0, ni = 0, total = 0;
+    // several species with cutoffs per pair of types: the pair's own list
+    // radius, (RCUT + skin)^2 (never above the box's)
+    const double *rl2row = rl2p ? rl2p + st.type[i] * nt : nullptr;
+    auto listed = [&](int j, double r2) {
+        return !rl2row || r2 < fmin(rl2row[st.type[j]], rl2);
+    };
     auto add = [&](int j, bool plain) {
         if (np + ni < mn) {
             if (plain)
@@ -511,7 +518,7 @@ __global__ __launch_bounds__(kBlock) void k_nlist(const unsigned *gate, int N, S
                     double dy = p2.y - yi;
                     double dz = ldpk_z(st.pk, (unsigned)j) - zi;
                     double r2 = (dx * dx + dy * dy) + dz * dz;
-                    if (r2 < rl2 && j != i) add(j, true);
+                    if (r2 < rl2 && j != i && listed(j, r2)) add(j, true);
                 }
             } else {
                 for (int j = s; j < e; ++j) {
@@ -520,7 +527,7 @@ __global__ __launch_bounds__(kBlock) void k_nlist(const unsigned *gate, int N, S
                     double dy = (p2.y - yi) + sy;
                     double dz = (ldpk_z(st.pk, (unsigned)j) - zi) + sz;
                     double r2 = (dx * dx + dy * dy) + dz * dz;
-                    if (r2 < rl2) add(j, false);
+                    if (r2 < rl2 && listed(j, r2)) add(j, false);
                 }
             }
         }
@@ -543,7 +550,8 @@ __global__ __launch_bounds__(kBlock) void k_nlist(const unsigned *gate, int N, S
                         dy = dy - ky_ * L;
                         dz = dz - kz_ * L;
                         double r2 = (dx * dx + dy * dy) + dz * dz;
-                        if (r2 < rl2) add(j, kx_ == 0.0 && ky_ == 0.0 && kz_ == 0.0);
+                        if (r2 < rl2 && listed(j, r2))
+                            add(j, kx_ == 0.0 && ky_ == 0.0 && kz_ == 0.0);
                     }
                 }
     }
@@ -572,9 +580,11 @@ __global__ __launch_bounds__(kBlock) void k_density(int N, State st, Boxes bx, N
     unsigned bad = 0;
     double rho = 0.0;
     const int ai = KIND == kTyped ? st.type[i] : 0;
+    // several species with cutoffs per pair of types: RCUT(a, b)^2
+    const double *cr = (KIND == kTyped && pot.cut2) ? pot.cut2 + ai * pot.nt : nullptr;
     auto body = [&](double dx, double dy, double dz, double, unsigned j) {
         double r2 = dev::dist2(dx, dy, dz);
-        if (r2 < pot.rc2) {
+        if (r2 < (cr ? cr[st.type[j]] : pot.rc2)) {
             if constexpr (KIND == kTyped)
                 rho += dens_typed(pot, r2 * rsqrt_nr(r2), ai, st.type[j], bad);
             else
@@ -638,9 +648,11 @@ __global__ __launch_bounds__(kBlock) void k_force(int N, State st, Boxes bx, NLi
     unsigned bad = 0;
     double ax = 0.0, ay = 0.0, az = 0.0, ep = 0.0, wv = 0.0;
     const int ai = KIND == kTyped ? st.type[i] : 0;
+    // several species with cutoffs per pair of types: RCUT(a, b)^2
+    const double *cr = (KIND == kTyped && pot.cut2) ? pot.cut2 + ai * pot.nt : nullptr;
     auto body = [&](double dx, double dy, double dz, double fpj, unsigned j) {
         double r2 = dev::dist2(dx, dy, dz);
-        if (r2 < pot.rc2) {
+        if (r2 < (cr ? cr[st.type[j]] : pot.rc2)) {
             double inv_r = rsqrt_nr(r2);
             double coef, v;
             if constexpr (KIND == kTyped) {
@@ -1083,7 +1095,9 @@ void launch_build(Ctx &c, bool gated, hipStream_t s)
     if (c.tiled)
         launch_tile_nlist(c, gate, s);
     else
-        k_nlist<<<grid_for(N, atom_block(N)), atom_block(N), 0, s>>>(gate, N, c.st, c.bx, c.bd, c.nl, c.dev.flags);
+        k_nlist<<<grid_for(N, atom_block(N)), atom_block(N), 0, s>>>(
+            gate, N, c.st, c.bx, c.bd, c.nl,
+            c.pot.cut2 ? c.pot.cut2 + (size_t)c.pot.nt * c.pot.nt : nullptr, c.pot.nt, c.dev.flags);
     if (c.baro_on)
         k_baro_rebuilt<<<grid_for(c.B), kBlock, 0, s>>>(gate, c.B, c.pot.rc, c.d_boxd, c.d_baro);
     if (!gated) k_count_build<<<1, 1, 0, s>>>(c.dev.flags);

@@ -295,11 +295,23 @@ __device__ __forceinline__ int row_entry(const double *rec, int k, bool typed)
     return e;
 }
 
+// Several species with cutoffs per pair of types: a hit within the box's
+// list radius stays only within its own pair's, rl2row[type_j] (the atom's
+// row of the (RCUT + skin)^2 table; null: no per-pair radius).
+__device__ __forceinline__ bool pair_listed(const double *rec, int k, double r2, double rl2,
+                                            const double *rl2row)
+{
+    if (!rl2row) return true;
+    int tj = reinterpret_cast<const int *>(rec + 4 * (size_t)k + 3)[0];
+    return r2 < fmin(rl2row[tj], rl2);
+}
+
 template <bool SHIFT>
 __device__ __forceinline__ void list_cell(const double *rec, int k0, int k1, int kself,
                                           double xi, double yi, double zi, double sx, double sy,
-                                          double sz, double rl2, int *__restrict__ idx, int i,
-                                          int N, int mn, bool typed, RowFill &row)
+                                          double sz, double rl2, const double *rl2row,
+                                          int *__restrict__ idx, int i, int N, int mn, bool typed,
+                                          RowFill &row)
 {
 #pragma clang fp contract(off)
     for (int c0 = k0; c0 < k1; c0 += 32) {
@@ -318,17 +330,28 @@ __device__ __forceinline__ void list_cell(const double *rec, int k0, int k1, int
         }
         unsigned d = (unsigned)(kself - c0);
         if (d < 32u) mask &= ~(1u << d);
-        row.total += __popc(mask);
         while (mask) {
             int q = __ffs(mask) - 1;
             mask &= mask - 1u;
+            if (rl2row) {
+                const double *r = rec + 4 * (c0 + q);
+                double dx = r[0] - xi, dy = r[1] - yi, dz = r[2] - zi;
+                if constexpr (SHIFT) {
+                    dx = dx + sx;
+                    dy = dy + sy;
+                    dz = dz + sz;
+                }
+                if (!pair_listed(rec, c0 + q, dist2(dx, dy, dz), rl2, rl2row)) continue;
+            }
+            ++row.total;
             row.put(idx, i, N, mn, !SHIFT, row_entry(rec, c0 + q, typed));
         }
     }
 }
 
 __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, State st, Boxes bx,
-                                                   Build bd, NList nl, int hmax, unsigned *flags)
+                                                   Build bd, NList nl, int hmax,
+                                                   const double *rl2p, int nt, unsigned *flags)
 {
 #pragma clang fp contract(off)
     if (skip(gate)) return;
@@ -349,6 +372,7 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
     for (int i = t.s0 + threadIdx.x; i < t.s1; i += kT) {
         double xi = st.x[i], yi = st.y[i], zi = st.z[i];
         int cx = cell_coord(xi, ncL, nc), cy = cell_coord(yi, ncL, nc), cz = cell_coord(zi, ncL, nc);
+        const double *rl2row = rl2p ? rl2p + st.type[i] * nt : nullptr;
         RowFill row;
         if (t.mode == kTileA) {
             int lx = cx - t.ox, ly = cy - t.oy, lz = cz - t.oz;
@@ -373,11 +397,11 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
                         int k0 = H.off[h], k1 = min(H.off[h + 1], hmax);
                         if (code == kNoShift)
                             list_cell<false>(rec, k0, k1, kself, xi, yi, zi, 0.0, 0.0, 0.0, rl2,
-                                             nl.idx, i, N, mn, typed, row);
+                                             rl2row, nl.idx, i, N, mn, typed, row);
                         else
                             list_cell<true>(rec, k0, k1, -1, xi, yi, zi, shift_of(code, 0, L),
                                             shift_of(code, 1, L), shift_of(code, 2, L), rl2,
-                                            nl.idx, i, N, mn, typed, row);
+                                            rl2row, nl.idx, i, N, mn, typed, row);
                     }
         } else {
             int kself = H.off[(cz * nc + cy) * nc + cx] + (i - H.start[(cz * nc + cy) * nc + cx]);
@@ -397,7 +421,8 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
                             dx = dx - kx_ * L;
                             dy2 = dy2 - ky_ * L;
                             dz2 = dz2 - kz_ * L;
-                            if (dist2(dx, dy2, dz2) < rl2) {
+                            double r2 = dist2(dx, dy2, dz2);
+                            if (r2 < rl2 && pair_listed(rec, k, r2, rl2, rl2row)) {
                                 row.put(nl.idx, i, N, mn, kx_ == 0.0 && ky_ == 0.0 && kz_ == 0.0,
                                         row_entry(rec, k, typed));
                                 ++row.total;
@@ -428,7 +453,7 @@ template <bool IMG, bool TYPED, bool WITH_FP, int S, class Body>
 __device__ __forceinline__ void for_row(const int *__restrict__ idx, int i, int N, int n1, int np,
                                         int part, const double *rec, double xi, double yi,
                                         double zi, double L, double invL, double rc2,
-                                        Body &&body)
+                                        const double *cut2row, Body &&body)
 {
     if (n1 <= 0) return;
     const int4 *g = reinterpret_cast<const int4 *>(idx) + i;
@@ -470,7 +495,9 @@ __device__ __forceinline__ void for_row(const int *__restrict__ idx, int i, int 
                 dz = min_image(dz, L, invL);
             }
             const double r2 = dist2(dx, dy, dz);
-            if (u < m && r2 < rc2) body(dx, dy, dz, r2, fj[u], tj[u]);
+            // several species with cutoffs per pair of types: RCUT(a, b)^2
+            const double c2 = (TYPED && cut2row) ? cut2row[tj[u]] : rc2;
+            if (u < m && r2 < c2) body(dx, dy, dz, r2, fj[u], tj[u]);
         }
     };
     // Every load is unconditional (past the end of the row it re-reads the
@@ -493,16 +520,17 @@ __device__ __forceinline__ void for_row(const int *__restrict__ idx, int i, int 
 template <bool TYPED, bool WITH_FP, int S, class Body>
 __device__ __forceinline__ void for_row_all(const NList &nl, int i, int N, int part,
                                             const double *rec, double xi, double yi, double zi,
-                                            double L, double invL, double rc2, Body &&body)
+                                            double L, double invL, double rc2,
+                                            const double *cut2row, Body &&body)
 {
     const unsigned w = (unsigned)nl.count[i];
     const int n1 = (int)(w & 0xffffu), np = (int)(w >> 16);
     if (__any(np < n1))
         for_row<true, TYPED, WITH_FP, S>(nl.idx, i, N, n1, np, part, rec, xi, yi, zi, L, invL,
-                                         rc2, body);
+                                         rc2, cut2row, body);
     else
         for_row<false, TYPED, WITH_FP, S>(nl.idx, i, N, n1, np, part, rec, xi, yi, zi, L, invL,
-                                          rc2, body);
+                                          rc2, cut2row, body);
 }
 
 // Sum over the P lanes (1 or 2, adjacent) that share the row of one atom: a
@@ -621,8 +649,9 @@ __global__ __launch_bounds__(kT) void k_tile_density(int N, int G, State st, Box
                 else
                     rho += dens<KIND>(pot, r2 * rsqrt_nr(r2), bad);
             };
+            const double *cr = (KIND == kTyped && pot.cut2) ? pot.cut2 + ai * pot.nt : nullptr;
             for_row_all<KIND == kTyped, false, P>(nl, i, N, part, rec, xi, yi, zi, t.L, t.invL,
-                                                  pot.rc2, body);
+                                                  pot.rc2, cr, body);
             rho = lanes_sum<P>(rho);
             if (P > 1 && part != 0) continue;
             double F, Fp;
@@ -708,8 +737,9 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
                     az = fma(coef, dz, az);
                 }
             };
+            const double *cr = (KIND == kTyped && pot.cut2) ? pot.cut2 + ai * pot.nt : nullptr;
             for_row_all<KIND == kTyped, true, P>(nl, i, N, part, rec, xi, yi, zi, t.L, t.invL,
-                                                 pot.rc2, body);
+                                                 pot.rc2, cr, body);
             ax = lanes_sum<P>(ax);
             ay = lanes_sum<P>(ay);
             az = lanes_sum<P>(az);
@@ -864,8 +894,9 @@ void tiled_prepare(Ctx &c)
 
 void launch_tile_nlist(Ctx &c, const unsigned *gate, hipStream_t s)
 {
+    const double *rl2p = c.pot.cut2 ? c.pot.cut2 + (size_t)c.pot.nt * c.pot.nt : nullptr;
     k_tile_nlist<<<c.ntiles, kT, c.tile_lds, s>>>(gate, (int)c.N, c.st, c.bx, c.bd, c.nl, c.hmax,
-                                                  c.dev.flags);
+                                                  rl2p, c.pot.nt, c.dev.flags);
 }
 
 template <int L>

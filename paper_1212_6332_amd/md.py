@@ -38,7 +38,7 @@ class md_potential(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n_params", C.c_int32), ("rc", C.c_double),
                 ("params", C.c_void_p), ("tab", C.c_void_p * 3), ("n_tab", C.c_int32 * 3),
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3),
-                ("n_types", C.c_int32)]
+                ("n_types", C.c_int32), ("rc_pair", C.c_void_p)]
 
 
 class md_system(C.Structure):
@@ -140,6 +140,9 @@ class _PotHolder:
         for k in range(3):
             s.lo[k] = float(pot.lo[k])
             s.hi[k] = float(pot.hi[k])
+        rcp = getattr(pot, "rc_pair", None)
+        self.rcp = None if rcp is None else np.ascontiguousarray(rcp, dtype=np.float64).ravel()
+        s.rc_pair = None if self.rcp is None else self.rcp.ctypes.data
         self.s = s
 
 

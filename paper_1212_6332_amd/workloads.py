@@ -74,6 +74,8 @@ class Potential:
     n_types: int = 1         # SPLINE with T > 1 species: tables[0] V^(ab) [T*T, n, 4],
                              # tables[1] rho^(ab) [T*T, n, 4] (density at an a atom from
                              # a b atom), tables[2] F^(a) [T, n, 4]; index a*T + b
+    rc_pair: np.ndarray = None  # [T, T] cutoff of each pair of types, symmetric, at most
+                                # rc (None: rc for every pair)
 
 
 @dataclass
@@ -205,12 +207,15 @@ def _cubic_table(x, y, bc):
     return np.ascontiguousarray(tab)
 
 
-def spline_tables_from_fs(par: np.ndarray, rho_hi: float, knots: int = 5000) -> Potential:
+def spline_tables_from_fs(par: np.ndarray, rho_hi: float, knots: int = 5000,
+                          r_hi: float = None) -> Potential:
     """Tabulated EAM: clamped cubic interpolating splines through `knots`
-    uniform samples of the FS forms (phi and f on [0, c], F on [0, rho_hi];
-    F has a natural end at 0 and a clamped end at rho_hi)."""
+    uniform samples of the FS forms (phi and f on [0, r_hi], r_hi = c unless
+    given, the forms zero beyond c; F on [0, rho_hi]; F has a natural end at 0
+    and a clamped end at rho_hi)."""
     c, d, c0, c1, c2, A = par
-    r = np.linspace(0.0, c, knots)
+    r_hi = float(c) if r_hi is None else float(r_hi)
+    r = np.linspace(0.0, r_hi, knots)
     phi = np.where(r < c, (r - c) ** 2 * (c0 + c1 * r + c2 * r * r), 0.0)
     f = np.where(r < d, (r - d) ** 2, 0.0)
     dphi0, _ = _fs_derivs(0.0, c, c0, c1, c2)
@@ -219,8 +224,8 @@ def spline_tables_from_fs(par: np.ndarray, rho_hi: float, knots: int = 5000) -> 
     rho = np.linspace(0.0, rho_hi, knots)
     F = -A * np.sqrt(rho)
     t_F = _cubic_table(rho, F, ((2, 0.0), (1, -A / (2.0 * np.sqrt(rho_hi)))))
-    return Potential(kind=POT_SPLINE, rc=float(c), tables=(t_phi, t_f, t_F),
-                     lo=(0.0, 0.0, 0.0), hi=(float(c), float(c), float(rho_hi)),
+    return Potential(kind=POT_SPLINE, rc=r_hi, tables=(t_phi, t_f, t_F),
+                     lo=(0.0, 0.0, 0.0), hi=(r_hi, r_hi, float(rho_hi)),
                      params=np.asarray(par, dtype=np.float64))
 
 
@@ -334,21 +339,24 @@ MASS_AG = 107.8682
 
 
 def alloy_tables(pars, chis, rho_hi: float, knots: int = 5000) -> Potential:
-    """Tabulated EAM for several species from per-species FS forms (cutoff c
-    shared) and density strengths chi: V^(aa) the species' own pair term,
-    V^(ab) = (V^(aa) + V^(bb))/2 for a != b, rho^(ab)(r) = chi_b f(r) (an
-    atom's density is the sum of the functions of its neighbours' species),
-    F^(a) = -(A_a / sqrt(chi_a)) sqrt(rho), so that each pure species is its
-    FS form.  Clamped cubic interpolating splines through `knots` samples, as
-    in spline_tables_from_fs."""
+    """Tabulated EAM for several species from per-species FS forms (each with
+    its own cutoff c_a = d_a) and density strengths chi: V^(aa) the species'
+    own pair term, V^(ab) = (V^(aa) + V^(bb))/2 for a != b, rho^(ab)(r) =
+    chi_b f_b(r) (an atom's density is the sum of the functions of its
+    neighbours' species), F^(a) = -(A_a / sqrt(chi_a)) sqrt(rho), so that each
+    pure species is its FS form.  Clamped cubic interpolating splines through
+    `knots` samples on the grid [0, max c_a] shared by all tables, as in
+    spline_tables_from_fs.  Cutoffs per pair of types: RCUT(a, b) =
+    max(c_a, c_b), beyond which every table of the pair vanishes."""
     T = len(pars)
-    c = float(pars[0][0])
-    assert all(float(p[0]) == c and float(p[1]) == c for p in pars)
+    cs = [float(p[0]) for p in pars]
+    assert all(float(p[1]) == float(p[0]) for p in pars)
+    c = max(cs)
     single = []
     for p, chi in zip(pars, chis):
         q = np.array(p, dtype=np.float64)
         q[5] /= np.sqrt(chi)
-        single.append(spline_tables_from_fs(q, rho_hi, knots))
+        single.append(spline_tables_from_fs(q, rho_hi, knots, r_hi=c))
     V = np.empty((T * T,) + single[0].tables[0].shape)
     R = np.empty((T * T,) + single[0].tables[1].shape)
     F = np.empty((T,) + single[0].tables[2].shape)
@@ -357,24 +365,27 @@ def alloy_tables(pars, chis, rho_hi: float, knots: int = 5000) -> Potential:
         for b in range(T):
             V[a * T + b] = 0.5 * (single[a].tables[0] + single[b].tables[0])
             R[a * T + b] = chis[b] * single[b].tables[1]
+    rcp = np.array([[max(ca, cb) for cb in cs] for ca in cs])
     return Potential(kind=POT_SPLINE, rc=c, tables=(V, R, F), lo=single[0].lo,
-                     hi=single[0].hi, n_types=T)
+                     hi=single[0].hi, n_types=T, rc_pair=None if (rcp == c).all() else rcp)
 
 
-def alloy(ncell: int = 100, frac: float = 0.3) -> Workload:
+def alloy(ncell: int = 100, frac: float = 0.3, cuts=(5.3, 5.0)) -> Workload:
     """Random substitutional binary FCC alloy: 100^3 cells (4,000,000 atoms),
     a = 3.615, a fraction `frac` of the sites species 1 (mass 107.8682), the
-    rest species 0 (mass 63.546); two seeded FS species (cutoff 5.3, each with
-    A from its own zero-pressure condition at a; density strengths 1 and 1.6)
-    tabulated on 5,000 knots with alloy_tables; sigma 0.05, 300 K.  Smaller ncell gives the same material in
-    a smaller box."""
+    rest species 0 (mass 63.546); two seeded FS species with cutoffs `cuts`
+    (5.3 and 5.0 Angstrom: species 1 reaches its third shell only), each with
+    A from its own zero-pressure condition at a, density strengths 1 and 1.6,
+    tabulated on 5,000 knots with alloy_tables (so RCUT(a, b) = 5.3 except
+    RCUT(1, 1) = 5.0); sigma 0.05, 300 K.  Smaller ncell gives the same
+    material in a smaller box."""
     ss = np.random.SeedSequence(SEED_BASE + 5)
     kids = ss.spawn(3)
-    a, cut = 3.615, 5.3
-    pars = [draw_fs(np.random.Generator(np.random.PCG64(kids[k])), "fcc", a, cut)
+    a = 3.615
+    pars = [draw_fs(np.random.Generator(np.random.PCG64(kids[k])), "fcc", a, cuts[k])
             for k in range(2)]
-    r, n = shells("fcc", a, cut)
-    rho0 = float((n * (r - cut) ** 2).sum())
+    r, n = shells("fcc", a, max(cuts))
+    rho0 = float((n * (r - max(cuts)) ** 2).sum())
     chis = (1.0, 1.6)
     pot = alloy_tables(pars, chis, rho_hi=2.0 * max(chis) * rho0)
     rng = np.random.Generator(np.random.PCG64(kids[2]))

@@ -53,7 +53,7 @@ def oracle_eval(wl):
     res["rows"] = [None] * n
     for b, s, L in O.boxes(wl):
         p = O.wrap(wl.pos[s], L)
-        cnt, ids = O.neighbor_list(p, L, O.rlist(wl.pot.rc, wl.skin, L))
+        cnt, ids = O.alloy_list(p, L, pot, wl.types[s], wl.skin)
         r = O.alloy_eval(p, L, pot, wl.types[s], cnt, ids)
         for k in ("rho", "F", "Fp", "e_atom", "f"):
             res[k][s] = r[k]
@@ -173,7 +173,7 @@ def test_set_types_checks_and_changes():
     S.close()
     L = wl.box_len[0, 0]
     p = O.wrap(wl.pos, L)
-    cnt, ids = O.neighbor_list(p, L, O.rlist(wl.pot.rc, wl.skin, L))
+    cnt, ids = O.alloy_list(p, L, O.Alloy(wl.pot), flipped, wl.skin)
     r = O.alloy_eval(p, L, O.Alloy(wl.pot), flipped, cnt, ids)
     assert rel(f.cpu().numpy(), r["f"]) <= TOL
     assert abs(float(eb[0]) - r["E"]) <= TOL * abs(r["E"])
@@ -197,7 +197,7 @@ def test_alloy_full_size_matches_oracle():
     S.close()
     assert flags == 0
     p = O.wrap(wl.pos, L)
-    cnt, ids = O.neighbor_list(p, L, O.rlist(wl.pot.rc, wl.skin, L), maxn=96)
+    cnt, ids = O.alloy_list(p, L, O.Alloy(wl.pot), wl.types, wl.skin, maxn=96)
     r = O.alloy_eval(p, L, O.Alloy(wl.pot), wl.types, cnt, ids)
     assert rel(f, r["f"]) <= TOL
     assert rel(rho, r["rho"]) <= TOL

@@ -176,3 +176,87 @@ def test_friction_per_species(orc):
             k4 = acc(u + h * k3)
             u = u + h / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
         assert np.allclose(v[i], u, rtol=1e-9, atol=0), (i, v[i], u)
+
+
+# ------------------------------------------------------------------ RCUT(a, b)
+
+def test_pair_cutoffs_dimer_by_hand(orc):
+    """Cutoffs per pair of types (Sections 3.2 and 3.3, RCUT(ity, jty)) with
+    linear tables that do not vanish at the cutoffs: a dimer of types (a, b)
+    just inside RCUT(a, b) has the hand-computed density, energy and force;
+    just outside it, the two atoms do not interact at all."""
+    g = np.array([[1.0, 0.7], [1.3, 0.9]])
+    s = np.array([-0.8, -1.1])
+    w = 0.25
+    rmax = 5.0
+    rcp = np.array([[5.0, 4.6], [4.6, 4.2]])
+    V = np.stack([linear_table(w, 0.0, rmax)] * 4)
+    R = np.stack([linear_table(g[a, b], 0.0, rmax) for a in range(2) for b in range(2)])
+    F = np.stack([linear_table(s[a], 0.0, 20.0) for a in range(2)])
+    pot = W.Potential(kind=W.POT_SPLINE, rc=rmax, tables=(V, R, F), lo=(0.0, 0.0, 0.0),
+                      hi=(rmax, rmax, 20.0), n_types=2, rc_pair=rcp)
+    u = np.array([0.6, -0.48, 0.64])           # unit vector
+    for a in range(2):
+        for b in range(2):
+            rc = rcp[a, b]
+            for r, inside in ((rc * (1 - 1e-12), True), (rc * (1 + 1e-12), False)):
+                pos = np.array([[10.0, 10.0, 10.0], 10.0 + r * u])
+                out = orc.alloy_eval(pos, 30.0, orc.Alloy(pot), np.array([a, b]))
+                rr = np.linalg.norm(pos[1] - pos[0])
+                if inside:
+                    assert np.allclose(out["rho"], [g[a, b] * rr, g[b, a] * rr], rtol=1e-12)
+                    e = [s[a] * g[a, b] * rr + 0.5 * w * rr, s[b] * g[b, a] * rr + 0.5 * w * rr]
+                    assert np.allclose(out["e_atom"], e, rtol=1e-12)
+                    k = s[a] * g[a, b] + s[b] * g[b, a] + w
+                    assert np.allclose(out["f"][0], k * u, rtol=1e-12)
+                else:
+                    assert np.all(out["rho"] == 0.0) and np.all(out["f"] == 0.0)
+                    assert np.all(out["e_atom"] == 0.0)
+
+
+def brute_pair_list(pos, L, types, rcp, skin):
+    """O(N^2) list with the list radius per pair of types, min(RCUT + skin,
+    L/2 - 1e-9), on the squared separation rounded term by term."""
+    n = pos.shape[0]
+    rows = []
+    for i in range(n):
+        d = pos - pos[i]
+        d = np.where(d > 0.5 * L, d - L, np.where(d < -0.5 * L, d + L, d))
+        r2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        rl = np.minimum(rcp[types[i], types] + skin, 0.5 * L - 1e-9)
+        ok = r2 < rl * rl
+        ok[i] = False
+        rows.append(np.nonzero(ok)[0].tolist())
+    return rows
+
+
+def test_pair_list_radius_is_per_pair(orc):
+    wl, L = small_alloy(ncell=4)
+    pos = orc.wrap(wl.pos, L)
+    rcp = wl.pot.rc_pair
+    assert rcp is not None and rcp[1, 1] < rcp[0, 0]
+    count, ids = orc.alloy_list(pos, L, orc.Alloy(wl.pot), wl.types, wl.skin)
+    ref = brute_pair_list(pos, L, wl.types, rcp, wl.skin)
+    for i in range(wl.n_atoms):
+        assert ids[i, :count[i]].tolist() == ref[i], i
+    # rows of two species-1 atoms end at 5.3 Angstrom instead of 5.6
+    one = np.nonzero(wl.types == 1)[0]
+    full = orc.neighbor_list(pos, L, orc.rlist(wl.pot.rc, wl.skin, L))
+    assert (count[one] < full[0][one]).any()
+
+
+def test_equal_pair_cutoffs_change_nothing(orc):
+    wl, L = small_alloy(ncell=3)
+    pos = orc.wrap(wl.pos, L)
+    a = orc.alloy_eval(pos, L, orc.Alloy(wl.pot), wl.types)
+    same = W.Potential(wl.pot.kind, wl.pot.rc, wl.pot.params, wl.pot.tables, wl.pot.lo,
+                       wl.pot.hi, n_types=2, rc_pair=np.full((2, 2), wl.pot.rc))
+    none = W.Potential(wl.pot.kind, wl.pot.rc, wl.pot.params, wl.pot.tables, wl.pot.lo,
+                       wl.pot.hi, n_types=2)
+    b = orc.alloy_eval(pos, L, orc.Alloy(same), wl.types)
+    c = orc.alloy_eval(pos, L, orc.Alloy(none), wl.types)
+    assert np.array_equal(b["f"], c["f"]) and np.array_equal(b["e_atom"], c["e_atom"])
+    # the workload's own RCUT(1, 1) = 5.0 cuts only where its tables vanish, up
+    # to the ripple an interpolating spline through samples of a form whose
+    # second derivative jumps at c carries past c (a few parts in 1e9 here)
+    assert np.abs(a["f"] - c["f"]).max() <= 1e-8 * np.abs(c["f"]).max()
