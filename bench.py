@@ -30,7 +30,7 @@ COUNTERS = os.path.join(ROOT, "profiles", "force_pass_fcc4m_counters.txt")
 CSRC = os.path.join(ROOT, "paper_1212_6332_amd", "csrc")
 # the sources the force kernel is compiled from
 KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("md_tiled.hip", "md_device.h", "md_internal.h")]
-FORCE_KERNEL = "k_tile_force<2, false, 1, 1>"
+FORCE_KERNEL = "k_tile_force<2, false, 2, 1>"
 
 # Algorithmic FP64 work, in lane-operations (one VALU operation on one lane):
 # every list entry costs the separation (3 differences), r^2 (1 multiply,
@@ -44,6 +44,9 @@ FORCE_KERNEL = "k_tile_force<2, false, 1, 1>"
 OPS_ENTRY = 7
 OPS_FORCE_PAIR = 7 + 2 * 15 + 6
 OPS_DENSITY_PAIR = 7 + 15 + 1
+# the step's force kernel also takes, per atom, two half kicks (6), the drift
+# (3) and the displacement test against the list's reference positions (6)
+OPS_STEP_ATOM = 15
 
 
 def force_pass_bytes(n_atoms, mean_list):
@@ -51,6 +54,14 @@ def force_pass_bytes(n_atoms, mean_list):
     per atom x,y,z (24) + F' (8) + count (4) + list (4 per entry) + force
     out (24) + velocity in/out (48); neighbour records counted once."""
     return n_atoms * (108.0 + 4.0 * mean_list)
+
+
+def step_force_bytes(n_atoms, mean_list):
+    """The force kernel as the step runs it (this step's second half kick,
+    the next step's first half kick and drift fused): the force pass's bytes
+    plus the list's reference positions in (24) and the drifted positions
+    out (24)."""
+    return n_atoms * (156.0 + 4.0 * mean_list)
 
 
 def density_pass_bytes(n_atoms, mean_list):
@@ -102,6 +113,10 @@ def list_stats(S, rc):
     return entries, pairs
 
 
+def median_pass(S, which, reps, n=5):
+    return float(sorted(S.time_pass(which, reps) for _ in range(n))[n // 2])
+
+
 def timed_steps(S, steps, warmup):
     import torch
     S.step(warmup)
@@ -151,14 +166,17 @@ def bench_main(steps, warmup, reps):
     n = wl.n_atoms
     mean_list = entries / n
     wall, gpu_s, rebuilds = timed_steps(S, steps, warmup)
-    ms = {name: S.time_pass(p, reps) for name, p in (
-        ("force", md.MD_PASS_FORCE), ("force_step", md.MD_PASS_FORCE_STEP),
+    # each pass: the median of 5 timings, each the mean of `reps` launches
+    # bracketed by HIP events on the library's stream
+    ms = {name: median_pass(S, p, reps) for name, p in (
+        ("force_step", md.MD_PASS_FORCE_STEP), ("force", md.MD_PASS_FORCE),
         ("density", md.MD_PASS_DENSITY), ("kick_drift", md.MD_PASS_KICK_DRIFT),
         ("build", md.MD_PASS_BUILD))}
-    f_ops = OPS_ENTRY * entries + OPS_FORCE_PAIR * pairs
+    f_ops = OPS_ENTRY * entries + OPS_FORCE_PAIR * pairs + OPS_STEP_ATOM * n
     d_ops = OPS_ENTRY * entries + OPS_DENSITY_PAIR * pairs
-    achieved = f_ops / (ms["force"] * 1e-3) / 1e12
-    fbytes = force_pass_bytes(n, mean_list)
+    t_f = ms["force_step"]
+    achieved = f_ops / (t_f * 1e-3) / 1e12
+    fbytes = step_force_bytes(n, mean_list)
     traffic = read_counters()
     res = {
         "value": n * steps / wall,
@@ -171,11 +189,13 @@ def bench_main(steps, warmup, reps):
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "T FP64 lane-ops/s", "frac": achieved / VALU_PEAK_TOPS,
                      "traffic": traffic,
-                     "kernel": f"{FORCE_KERNEL}: force pass with the fused half kick",
-                     "ops_per_launch": f_ops, "ms_per_launch": ms["force"],
+                     "kernel": f"{FORCE_KERNEL}: the step's force kernel (half kick, next "
+                               f"half kick and drift fused)",
+                     "ops_per_launch": f_ops, "ms_per_launch": t_f,
+                     "ms_per_launch_from": "median of 5 x mean of %d launches" % reps,
                      "hbm": {"algorithmic_bytes_per_launch": fbytes,
-                             "algorithmic_gbs": fbytes / (ms["force"] * 1e-3) / 1e9,
-                             "measured_gbs": (traffic / (ms["force"] * 1e-3) / 1e9
+                             "algorithmic_gbs": fbytes / (t_f * 1e-3) / 1e9,
+                             "measured_gbs": (traffic / (t_f * 1e-3) / 1e9
                                               if traffic else None),
                              "peak_gbs": HBM_PEAK_GBS,
                              "copy_kernel_gbs": copy_gbs()},
@@ -351,30 +371,61 @@ def bench_c2(steps=1000, warmup=20):
             "passes": ("tiled" if tiled else "per-atom") + " (md_autotune)"}
 
 
-def cpu_baseline(ncell=50, steps=120):
-    """The CPU oracle on a bounded sample: the same material (FCC SMTB, a =
-    3.615, 300 K, sigma 0.05) in a 50^3-cell box (500,000 atoms, 1/8 of the
-    full system), 120 velocity-Verlet steps (about 10-20 s on the host's
-    cores); list build and initial forces timed separately and excluded."""
-    import oracle as O
-    from paper_1212_6332_amd import workloads as W
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    wl = W.fcc4m(ncell=ncell)
+
+def _oracle_vv_rate(O, wl, steps):
+    """Seconds of setup (list build + first forces) and atom-steps/s of the
+    steps after it, for the oracle's velocity Verlet on one box."""
     L = float(wl.box_len[0, 0])
     pot = O.Pot(wl.pot)
     t = time.perf_counter()
     O.vv(wl.pos, wl.vel, L, pot, wl.mass, wl.dt, wl.skin, 0, energies=False)
     setup = time.perf_counter() - t
     t = time.perf_counter()
-    O.vv(wl.pos, wl.vel, L, pot, wl.mass, wl.dt, wl.skin, steps, energies=False)
+    _, _, _, _, reb = O.vv(wl.pos, wl.vel, L, pot, wl.mass, wl.dt, wl.skin, steps,
+                           energies=False)
     run = time.perf_counter() - t
-    per_step = max(run - setup, 1e-9) / steps
-    return {"value": wl.n_atoms / per_step, "unit": "atom-steps/s", "cores": O.threads(),
-            "kind": "oracle",
-            "sample": f"FCC SMTB {ncell}^3 cells ({wl.n_atoms} atoms, same density, potential "
-                      f"and temperature as the 4M-atom box), {steps} velocity-Verlet steps; "
-                      f"setup (list build + first forces, {setup:.2f} s) excluded",
-            "seconds": run + setup}
+    return setup, wl.n_atoms * steps / max(run - setup, 1e-9), run + setup, int(reb)
+
+
+def cpu_baseline(steps=10, ncell_1t=50, steps_1t=3):
+    """The CPU oracle, built -O3 -march=native on this host, on the headline
+    workload itself (the 4,000,000-atom FCC SMTB box, 10 velocity-Verlet
+    steps, list build and first forces timed separately and excluded) with
+    every OpenMP thread, and on a 500,000-atom box of the same material
+    (3 steps) with one thread."""
+    import tempfile
+
+    import oracle as O
+    from paper_1212_6332_amd import workloads as W
+
+    O.use_tuned(tempfile.mkdtemp(prefix="oracle_native_"))
+    threads = O.threads()
+    wl = W.fcc4m()
+    setup, rate, secs, reb = _oracle_vv_rate(O, wl, steps)
+    O.set_threads(1)
+    w1 = W.fcc4m(ncell=ncell_1t)
+    setup1, rate1, secs1, _ = _oracle_vv_rate(O, w1, steps_1t)
+    O.set_threads(threads)
+    return {"value": rate, "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"the 4,000,000-atom FCC SMTB box, {steps} velocity-Verlet steps "
+                      f"({reb} list rebuilds inside them); setup (list build + first forces, "
+                      f"{setup:.1f} s) excluded; oracle built -O3 -march=native "
+                      f"-ffp-contract=off -fopenmp",
+            "host_cpu": _cpu_model(), "seconds": secs,
+            "one_thread": {"value": rate1, "unit": "atom-steps/s", "cores": 1,
+                           "sample": f"FCC SMTB {ncell_1t}^3 cells ({w1.n_atoms} atoms, the "
+                                     f"same material), {steps_1t} steps; setup "
+                                     f"({setup1:.1f} s) excluded",
+                           "seconds": secs1}}
 
 
 def pmc_probe(reps):

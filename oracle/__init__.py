@@ -27,14 +27,35 @@ KAPPA = 1.602176634e-19 / 1.66053906660e-27 * 1e-10
 KB_EV = 8.617333262e-5
 
 
-def build(force: bool = True) -> str:
-    """Compile liboracle.so with gcc (plain C, OpenMP, no FP contraction)."""
-    if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fopenmp", "-shared",
-               "-fPIC", _SRC, "-o", _LIB + ".tmp", "-lm"]
+def build(force: bool = True, out: str = None, tuned: bool = False) -> str:
+    """Compile liboracle.so with gcc (plain C, OpenMP, no FP contraction).
+
+    tuned: -O3 -march=native for the host that runs the build (the timed
+    CPU-baseline copy, built where it runs, into `out`); otherwise -O2 for
+    any x86-64 host.  The arithmetic is the same either way: contraction
+    stays off and no fast-math option is given."""
+    dst = out or _LIB
+    if force or not os.path.exists(dst):
+        opt = ["-O3", "-march=native"] if tuned else ["-O2"]
+        cmd = ["gcc", *opt, "-std=c11", "-Wall", "-ffp-contract=off", "-fopenmp", "-shared",
+               "-fPIC", _SRC, "-o", dst + ".tmp", "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(_LIB + ".tmp", _LIB)
-    return _LIB
+        os.replace(dst + ".tmp", dst)
+    return dst
+
+
+def use_tuned(directory: str) -> str:
+    """Build the -O3 -march=native copy into `directory` and load it in place
+    of the default library (for timing the oracle on the host it runs on)."""
+    global _lib, _LIB
+    path = build(out=os.path.join(directory, "liboracle_native.so"), tuned=True)
+    _LIB, _lib = path, None
+    return path
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads used by later calls."""
+    lib().orc_set_threads(int(n))
 
 
 class _Pot(C.Structure):
@@ -77,6 +98,7 @@ def lib():
                              dbl, i32, i32, C.c_void_p, C.c_void_p]
         L.orc_vv.restype = i32
         L.orc_threads.restype = i32
+        L.orc_set_threads.argtypes = [i32]
         L.orc_adjoint.argtypes = [i64, _f64p, _f64p, _f64p, dbl, P, _i32p, _i32p, i32, _f64p,
                                   _f64p, _f64p, dbl, _f64p]
         L.orc_virial.argtypes = [i64, _f64p, _f64p, _f64p, dbl, P, _i32p, _i32p, i32, _f64p]
