@@ -327,8 +327,8 @@ int md_set_frozen(md_ctx *ctx, const uint8_t *frozen);
  *   f_i = -sum_j [F^(a)'(rho_i) rho^(ab)'(r) + F^(b)'(rho_j) rho^(ba)'(r)
  *                 + V^(ab)'(r)] (x_i - x_j) / r,
  * and every kick, the friction of md_set_thermostat and the kinetic energy
- * take the mass of the atom's species.  Several-species contexts step
- * several boxes with the merged-box kernels (MD_OPT_BATCHED is 0). */
+ * take the mass of the atom's species (in the merged-box kernels and in the
+ * persistent multi-box stepper alike). */
 int md_set_types(md_ctx *ctx, const int32_t *types, const double *type_mass);
 
 /* Electron-gas thermostat, eq. (4) of Section 2, applied by md_step: each
@@ -348,9 +348,15 @@ int md_set_thermostat(md_ctx *ctx, double t_e, double tau_t);
 int md_get_box(md_ctx *ctx, double *box_len, void *stream);
 
 /* Autotuner.  Contexts whose md_step runs the persistent multi-box stepper
- * (several boxes): times the workgroup sizes 256, 512 and 1024 on the
- * context's own boxes (20 steps each after a warm-up), keeps the fastest as
- * MD_OPT_BATCH_BLOCK and writes it to *block (host).  Other contexts that
+ * (several boxes): times the block shapes of the stepper on the context's own
+ * boxes (20 steps each after a warm-up): workgroup sizes 256, 512 and 1024,
+ * each with one box per workgroup and with packs of small boxes of up to one
+ * and two workgroups' worth of atoms, in index and in cell visiting order.
+ * Keeps the fastest as MD_OPT_BATCH_BLOCK, MD_OPT_BATCH_PACK and
+ * MD_OPT_BATCH_ORDER and writes the workgroup size to *block (host).  The
+ * cell grid of each box is not tuned: it is the grid of cells at least the
+ * list radius wide, because each atom's neighbour order (and so the rounding
+ * of its sums) follows the grid, and tuning must not change results.  Other contexts that
  * can be tiled (one box, or boxes stepped by the merged-box kernels; not
  * with the barostat): times the passes of a step (density, force with the
  * fused kicks, a tenth of a list build) with the tiled and with the
@@ -394,9 +400,18 @@ enum {
                                contexts all but the last one or two steps of a
                                graph fuse the next kick and drift into the force
                                pass, with bitwise the same trajectory)            */
-    MD_OPT_TILED = 5        /* 1: list build, density and force stage each tile's
+    MD_OPT_TILED = 5,       /* 1: list build, density and force stage each tile's
                                neighbour records in LDS (default where the tiles
                                fit); 0: per-atom kernels gathering from HBM       */
+    MD_OPT_BATCH_PACK = 6,  /* persistent kernel: a workgroup takes one box (0, the
+                               default) or a pack of consecutive boxes of the
+                               size-sorted order holding at most this many atoms
+                               together (a larger box still goes alone); 0..65535 */
+    MD_OPT_BATCH_ORDER = 7  /* persistent kernel: threads take a pack's atoms in
+                               index order (0, default) or in the cell order of
+                               the last binning (1).  Neither this nor
+                               MD_OPT_BATCH_PACK or MD_OPT_BATCH_BLOCK changes
+                               any result: each atom's arithmetic is the same  */
 };
 int md_set_option(md_ctx *ctx, int32_t key, int64_t value);
 int md_get_option(const md_ctx *ctx, int32_t key, int64_t *value);

@@ -1191,17 +1191,27 @@ int md_autotune(md_ctx *h, void *stream, int32_t *block)
         c.forces_valid = c.list_valid = c.density_valid = false;
         return MD_OK;
     };
-    const int candidates[3] = {256, 512, 1024};
+    // block shapes: workgroup size x pack capacity (one box, one or two
+    // workgroups' worth of atoms) x visiting order
+    struct Shape {
+        int block, cap, order;
+    };
+    std::vector<Shape> shapes;
+    for (int T : {256, 512, 1024})
+        for (int cap : {0, T, 2 * T})
+            for (int order : {0, 1}) shapes.push_back({T, cap, order});
     const int reps = 20;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     float best_ms = 0.0f;
-    int best = c.batch_block;
+    Shape best{c.batch_block, c.batch_cap, c.batch_cell_order};
     int rc = MD_OK;
-    for (int T : candidates) {
+    for (const Shape &sh : shapes) {
         if ((rc = restore()) != MD_OK) break;
-        c.batch_block = T;
+        c.batch_block = sh.block;
+        c.batch_cap = sh.cap;
+        c.batch_cell_order = sh.order;
         if ((rc = launch_batched_steps(c, 5, s)) != MD_OK) break;  // lists, forces, first steps
         if (hipEventRecord(e0, s) != hipSuccess) { rc = MD_ERR_DEVICE; break; }
         if ((rc = launch_batched_steps(c, reps, s)) != MD_OK) break;
@@ -1213,15 +1223,17 @@ int md_autotune(md_ctx *h, void *stream, int32_t *block)
         (void)hipEventElapsedTime(&ms, e0, e1);
         if (best_ms == 0.0f || ms < best_ms) {
             best_ms = ms;
-            best = T;
+            best = sh;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    c.batch_block = best;
+    c.batch_block = best.block;
+    c.batch_cap = best.cap;
+    c.batch_cell_order = best.order;
     int rr = restore();
     HIP_TRY(hipStreamSynchronize(s));
-    *block = best;
+    *block = best.block;
     return rc != MD_OK ? rc : rr;
 }
 
@@ -1324,8 +1336,10 @@ int md_set_types(md_ctx *h, const int32_t *types, const double *type_mass)
         launch_refresh_types(c, nullptr);
         HIP_TRY(hipDeviceSynchronize());
     }
-    // rows carry the neighbours' species; energies and forces change
+    // rows carry the neighbours' species; energies and forces change (and
+    // with cutoffs per pair of types, the rows themselves)
     c.list_valid = c.density_valid = c.forces_valid = false;
+    batched_invalidate(c);
     c.baro_mu_valid = false;
     graph_reset(c);
     return MD_OK;
@@ -1519,6 +1533,14 @@ int md_set_option(md_ctx *h, int32_t key, int64_t v)
         if (v && !c.tile_feasible) return MD_ERR_ARG;
         set_tiled(c, v != 0);
         return MD_OK;
+    case MD_OPT_BATCH_PACK:
+        if (v < 0 || v > 65535) return MD_ERR_ARG;
+        c.batch_cap = (int)v;
+        return MD_OK;
+    case MD_OPT_BATCH_ORDER:
+        if (v != 0 && v != 1) return MD_ERR_ARG;
+        c.batch_cell_order = (int)v;
+        return MD_OK;
     }
     return MD_ERR_ARG;
 }
@@ -1533,6 +1555,8 @@ int md_get_option(const md_ctx *h, int32_t key, int64_t *v)
     case MD_OPT_USE_GRAPH: *v = c.use_graph; return MD_OK;
     case MD_OPT_GRAPH_STEPS: *v = c.graph_steps; return MD_OK;
     case MD_OPT_TILED: *v = c.tiled; return MD_OK;
+    case MD_OPT_BATCH_PACK: *v = c.batch_cap; return MD_OK;
+    case MD_OPT_BATCH_ORDER: *v = c.batch_cell_order; return MD_OK;
     }
     return MD_ERR_ARG;
 }

@@ -284,6 +284,8 @@ struct Ctx {
 
     // batched persistent kernel (form 2)
     int batch_block = 256;
+    int batch_cap = 0;                 // atoms per pack of boxes (0: one box per workgroup)
+    int batch_cell_order = 0;          // threads visit atoms in cell order
     bool batched = false;
     bool batch_feasible = false;
     int64_t host_steps = 0;            // steps taken by the persistent kernel

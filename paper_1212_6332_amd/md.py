@@ -24,6 +24,7 @@ MD_ERR_NONFINITE, MD_ERR_DEVICE, MD_ERR_STATE, MD_ERR_NOMEM, MD_ERR_SCRATCH = -5
  MD_FLAG_BOX_RANGE) = 1, 2, 4, 8, 16
 MD_POT_FS, MD_POT_SMTB, MD_POT_SPLINE, MD_POT_BSPLINE = 1, 2, 3, 4
 MD_OPT_BATCHED, MD_OPT_BATCH_BLOCK, MD_OPT_USE_GRAPH, MD_OPT_GRAPH_STEPS, MD_OPT_TILED = 1, 2, 3, 4, 5
+MD_OPT_BATCH_PACK, MD_OPT_BATCH_ORDER = 6, 7
 (MD_PASS_BUILD, MD_PASS_DENSITY, MD_PASS_FORCE, MD_PASS_KICK_DRIFT, MD_PASS_FORCE_STEP,
  MD_PASS_PRESSURE) = 0, 1, 2, 3, 4, 5
 
@@ -256,8 +257,9 @@ class System:
 
     @_mutates
     def autotune(self):
-        """Pick the fastest workgroup size of the persistent multi-box stepper
-        (md_autotune); returns it."""
+        """md_autotune: the fastest block shape of the persistent multi-box
+        stepper (workgroup size, box packing, visiting order), or tiled versus
+        per-atom passes elsewhere; returns the stepper's workgroup size."""
         b = C.c_int32()
         _check(lib().md_autotune(self._h, _stream(), C.byref(b)), "md_autotune")
         return int(b.value)

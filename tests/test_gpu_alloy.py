@@ -151,8 +151,8 @@ def test_alloy_graph_equals_direct_launches():
 
 def test_set_types_checks_and_changes():
     """Types out of range, non-positive masses, a single-species context and
-    the persistent multi-box stepper are refused; new types after the state
-    is set take effect at once (rows carry the neighbours' species)."""
+    the persistent multi-box stepper on one box are refused; new types after
+    the state is set take effect at once (rows carry the neighbours' species)."""
     wl = W.alloy(ncell=12)
     S = md.System.from_workload(wl)
     assert S.get_option(md.MD_OPT_BATCHED) == 0
