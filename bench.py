@@ -26,7 +26,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0                    # MI355X HBM3E
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # FP64 VALU lane-operations: 256 CUs x 64 lanes x 2.4 GHz
 METRIC = "atom-steps/s FP64 EAM step at 4M atoms; HBM GB/s fraction; batched box-steps/s"
-COUNTERS = os.path.join(ROOT, "profiles", "force_pass_fcc4m_counters.txt")
+COUNTERS = os.path.join(ROOT, "profiles", "step_force_fcc4m_counters.txt")
 CSRC = os.path.join(ROOT, "paper_1212_6332_amd", "csrc")
 # the sources the force kernel is compiled from
 KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("md_tiled.hip", "md_device.h", "md_internal.h")]
