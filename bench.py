@@ -33,15 +33,17 @@ KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("md_tiled.hip", "md_device.h", "m
 FORCE_KERNEL = "k_tile_force<2, false, 2, 1>"
 
 # Algorithmic FP64 work, in lane-operations (one VALU operation on one lane):
-# every list entry costs the separation (3 differences), r^2 (1 multiply,
-# 2 fma) and the cutoff compare; every pair inside the cutoff costs 1/r and r
+# every list entry costs the separation (3 differences), r^2 (3 multiplies
+# and 2 additions, each rounded on its own, so that every kernel and the
+# oracle decide a pair at the cutoff alike) and the cutoff compare; every
+# pair inside the cutoff costs 1/r and r
 # (estimate, one third-order correction, one multiply: 7) and, per
 # exponential 2^t, its argument (1), reduction (3), degree-10 polynomial (10,
 # the lowest degree within a few units in the last place) and scaling (1);
 # the force pass takes two exponentials and assembles (F'_i + F'_j) rho' + V'
 # and the three force components (6), the density pass takes one exponential
 # and one accumulation.
-OPS_ENTRY = 7
+OPS_ENTRY = 9
 OPS_FORCE_PAIR = 7 + 2 * 15 + 6
 OPS_DENSITY_PAIR = 7 + 15 + 1
 # the step's force kernel also takes, per atom, two half kicks (6), the drift
