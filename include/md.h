@@ -153,9 +153,13 @@ typedef struct {
                                    half of (list radius - rc) since the last build    */
 } md_system;
 
-/* Create a context on the current device.  Validates the descriptors
- * (MD_ERR_ARG), requires box_len[b] > 2 rc for every box (MD_ERR_BOX),
- * uploads the potential, and allocates all device memory of the context. */
+/* Create a context on the current device (Section 3.1: the device-resident
+ * arrays of positions, velocities, forces, densities, list counts and the
+ * list, with the type and state arrays when used, allocated once; Section
+ * 3.3: the potential's tables prepared on the host once and uploaded).
+ * Validates the descriptors (MD_ERR_ARG), requires box_len[b] > 2 rc for
+ * every box (MD_ERR_BOX), uploads the potential, and allocates all device
+ * memory of the context. */
 int md_create(const md_system *sys, const md_potential *pot, md_ctx **out);
 
 /* Device bytes a context for these descriptors holds (*bytes): the size of
@@ -221,11 +225,13 @@ int md_get_state(md_ctx *ctx, double *pos, double *vel, void *stream);
  * when a row did not fit. */
 int md_build_neighbors(md_ctx *ctx, void *stream);
 
-/* Density pass (Fig. 5) with the embedding fused: rho_i = sum of rho(r_ij)
- * over listed j with r_ij < rc.  rho_out[N] may be NULL. */
+/* Density pass (Fig. 5, eq. 3) with the embedding fused: rho_i = sum of
+ * rho(r_ij) over listed j with r_ij < rc (r_ij < RCUT(a, b) with cutoffs per
+ * pair of types).  rho_out[N] may be NULL. */
 int md_density(md_ctx *ctx, double *rho_out, void *stream);
 
-/* Embedding pass: F(rho_i) and F'(rho_i) of the last density pass.
+/* Embedding pass (eq. 1: F(rho); Section 4: F = -sqrt(rho) for the
+ * tight-binding form): F(rho_i) and F'(rho_i) of the last density pass.
  * Either output [N] may be NULL. */
 int md_embed(md_ctx *ctx, double *F_out, double *Fp_out, void *stream);
 
@@ -239,7 +245,9 @@ int md_embed(md_ctx *ctx, double *F_out, double *Fp_out, void *stream);
  * evaluation). */
 int md_forces(md_ctx *ctx, double *f_out, double *e_atom, double *e_box, void *stream);
 
-/* nsteps of velocity Verlet: half kick, drift, conditional list rebuild
+/* The time integration of Section 3.3, with velocity Verlet in place of the
+ * paper's predictor-corrector and a displacement test in place of its fixed
+ * list refresh: nsteps of half kick, drift, conditional list rebuild
  * decided on the device, density + embedding, force, half kick.  Brings the
  * list and forces up to date first if needed (nsteps = 0 does only that,
  * with the kernels that would take the steps).  The step sequence is
@@ -251,7 +259,8 @@ int md_forces(md_ctx *ctx, double *f_out, double *e_atom, double *e_box, void *s
  * those conditions (the state is then the one the kernels reached). */
 int md_step(md_ctx *ctx, int nsteps, void *stream);
 
-/* Kinetic energy per box, ke_box[B] = sum m v^2 / 2 (eV). */
+/* Kinetic energy per box, ke_box[B] = sum m v^2 / 2 (eV): the kinetic part
+ * of the pressure of eq. (6). */
 int md_kinetic(md_ctx *ctx, double *ke_box, void *stream);
 
 /* Neighbour rows in original indices: counts[N] and ids[N][max_cols]
