@@ -477,14 +477,29 @@ def cpu_baseline(steps=10, ncell_1t=50, steps_1t=3):
                            "seconds": secs1}}
 
 
-def pmc_probe(reps):
+def pmc_probe(reps, workload="fcc4m"):
     """Short run for hardware-counter collection: force (plain and as run in
-    the step), density and list-build passes of the 4M-atom workload, then one
-    plain 2 GiB device copy used to scale the counters."""
+    the step), density and list-build passes of the 4M-atom workload (or of
+    the 4M-atom alloy), or 100 steps of the persistent multi-box stepper on
+    batch2048 in its default shape; then one plain 2 GiB device copy used to
+    scale the counters."""
     import torch
     from paper_1212_6332_amd import md, workloads as W
 
-    wl = W.fcc4m()
+    if workload == "batch2048":
+        wl = W.batch2048()
+        S = md.System.from_workload(wl)
+        S.set_state(wl.pos, wl.vel)
+        S.step(100)
+        torch.cuda.synchronize()
+        S.close()
+        src = torch.ones(2 ** 28, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 8}))
+        return
+    wl = W.alloy() if workload == "alloy" else W.fcc4m()
     S = md.System.from_workload(wl)
     S.set_state(wl.pos, wl.vel)
     S.forces(energy=False)
@@ -513,6 +528,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-probe", action="store_true", help="counter-collection run only")
+    ap.add_argument("--pmc-workload", default="fcc4m", choices=["fcc4m", "alloy", "batch2048"],
+                    help="workload of the counter-collection run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the whole box fits in one MI355X's HBM); "
@@ -522,7 +539,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.pmc_probe:
-        pmc_probe(args.reps)
+        pmc_probe(args.reps, args.pmc_workload)
         return
     t0 = time.perf_counter()
     r = bench_main(args.steps, args.warmup, args.reps)

@@ -140,6 +140,12 @@ __host__ __device__ inline size_t pack_lds_bytes(int smax, int cmax)
     return (b + 15) & ~(size_t)15;
 }
 
+// The kernel's static LDS (the pack's box descriptors, prefix tables and
+// rebuild flags), with a margin for alignment: the dynamic part may take
+// what the device allows per workgroup minus this.
+constexpr size_t kStaticLds = sizeof(BBox) * kPackBoxes + sizeof(int) * 2 * (kPackBoxes + 1) +
+                              sizeof(unsigned) * (2 * kPackBoxes + 2) + sizeof(int) + 256;
+
 template <int KIND, int T>
 __global__ __launch_bounds__(T) void k_batched(BArgs a)
 {
@@ -582,7 +588,7 @@ int batched_prepare(Ctx &c)
     }
     // 16-bit local indices and cells, 8-bit species; LDS must hold one box
     bool feasible = nmax <= 65535 && cmax < 65535 && c.ntypes <= 256 &&
-                    pack_lds_bytes(nmax, cmax + 1) <= (size_t)max_lds;
+                    pack_lds_bytes(nmax, cmax + 1) + kStaticLds <= (size_t)max_lds;
     c.batch_feasible = feasible;
     c.batched = b->prepared ? (c.batched && feasible) : feasible;
     b->prepared = true;
@@ -671,7 +677,8 @@ static int batched_configure(Ctx &c, Batch &b, hipStream_t s)
         return MD_ERR_DEVICE;
     if (b.packed_cap != c.batch_cap) {
         std::vector<BPack> packs;
-        form_packs(b.hb, b.horder, c.batch_cap, (size_t)max_lds, packs, b.smax, b.cmax);
+        form_packs(b.hb, b.horder, c.batch_cap, (size_t)max_lds - kStaticLds, packs, b.smax,
+                   b.cmax);
         b.npacks = (int)packs.size();
         b.lds = pack_lds_bytes(b.smax, b.cmax);
         // the previous launches on this stream may still read the packs

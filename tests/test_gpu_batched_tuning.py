@@ -87,6 +87,54 @@ def test_block_shapes_change_nothing(name):
         assert np.array_equal(p, ref[0]) and np.array_equal(v, ref[1]), sh
 
 
+def test_shapes_with_frozen_atoms_and_friction():
+    """Packs, visiting order and workgroup size with a frozen slab and the
+    electron-gas friction of eq. (4): bitwise the default shape, frozen atoms
+    in place."""
+    wl = alloy_boxes(True)
+    L = np.repeat(wl.box_len[:, 0], np.diff(wl.box_offset))
+    frozen = (np.mod(wl.pos[:, 2], L) < 0.25 * L).astype(np.uint8)
+
+    def go(shape):
+        S = md.System.from_workload(wl)
+        S.set_option(md.MD_OPT_BATCH_BLOCK, shape[0])
+        S.set_option(md.MD_OPT_BATCH_PACK, shape[1])
+        S.set_option(md.MD_OPT_BATCH_ORDER, shape[2])
+        S.set_frozen(frozen)
+        S.set_state(wl.pos, wl.vel)
+        S.set_thermostat(900.0, 20.0)
+        S.step(60)
+        p, v = (t.cpu().numpy() for t in S.get_state())
+        assert S.status()[0] == 0
+        S.close()
+        return p, v
+
+    p0, v0 = go(SHAPES[0])
+    f = frozen.astype(bool)
+    assert not v0[f].any()
+    for b, s, L in O.boxes(wl):       # frozen atoms stay where the first build wrapped them
+        assert np.array_equal(p0[s][f[s]], O.wrap(wl.pos[s], L)[f[s]]), b
+    for sh in SHAPES[1:4]:
+        p, v = go(sh)
+        assert np.array_equal(p, p0) and np.array_equal(v, v0), sh
+
+
+def test_pack_option_checks():
+    wl = W.batch2048(n_boxes=8)
+    S = md.System.from_workload(wl)
+    for key, bad in ((md.MD_OPT_BATCH_PACK, -1), (md.MD_OPT_BATCH_PACK, 65536),
+                     (md.MD_OPT_BATCH_ORDER, 2)):
+        with pytest.raises(md.MDError):
+            S.set_option(key, bad)
+    S.set_option(md.MD_OPT_BATCH_PACK, 100000 // 2)   # larger than every pack: all boxes in few packs
+    S.set_state(wl.pos, wl.vel)
+    S.step(3)
+    p = S.get_state()[0].cpu().numpy()
+    S.close()
+    q = run(wl, 3, SHAPES[0])[0]
+    assert np.array_equal(p, q)
+
+
 def test_autotune_picks_a_shape_and_changes_nothing():
     wl = W.batch2048(n_boxes=64)
     p, v, st, picked = run(wl, 40, tune=True)
