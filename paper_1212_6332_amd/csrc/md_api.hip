@@ -130,7 +130,7 @@ int upload_potential(Ctx &c, const md_potential *p, hipStream_t s, bool first)
     if (p->kind == MD_POT_FS) {
         q.kind = MD_POT_FS;
         q.nt = 1;
-        q.pair = nullptr;
+        q.pair = q.dpair = nullptr;
         q.c = p->params[0];
         q.d = p->params[1];
         q.c0 = p->params[2];
@@ -140,7 +140,7 @@ int upload_potential(Ctx &c, const md_potential *p, hipStream_t s, bool first)
     } else if (p->kind == MD_POT_SMTB) {
         q.kind = MD_POT_SMTB;
         q.nt = 1;
-        q.pair = nullptr;
+        q.pair = q.dpair = nullptr;
         double A = p->params[0], xi = p->params[1], pp = p->params[2], qq = p->params[3],
                r0 = p->params[4];
         if (!(A > 0.0 && xi > 0.0 && r0 > 0.0 && pp > 0.0 && qq > 0.0)) return MD_ERR_ARG;
@@ -207,8 +207,12 @@ int upload_potential(Ctx &c, const md_potential *p, hipStream_t s, bool first)
         // the force pass reads V and rho of one interval together when they share a grid
         const bool shared = q.tab[0].n == q.tab[1].n && p->lo[0] == p->lo[1] && p->hi[0] == p->hi[1];
         // sized at creation for the V grid, so a later potential with shared grids fits
-        if (first) ALLOC(c.pair_tab, (size_t)(T > 1 ? 16 : 8) * T * T * q.tab[0].n);
+        if (first) {
+            ALLOC(c.pair_tab, (size_t)(T > 1 ? 16 : 8) * T * T * q.tab[0].n);
+            ALLOC(c.dpair_tab, (size_t)(T > 1 ? 10 : 6) * T * T * q.tab[0].n);
+        }
         q.pair = shared ? c.pair_tab : nullptr;
+        q.dpair = shared ? c.dpair_tab : nullptr;
         // cutoffs per pair of types: RCUT^2 and (RCUT + skin)^2
         if (first && T > 1) ALLOC(c.cut_tab, 2 * (size_t)T * T);
         c.rc_pair.clear();

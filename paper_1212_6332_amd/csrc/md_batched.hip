@@ -398,13 +398,13 @@ __global__ __launch_bounds__(T) void k_batched(BArgs a)
                     if constexpr (TYPED) {
                         const int tj = ty[base + j];
                         if (!(r2 < (cr ? cr[tj] : pot.rc2))) return;
-                        double inv_r = rsqrt_nr(r2), dab, dba, v, dv;
-                        pair_terms_typed(pot, r2 * inv_r, ai, tj, dab, dba, v, dv, bad);
+                        double inv_r = rsqrt_nr(r2), dab, dba, dv;
+                        pair_derivs_typed(pot, r2 * inv_r, ai, tj, dab, dba, dv, bad);
                         coef = fma(fpi, dab, fma(FP[base + j], dba, dv)) * inv_r;
                     } else {
                         if (!(r2 < pot.rc2)) return;
-                        double inv_r = rsqrt_nr(r2), dfr, v, dv;
-                        pair_terms<KIND>(pot, r2 * inv_r, dfr, v, dv, bad);
+                        double inv_r = rsqrt_nr(r2), dfr, dv;
+                        pair_derivs<KIND>(pot, r2 * inv_r, dfr, dv, bad);
                         coef = fma(fpi + FP[base + j], dfr, dv) * inv_r;
                     }
                     ax = fma(coef, dx, ax);

@@ -64,6 +64,11 @@ struct Pot {
     // V and rho grids differ): one species [V | rho] (8 doubles), several
     // [V^(ab) | rho^(ab) | rho^(ba) | 0] (16 doubles, index (a nt + b) n + m)
     const double *pair;
+    // the same intervals with only what the derivatives need (forces without
+    // energies): one species [V_b V_c V_d | rho_b rho_c rho_d] (6 doubles,
+    // 48 bytes), several [V^(ab) | rho^(ab) | rho^(ba)] b, c, d and one zero
+    // (10 doubles, 80 bytes); null when pair is
+    const double *dpair;
     int nt;                            // species; with nt > 1 each Table holds nt*nt (V, rho)
                                        // or nt (F) tables back to back, table a*nt + b
     // cutoffs per pair of types (null: rc for every pair): cut2[a nt + b] =
@@ -249,6 +254,7 @@ struct Ctx {
     double *tables = nullptr;          // device, 3 tables back to back
     double *theta = nullptr;           // device copy of B-spline coefficients [3K]
     double *pair_tab = nullptr;        // interleaved r-grid tables (Pot::pair)
+    double *dpair_tab = nullptr;       // their derivative coefficients (Pot::dpair)
     double *cut_tab = nullptr;         // Pot::cut2 (several species)
     std::vector<double> rc_pair;       // host copy of RCUT(a, b) (empty: rc for every pair)
 

@@ -658,12 +658,18 @@ __global__ __launch_bounds__(kBlock) void k_force(int N, State st, Boxes bx, NLi
             if constexpr (KIND == kTyped) {
                 // [F'_i rho^(ab)'(r) + F'_j rho^(ba)'(r) + V^(ab)'(r)] / r
                 double dab, dba, dv;
-                pair_terms_typed(pot, r2 * inv_r, ai, st.type[j], dab, dba, v, dv, bad);
+                if constexpr (ENERGY)
+                    pair_terms_typed(pot, r2 * inv_r, ai, st.type[j], dab, dba, v, dv, bad);
+                else
+                    pair_derivs_typed(pot, r2 * inv_r, ai, st.type[j], dab, dba, dv, bad);
                 coef = fma(fpi, dab, fma(fpj, dba, dv)) * inv_r;
             } else {
                 // [(F'_i + F'_j) rho'(r) + V'(r)] / r
                 double dfr, dv;
-                pair_terms<KIND>(pot, r2 * inv_r, dfr, v, dv, bad);
+                if constexpr (ENERGY)
+                    pair_terms<KIND>(pot, r2 * inv_r, dfr, v, dv, bad);
+                else
+                    pair_derivs<KIND>(pot, r2 * inv_r, dfr, dv, bad);
                 coef = fma(fpi + fpj, dfr, dv) * inv_r;
             }
             // f_i += coef (x_j - x_i)
@@ -963,29 +969,40 @@ __global__ void k_bspline_tables(int K, const double *__restrict__ theta, double
 // Interleaved r-grid tables of the force pass (Pot::pair): thread g fills
 // interval m of table pair ab = g / n.
 __global__ void k_pair_tables(int n, int T, const double *__restrict__ V,
-                              const double *__restrict__ R, double *__restrict__ out)
+                              const double *__restrict__ R, double *__restrict__ out,
+                              double *__restrict__ dout)
 {
     int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= T * T * n) return;
     int ab = g / n, m = g % n;
     const double *v = V + 4 * (size_t)g, *rab = R + 4 * (size_t)g;
     if (T == 1) {
-        double *o = out + 8 * (size_t)m;
+        double *o = out + 8 * (size_t)m, *d = dout + 6 * (size_t)m;
         for (int k = 0; k < 4; ++k) {
             o[k] = v[k];
             o[4 + k] = rab[k];
+        }
+        for (int k = 1; k < 4; ++k) {
+            d[k - 1] = v[k];
+            d[2 + k] = rab[k];
         }
         return;
     }
     int a = ab / T, b = ab % T;
     const double *rba = R + 4 * ((size_t)(b * T + a) * n + m);
-    double *o = out + 16 * (size_t)g;
+    double *o = out + 16 * (size_t)g, *d = dout + 10 * (size_t)g;
     for (int k = 0; k < 4; ++k) {
         o[k] = v[k];
         o[4 + k] = rab[k];
         o[8 + k] = rba[k];
         o[12 + k] = 0.0;
     }
+    for (int k = 1; k < 4; ++k) {
+        d[k - 1] = v[k];
+        d[2 + k] = rab[k];
+        d[5 + k] = rba[k];
+    }
+    d[9] = 0.0;
 }
 
 inline int grid_for(int64_t n, int block = kBlock) { return (int)((n + block - 1) / block); }
@@ -1229,7 +1246,8 @@ void launch_pair_tables(Ctx &c, hipStream_t s)
     if (!c.pot.pair) return;
     const int n = c.pot.tab[0].n, T = c.pot.nt;
     k_pair_tables<<<grid_for((int64_t)T * T * n), kBlock, 0, s>>>(n, T, c.pot.tab[0].c,
-                                                                 c.pot.tab[1].c, c.pair_tab);
+                                                                 c.pot.tab[1].c, c.pair_tab,
+                                                                 c.dpair_tab);
 }
 
 }  // namespace mdk

@@ -717,7 +717,10 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
                     double coef;
                     if constexpr (KIND == kTyped) {
                         double dab, dba, v, dv;
-                        pair_terms_typed(pot, r2 * inv_r, ai, tj, dab, dba, v, dv, bad);
+                        if constexpr (ENERGY)
+                            pair_terms_typed(pot, r2 * inv_r, ai, tj, dab, dba, v, dv, bad);
+                        else
+                            pair_derivs_typed(pot, r2 * inv_r, ai, tj, dab, dba, dv, bad);
                         coef = fma(fpi, dab, fma(fpj, dba, dv)) * inv_r;
                         if constexpr (ENERGY) {
                             ep += v;
