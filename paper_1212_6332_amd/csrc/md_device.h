@@ -263,10 +263,15 @@ __device__ __forceinline__ void pair_derivs_typed(const Pot &p, double r, int a,
     const double2 *c =
         reinterpret_cast<const double2 *>(p.dpair + 10 * ((size_t)(a * p.nt + b) * t.n + m));
     // (Vb, Vc) (Vd, Ab) (Ac, Ad) (Bb, Bc) (Bd, 0): A = rho^(ab), B = rho^(ba)
-    const double2 c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3], c4 = c[4];
+    const double2 c0 = c[0], c1 = c[1], c2 = c[2];
     dv = fma(tt, fma(tt, 3.0 * c1.x, 2.0 * c0.y), c0.x) * t.inv_h;
     dab = fma(tt, fma(tt, 3.0 * c2.y, 2.0 * c2.x), c1.y) * t.inv_h;
-    dba = fma(tt, fma(tt, 3.0 * c4.x, 2.0 * c3.y), c3.x) * t.inv_h;
+    if (a == b) {
+        dba = dab;   // the same table: the lanes of such pairs skip its last two loads
+    } else {
+        const double2 c3 = c[3], c4 = c[4];
+        dba = fma(tt, fma(tt, 3.0 * c4.x, 2.0 * c3.y), c3.x) * t.inv_h;
+    }
 }
 
 // F^(a)(rho), F^(a)'(rho).

@@ -467,7 +467,8 @@ __device__ __forceinline__ void for_row(const int *__restrict__ idx, int i, int 
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             unsigned o = (unsigned)kk[u];
-            tj[u] = TYPED ? (int)(o & 31u) : 0;
+            // entries past the end of the row are not this build's: record 0, species 0
+            tj[u] = (TYPED && u < m) ? (int)(o & 31u) : 0;
             if constexpr (TYPED) o &= ~31u;
             off[u] = u < m ? o : 0u;
         }
