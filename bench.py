@@ -284,7 +284,10 @@ def bench_batched(steps=200, warmup=5):
                          "achieved": achieved, "peak": VALU_PEAK_TOPS,
                          "unit": "T FP64 lane-ops/s", "frac": achieved / VALU_PEAK_TOPS,
                          "ops_per_step": ops, "ms_per_step": ms, "entries": entries,
-                         "pairs": pairs}}
+                         "pairs": pairs,
+                         "binding": "vector L1 gathers of the spline intervals (one per pair "
+                                    "and table, each lane its own line): about 0.8 L1 "
+                                    "accesses per CU per cycle in the rocprofv3 counters"}}
 
 
 def bench_adjoint(evals=50, steps=100):
