@@ -186,7 +186,10 @@ void md_destroy(md_ctx *ctx);
 /* Human-readable text of a return code. */
 const char *md_strerror(int code);
 
-/* Replace the potential (same kind and table sizes as at creation). */
+/* Replace the potential: same kind, table sizes and cutoff rc as at
+ * creation (MD_ERR_ARG otherwise; rc sets the list radius, the cells and the
+ * rebuild threshold).  Cutoffs per pair of types may change; the lists are
+ * then built again before the next pass. */
 int md_set_potential(md_ctx *ctx, const md_potential *pot, void *stream);
 
 /* B-spline potentials only: upload 3K coefficients (device pointer, order

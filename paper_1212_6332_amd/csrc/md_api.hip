@@ -1022,8 +1022,19 @@ int md_set_potential(md_ctx *h, const md_potential *pot, void *stream)
     if (!h) return MD_ERR_ARG;
     int rc = check_potential(pot);
     if (rc != MD_OK) return rc;
-    if (pot->kind != h->c.kind_user) return MD_ERR_ARG;
-    return upload_potential(h->c, pot, as_stream(stream), false);
+    Ctx &c = h->c;
+    if (pot->kind != c.kind_user) return MD_ERR_ARG;
+    // the list radius, the cells and the rebuild threshold follow rc
+    if (pot->rc != c.pot.rc) return MD_ERR_ARG;
+    const std::vector<double> before = c.rc_pair;
+    rc = upload_potential(c, pot, as_stream(stream), false);
+    if (rc != MD_OK) return rc;
+    if (c.rc_pair != before) {
+        // cutoffs per pair of types set the list radius of each pair
+        c.list_valid = false;
+        batched_invalidate(c);
+    }
+    return MD_OK;
 }
 
 int md_set_theta(md_ctx *h, const double *theta, void *stream)

@@ -101,3 +101,30 @@ def test_pair_cutoff_trajectory_matches_oracle():
     d -= L * np.round(d / L)
     assert np.abs(d).max() < 1e-10
     assert rel(v, vo) < 1e-9
+
+
+@pytest.mark.parametrize("tiled", [1, 0])
+def test_set_potential_changes_pair_cutoffs(tiled):
+    """md_set_potential with other cutoffs per pair: the lists are built again
+    and the forces are the oracle's for the new cutoffs; another rc is refused."""
+    wl, L = case(14, 37)
+    t = wl.pot
+    S = md.System.from_workload(wl)
+    S.set_option(md.MD_OPT_TILED, tiled)
+    S.set_state(wl.pos, wl.vel)
+    S.forces()
+    other = W.Potential(t.kind, t.rc, t.params, t.tables, t.lo, t.hi, n_types=2,
+                        rc_pair=np.array([[5.2, 5.0], [5.0, 4.8]]))
+    S.set_potential(other)
+    f, e, eb = (x.cpu().numpy() for x in S.forces())
+    assert S.status()[0] == 0
+    bad_rc = W.Potential(t.kind, 5.2, t.params, t.tables, t.lo, t.hi, n_types=2)
+    with pytest.raises(md.MDError) as err:
+        S.set_potential(bad_rc)
+    assert err.value.code == md.MD_ERR_ARG
+    S.close()
+    pot = O.Alloy(other)
+    cnt, oid = O.alloy_list(wl.pos, L, pot, wl.types, wl.skin)
+    o = O.alloy_eval(wl.pos, L, pot, wl.types, cnt, oid)
+    assert rel(f, o["f"]) <= TOL
+    assert abs(eb[0] - o["E"]) <= TOL * abs(o["E"])
