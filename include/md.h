@@ -404,7 +404,8 @@ int md_time_pass(md_ctx *ctx, int32_t pass, int32_t reps, void *stream, double *
 
 /* Options. */
 enum {
-    MD_OPT_BATCHED = 1,     /* multi-box md_step: 1 persistent box-per-workgroup kernel
+    MD_OPT_BATCHED = 1,     /* multi-box md_step: 1 persistent kernel, a workgroup per
+                               box or pack of boxes (Section 4.4's many-box runs)
                                (default when B > 1), 0 the merged-box kernels     */
     MD_OPT_BATCH_BLOCK = 2, /* workgroup size of the persistent kernel (256/512/1024) */
     MD_OPT_USE_GRAPH = 3,   /* md_step replays a captured HIP graph (default 1)     */
