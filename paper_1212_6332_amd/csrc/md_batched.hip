@@ -681,8 +681,9 @@ static int batched_configure(Ctx &c, Batch &b, hipStream_t s)
                    b.cmax);
         b.npacks = (int)packs.size();
         b.lds = pack_lds_bytes(b.smax, b.cmax);
-        // the previous launches on this stream may still read the packs
-        if (hipStreamSynchronize(s) != hipSuccess ||
+        // earlier launches (on any stream) may still read the packs
+        (void)s;
+        if (hipDeviceSynchronize() != hipSuccess ||
             hipMemcpy(b.packs, packs.data(), sizeof(BPack) * packs.size(),
                       hipMemcpyHostToDevice) != hipSuccess)
             return MD_ERR_DEVICE;
