@@ -411,6 +411,21 @@ def bench_alloy(steps=100, warmup=10, reps=10):
             "rebuilds": int(reb), "steps": steps, "pass_ms": ms}
 
 
+def bench_32m(steps=50, warmup=5):
+    """One 32,000,000-atom box (FCC 200^3 cells of the same SMTB material)
+    on the one GPU: the headline step at eight times the atoms."""
+    from paper_1212_6332_amd import md, workloads as W
+
+    wl = W.fcc4m(ncell=200)
+    S = md.System.from_workload(wl)
+    S.set_state(wl.pos, wl.vel)
+    wall, _, reb = timed_steps(S, steps, warmup)
+    S.close()
+    return {"workload": "fcc32m: FCC 200^3 cells (32,000,000 atoms), the fcc4m material",
+            "atom_steps_per_s": wl.n_atoms * steps / wall, "ms_per_step": wall / steps * 1e3,
+            "rebuilds": int(reb), "steps": steps}
+
+
 def bench_c2(steps=1000, warmup=20):
     from paper_1212_6332_amd import md, workloads as W
 
@@ -586,7 +601,8 @@ def main():
     if not args.no_extras:
         for key, leg in (("batched", bench_batched), ("adjoint", bench_adjoint),
                          ("bcc128k", bench_c2), ("pressure", bench_pressure),
-                         ("thermostat", bench_thermostat), ("alloy", bench_alloy)):
+                         ("thermostat", bench_thermostat), ("alloy", bench_alloy),
+                         ("fcc32m", bench_32m)):
             out[key] = leg()
             log(f"{key} done ({time.perf_counter() - t0:.1f} s)")
     if not args.no_cpu_baseline:
