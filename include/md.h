@@ -390,7 +390,9 @@ int md_autotune(md_ctx *ctx, void *stream, int32_t *block);
  * contexts: force, half kick, and the next step's half kick and drift into the
  * second position buffer; elsewhere the same as MD_PASS_FORCE).  Positions and
  * velocities are restored afterwards, so timing leaves the trajectory
- * unchanged. */
+ * unchanged, except that timed list builds leave the state as a list build
+ * does (wrapped into the box and re-sorted) and the next pass builds again:
+ * timing MD_PASS_BUILD acts as one list rebuild at that point. */
 enum {
     MD_PASS_BUILD = 0,
     MD_PASS_DENSITY = 1,
