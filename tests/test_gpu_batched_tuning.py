@@ -200,3 +200,14 @@ def test_species_stepper_trajectory_matches_oracle(cutoffs, thermo):
         d = p[s] - q[s]
         d -= L * np.round(d / L)
         assert np.abs(d).max() < 1e-10, b
+
+
+def test_many_small_boxes_in_large_packs():
+    """3,000 boxes of 108 atoms: packs limited by the 64 boxes a pack holds
+    and by LDS, bitwise the trajectory of one box per workgroup."""
+    wl = W.batch2048(n_boxes=3000, nmin=3, nmax=3)
+    assert (np.diff(wl.box_offset) == 108).all()
+    a = run(wl, 30, (256, 0, 0))
+    b = run(wl, 30, (1024, 65535, 1))
+    assert a[2][0] == 0 and b[2][0] == 0
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
