@@ -168,6 +168,10 @@ def bench_main(steps, warmup, reps):
     wl = W.fcc4m()
     S = md.System.from_workload(wl)
     S.set_state(wl.pos, wl.vel)
+    S.autotune()                  # tiled or per-atom passes and the tile shape, by timing
+    tuned = {"tiled": int(S.get_option(md.MD_OPT_TILED)),
+             "tile_shape": int(S.get_option(md.MD_OPT_TILE_SHAPE)),
+             "tile_shapes": int(S.get_option(md.MD_OPT_TILE_SHAPES))}
     S.forces(energy=False)
     entries, pairs = list_stats(S, wl.pot.rc)
     n = wl.n_atoms
@@ -215,6 +219,7 @@ def bench_main(steps, warmup, reps):
                                       "algorithmic_gbs": density_pass_bytes(n, mean_list)
                                       / (ms["density"] * 1e-3) / 1e9}},
         "n_atoms": n,
+        "tuned": tuned,
     }
     S.close()
     return res
@@ -400,6 +405,8 @@ def bench_alloy(steps=100, warmup=10, reps=10):
     wl = W.alloy()
     S = md.System.from_workload(wl)
     S.set_state(wl.pos, wl.vel)
+    S.autotune()                  # tiled or per-atom passes and the tile shape, by timing
+    shape = int(S.get_option(md.MD_OPT_TILE_SHAPE))
     wall, _, reb = timed_steps(S, steps, warmup)
     ms = {"force_step": S.time_pass(md.MD_PASS_FORCE_STEP, reps),
           "density": S.time_pass(md.MD_PASS_DENSITY, reps),
@@ -408,7 +415,8 @@ def bench_alloy(steps=100, warmup=10, reps=10):
     return {"workload": "alloy: binary FCC 100^3 cells (4,000,000 atoms, 30 % species 1), "
                         "per-type-pair 5,000-knot splines, rc 5.3 A, skin 0.3 A, 300 K",
             "atom_steps_per_s": wl.n_atoms * steps / wall, "ms_per_step": wall / steps * 1e3,
-            "rebuilds": int(reb), "steps": steps, "pass_ms": ms}
+            "rebuilds": int(reb), "steps": steps, "pass_ms": ms,
+            "tile_shape": shape, "tile_shape_from": "md_autotune"}
 
 
 def bench_32m(steps=50, warmup=5):
@@ -595,7 +603,7 @@ def main():
                    "gpu_ms_per_step": r["gpu_ms_per_step"],
                    "ms_per_step_5_windows": r["ms_per_step_5_windows"],
                    "ms_per_step_median_of_5": r["ms_per_step_median_of_5"],
-                   "pass_ms": r["pass_ms"]},
+                   "pass_ms": r["pass_ms"], "tuned": r["tuned"]},
         "roofline": r["roofline"],
     }
     if not args.no_extras:

@@ -366,20 +366,21 @@ int md_get_box(md_ctx *ctx, double *box_len, void *stream);
  * and two workgroups' worth of atoms, in index and in cell visiting order.
  * Keeps the fastest as MD_OPT_BATCH_BLOCK, MD_OPT_BATCH_PACK and
  * MD_OPT_BATCH_ORDER and writes the workgroup size to *block (host).  The
- * cell grid of each box is not tuned: it is the grid of cells at least the
- * list radius wide, because each atom's neighbour order (and so the rounding
- * of its sums) follows the grid, and tuning must not change results.  Other contexts that
- * can be tiled (one box, or boxes stepped by the merged-box kernels; not
- * with the barostat): times the passes of a step (density, force with the
- * fused kicks, a tenth of a list build) with the tiled and with the
- * per-atom kernels and keeps the faster as MD_OPT_TILED (small systems,
- * with fewer tiles than the GPU has room for, are often faster per atom);
- * *block is then the unchanged MD_OPT_BATCH_BLOCK.  Positions and
- * velocities are restored afterwards, and the next md_step rebuilds the
- * lists and recomputes the forces from them: called between md_set_state
- * and the first md_step, the trajectory is bitwise that of an untuned
- * context with the chosen setting.  Synchronises.  Other contexts are left
- * unchanged. */
+ * cell grid of each of these boxes is not tuned: it is the grid of cells at
+ * least the list radius wide, because each atom's neighbour order (and so
+ * the rounding of its sums) follows that grid, and tuning must not change
+ * results.  Other contexts that can be tiled (one box, or boxes stepped by
+ * the merged-box kernels; not with the barostat): times the passes of a step
+ * (density, force with the fused kicks, a tenth of a list build) with the
+ * per-atom kernels and with the tiled kernels in each candidate tile shape,
+ * and keeps the fastest as MD_OPT_TILED and MD_OPT_TILE_SHAPE (small systems,
+ * with fewer tiles than the GPU has room for, are often faster per atom; the
+ * best tile shape depends on the atoms per cell); *block is then the
+ * unchanged MD_OPT_BATCH_BLOCK.  Positions and velocities are restored
+ * afterwards, and the next md_step rebuilds the lists and recomputes the
+ * forces from them: called between md_set_state and the first md_step, the
+ * trajectory is bitwise that of an untuned context (with the chosen tiled or
+ * per-atom setting).  Synchronises.  Other contexts are left unchanged. */
 int md_autotune(md_ctx *ctx, void *stream, int32_t *block);
 
 /* Benchmarking: launch one pass `reps` times on `stream`, bracketed by HIP
@@ -422,11 +423,20 @@ enum {
                                default) or a pack of consecutive boxes of the
                                size-sorted order holding at most this many atoms
                                together (a larger box still goes alone); 0..65535 */
-    MD_OPT_BATCH_ORDER = 7  /* persistent kernel: threads take a pack's atoms in
+    MD_OPT_BATCH_ORDER = 7, /* persistent kernel: threads take a pack's atoms in
                                index order (0, default) or in the cell order of
                                the last binning (1).  Neither this nor
                                MD_OPT_BATCH_PACK or MD_OPT_BATCH_BLOCK changes
                                any result: each atom's arithmetic is the same  */
+    MD_OPT_TILE_SHAPE = 8,  /* tiled passes: which of the context's candidate
+                               tile shapes (cells per tile along each axis)
+                               cuts its boxes into tiles, 0 .. MD_OPT_TILE_SHAPES
+                               - 1 (0: the planner's choice, the default).  The
+                               shape changes no result (each atom's neighbours
+                               are summed in the same order); the next pass
+                               builds the lists again                          */
+    MD_OPT_TILE_SHAPES = 9  /* read only: number of candidate tile shapes (1 for
+                               systems of few tiles)                           */
 };
 int md_set_option(md_ctx *ctx, int32_t key, int64_t value);
 int md_get_option(const md_ctx *ctx, int32_t key, int64_t *value);

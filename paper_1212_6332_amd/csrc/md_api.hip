@@ -303,6 +303,40 @@ void set_tiled(Ctx &c, bool v)
     c.list_valid = c.density_valid = c.forces_valid = false;
 }
 
+int tile_grid(const Ctx &c, const int s[3], std::vector<int> &bt);
+int64_t grid_cells(const Ctx &c, const std::vector<int> &bt, std::vector<int> &cell_off);
+void tile_table(const Ctx &c, std::vector<int> &ht);
+
+// Switch to candidate tile shape k: the tile grid, the cell numbering and the
+// device tables that describe them (their buffers were sized for every
+// candidate at creation); lists and graphs are built again.  Results do not
+// change, only the time of the passes.
+int apply_tile_shape(Ctx &c, int k)
+{
+    if (k < 0 || 3 * (size_t)k >= c.tile_shapes.size()) return MD_ERR_ARG;
+    if (k == c.tile_shape) return MD_OK;
+    HIP_TRY(hipDeviceSynchronize());
+    std::vector<int> bt, co, ht;
+    const int nt = tile_grid(c, &c.tile_shapes[3 * (size_t)k], bt);
+    const int64_t cells = grid_cells(c, bt, co);
+    if (cells < 0 || cells > c.cap_cells || nt > c.cap_tiles) return MD_ERR_ARG;
+    c.box_tile = bt;
+    c.ntiles = nt;
+    c.box_cell_off = co;
+    c.bd.n_cells = (int)cells;
+    tile_table(c, ht);
+    int rc;
+    if ((rc = h2d(c, c.d_tiles, ht.data(), ht.size() * sizeof(int))) != MD_OK ||
+        (rc = h2d(c, c.d_boxi + c.B, co.data(), sizeof(int) * (size_t)c.B)) != MD_OK)
+        return rc;
+    c.tile_shape = k;
+    if (c.tile_feasible) tiled_prepare(c);
+    graph_reset(c);
+    c.list_valid = c.density_valid = c.forces_valid = false;
+    batched_invalidate(c);
+    return MD_OK;
+}
+
 // The device status words after the work enqueued on s (waits for it).
 int read_flags(Ctx &c, hipStream_t s, unsigned *w)
 {
@@ -562,6 +596,69 @@ int steps_batched(Ctx &c, int nsteps, hipStream_t s)
     return MD_OK;
 }
 
+// Tile grid of every box for one tile shape s (cells per tile along x, y,
+// z): per box tx ty tz, tiles per axis, cells per tile and halo mode, in bt;
+// returns the number of tiles.  Boxes with at least max(s) + 2 cells per
+// axis are cut into tiles (halo mode A), a smaller box is one tile (mode B),
+// and without tiling every box is one tile numbered row-major.
+int tile_grid(const Ctx &c, const int s[3], std::vector<int> &bt)
+{
+    const int tmax = std::max(s[0], std::max(s[1], s[2]));
+    bt.assign(8 * (size_t)c.B, 0);
+    int ntiles = 0;
+    for (int b = 0; b < c.B; ++b) {
+        int nc = c.box_nc[b];
+        int *t = &bt[8 * b];
+        if (c.tile_feasible && nc >= tmax + 2) {
+            for (int d = 0; d < 3; ++d) {
+                t[d] = s[d];
+                t[3 + d] = (nc + s[d] - 1) / s[d];
+            }
+            t[7] = kTileA;
+        } else {
+            t[0] = t[1] = t[2] = nc;
+            t[3] = t[4] = t[5] = 1;
+            t[7] = c.tile_feasible ? kTileB : kTileGlobal;
+        }
+        t[6] = t[0] * t[1] * t[2];
+        ntiles += t[3] * t[4] * t[5];
+    }
+    return ntiles;
+}
+
+// Cells of every box (tiles times cells per tile, so a box's cells are
+// numbered tile by tile) for the tile grid bt: the first cell of each box in
+// cell_off[B + 1]; returns the total, or -1 beyond 2^30.
+int64_t grid_cells(const Ctx &c, const std::vector<int> &bt, std::vector<int> &cell_off)
+{
+    cell_off.assign(c.B + 1, 0);
+    int64_t cells = 0;
+    for (int b = 0; b < c.B; ++b) {
+        const int *t = &bt[8 * b];
+        cell_off[b] = (int)cells;
+        cells += (int64_t)t[3] * t[4] * t[5] * t[6];
+        if (cells >= (int64_t)1 << 30) return -1;
+    }
+    cell_off[c.B] = (int)cells;
+    return cells;
+}
+
+// The device tile table: tile(8B) | tile_off(B+1) | tile_box(ntiles).
+void tile_table(const Ctx &c, std::vector<int> &ht)
+{
+    const int B = c.B;
+    ht.assign(8 * (size_t)B + B + 1 + c.ntiles, 0);
+    std::copy(c.box_tile.begin(), c.box_tile.end(), ht.begin());
+    int g = 0;
+    for (int b = 0; b < B; ++b) {
+        ht[8 * B + b] = g;
+        const int *t = &c.box_tile[8 * b];
+        for (int k = 0; k < t[3] * t[4] * t[5]; ++k) ht[9 * B + 1 + g + k] = b;
+        g += t[3] * t[4] * t[5];
+    }
+    ht[9 * B] = g;
+}
+
 // Tile geometry.  Tiles of tx x ty x tz cells are chosen so that a tile
 // holds about one 1024-thread workgroup of atoms and its halo (the tile grown
 // by one cell) fits the LDS of one workgroup with a 30% margin.  Boxes with at
@@ -582,7 +679,7 @@ int plan_tiles(Ctx &c, double per_cell, bool allow)
         return MD_ERR_DEVICE;
     // the tile of at most max_atoms atoms (on average) and at most tlim cells
     // per axis with the most atoms whose halo fits in LDS
-    auto pick = [&](double max_atoms, int tlim, int out[3]) {
+    auto pick = [&](double max_atoms, int tlim, int out[3], double margin = 1.3) {
         double best_atoms = 0.0;
         out[0] = out[1] = out[2] = 0;
         for (int tz = 1; tz <= tlim; ++tz)
@@ -591,7 +688,7 @@ int plan_tiles(Ctx &c, double per_cell, bool allow)
                     double atoms = tx * ty * tz * per_cell;
                     int halo_cells = (tx + 2) * (ty + 2) * (tz + 2);
                     double halo = halo_cells * per_cell;
-                    if (atoms > max_atoms || 1.3 * halo > c.hmax || halo_cells > kHaloCells)
+                    if (atoms > max_atoms || margin * halo > c.hmax || halo_cells > kHaloCells)
                         continue;
                     if (atoms > best_atoms) {
                         best_atoms = atoms;
@@ -644,25 +741,29 @@ int plan_tiles(Ctx &c, double per_cell, bool allow)
     }
     c.tile_feasible = feasible;
     c.tiled = feasible;
-    c.box_tile.assign(8 * (size_t)c.B, 0);
-    c.ntiles = 0;
-    for (int b = 0; b < c.B; ++b) {
-        int nc = c.box_nc[b];
-        int *t = &c.box_tile[8 * b];
-        if (feasible && nc >= tmax + 2) {
-            for (int d = 0; d < 3; ++d) {
-                t[d] = best[d];
-                t[3 + d] = (nc + best[d] - 1) / best[d];
-            }
-            t[7] = kTileA;
-        } else {
-            t[0] = t[1] = t[2] = nc;
-            t[3] = t[4] = t[5] = 1;
-            t[7] = feasible ? kTileB : kTileGlobal;
+    // other shapes for md_autotune (large systems with full tiles): a larger
+    // tile with a thinner LDS margin and a smaller one, each kept only when
+    // no box changes its halo mode (the tile overflow check guards the
+    // thinner margin as it guards every tile)
+    c.tile_shapes.assign(best, best + 3);
+    if (feasible && c.tile_lanes == 1) {
+        int alt[2][3];
+        pick(1300.0, 6, alt[0], 1.12);
+        pick(900.0, 6, alt[1]);
+        for (const auto &s : alt) {
+            if (s[0] <= 0) continue;
+            bool same = false;
+            for (size_t k = 0; k < c.tile_shapes.size(); k += 3)
+                same = same || (c.tile_shapes[k] == s[0] && c.tile_shapes[k + 1] == s[1] &&
+                                c.tile_shapes[k + 2] == s[2]);
+            int tm = std::max(s[0], std::max(s[1], s[2]));
+            for (int b = 0; b < c.B && !same; ++b)
+                same = (c.box_nc[b] >= tm + 2) != (c.box_nc[b] >= tmax + 2);
+            if (!same) c.tile_shapes.insert(c.tile_shapes.end(), s, s + 3);
         }
-        t[6] = t[0] * t[1] * t[2];
-        c.ntiles += t[3] * t[4] * t[5];
     }
+    c.tile_shape = 0;
+    c.ntiles = tile_grid(c, best, c.box_tile);
     return MD_OK;
 }
 
@@ -754,15 +855,20 @@ int create_impl(const md_system *sys, const md_potential *pot, md_ctx **out, voi
     }
     int rc_t = plan_tiles(c, per_cell, pot->kind != MD_POT_BSPLINE);
     if (rc_t != MD_OK) return fail(rc_t);
-    int64_t cells = 0;
-    for (int b = 0; b < B; ++b) {
-        const int *t = &c.box_tile[8 * b];
-        c.box_cell_off[b] = (int)cells;
-        cells += (int64_t)t[3] * t[4] * t[5] * t[6];
-        if (cells >= (int64_t)1 << 30) return fail(MD_ERR_ARG);
-    }
-    c.box_cell_off[B] = (int)cells;
+    const int64_t cells = grid_cells(c, c.box_tile, c.box_cell_off);
+    if (cells < 0) return fail(MD_ERR_ARG);
     c.bd.n_cells = (int)cells;
+    // buffers for the largest of the candidate tile shapes
+    c.cap_cells = (int)cells;
+    c.cap_tiles = c.ntiles;
+    for (size_t k = 3; k < c.tile_shapes.size(); k += 3) {
+        std::vector<int> bt, co;
+        const int nt = tile_grid(c, &c.tile_shapes[k], bt);
+        const int64_t nc = grid_cells(c, bt, co);
+        if (nc < 0) return fail(MD_ERR_ARG);
+        c.cap_cells = std::max(c.cap_cells, (int)nc);
+        c.cap_tiles = std::max(c.cap_tiles, nt);
+    }
     int mn = sys->max_neighbors > 0 ? sys->max_neighbors : ((int)mn_est + 7) / 8 * 8;
     if (mn < 1) mn = 1;
     if (mn > kMaxCapacity) return fail(MD_ERR_ARG);
@@ -806,17 +912,10 @@ int create_impl(const md_system *sys, const md_potential *pot, md_ctx **out, voi
 
     // tile descriptors
     {
-        std::vector<int> ht(8 * (size_t)B + B + 1 + c.ntiles);
-        std::copy(c.box_tile.begin(), c.box_tile.end(), ht.begin());
-        int g = 0;
-        for (int b = 0; b < B; ++b) {
-            ht[8 * B + b] = g;
-            const int *t = &c.box_tile[8 * b];
-            for (int k = 0; k < t[3] * t[4] * t[5]; ++k) ht[9 * B + 1 + g + k] = b;
-            g += t[3] * t[4] * t[5];
-        }
-        ht[9 * B] = g;
-        if ((rc = dev_alloc(c, &c.d_tiles, ht.size())) != MD_OK) return fail(rc);
+        std::vector<int> ht;
+        tile_table(c, ht);
+        if ((rc = dev_alloc(c, &c.d_tiles, 9 * (size_t)B + 1 + c.cap_tiles)) != MD_OK)
+            return fail(rc);
         if ((rc = h2d(c, c.d_tiles, ht.data(), ht.size() * sizeof(int))) != MD_OK)
             return fail(rc);
         c.bx.tile = c.d_tiles;
@@ -824,8 +923,9 @@ int create_impl(const md_system *sys, const md_potential *pot, md_ctx **out, voi
         c.bx.tile_box = c.d_tiles + 9 * B + 1;
         if (c.tile_feasible) {
             tiled_prepare(c);
-            if ((rc = dev_alloc(c, &c.nl.tsrc, (size_t)c.ntiles * c.hmax)) != MD_OK) return fail(rc);
-            if ((rc = dev_alloc(c, &c.nl.ttotal, (size_t)c.ntiles)) != MD_OK) return fail(rc);
+            if ((rc = dev_alloc(c, &c.nl.tsrc, (size_t)c.cap_tiles * c.hmax)) != MD_OK)
+                return fail(rc);
+            if ((rc = dev_alloc(c, &c.nl.ttotal, (size_t)c.cap_tiles)) != MD_OK) return fail(rc);
         }
     }
 
@@ -842,10 +942,11 @@ int create_impl(const md_system *sys, const md_potential *pot, md_ctx **out, voi
                     &c.nl.count, &c.nl.total};
     for (int **p : ints)
         if ((rc = dev_alloc(c, p, (size_t)N)) != MD_OK) return fail(rc);
-    if ((rc = dev_alloc(c, &c.bd.cell_count, (size_t)cells)) != MD_OK) return fail(rc);
-    if ((rc = dev_alloc(c, &c.bd.cell_start, (size_t)cells + 1)) != MD_OK) return fail(rc);
-    if ((rc = dev_alloc(c, &c.bd.bsum, (size_t)cells / 4096 + 2)) != MD_OK) return fail(rc);
-    if ((rc = zero(c, c.bd.cell_count, sizeof(int) * (size_t)cells)) != MD_OK) return fail(rc);
+    const size_t cap = (size_t)c.cap_cells;
+    if ((rc = dev_alloc(c, &c.bd.cell_count, cap)) != MD_OK) return fail(rc);
+    if ((rc = dev_alloc(c, &c.bd.cell_start, cap + 1)) != MD_OK) return fail(rc);
+    if ((rc = dev_alloc(c, &c.bd.bsum, cap / 4096 + 2)) != MD_OK) return fail(rc);
+    if ((rc = zero(c, c.bd.cell_count, sizeof(int) * cap)) != MD_OK) return fail(rc);
     if ((rc = alloc_list(c, mn)) != MD_OK) return fail(rc);
     if ((rc = dev_alloc(c, &c.dev.flags, kFlagWords)) != MD_OK) return fail(rc);
     {
@@ -1178,18 +1279,35 @@ int md_autotune(md_ctx *h, void *stream, int32_t *block)
         // and the per-atom passes for a step (density, force with the fused
         // kicks, a tenth of a list build), timed on the current state
         if (!c.tile_feasible || c.baro_on) return MD_OK;
-        double cost[2] = {0.0, 0.0};
-        for (int t = 0; t < 2; ++t) {
-            set_tiled(c, t == 1);
+        // candidates: the per-atom passes (-1) and the tiled passes with each
+        // candidate tile shape
+        auto cost_of = [&](double &cost) -> int {
             double b = 0.0, d = 0.0, f = 0.0;
             int rc;
             if ((rc = md_time_pass(h, MD_PASS_BUILD, 2, stream, &b)) != MD_OK ||
                 (rc = md_time_pass(h, MD_PASS_DENSITY, 10, stream, &d)) != MD_OK ||
                 (rc = md_time_pass(h, MD_PASS_FORCE_STEP, 10, stream, &f)) != MD_OK)
                 return rc;
-            cost[t] = d + f + 0.1 * b;
+            cost = d + f + 0.1 * b;
+            return MD_OK;
+        };
+        const int start = c.tile_shape;
+        int best = -1, rc;
+        double best_cost = 0.0;
+        set_tiled(c, false);
+        if ((rc = cost_of(best_cost)) != MD_OK) return rc;
+        for (int k = 0; 3 * (size_t)k < c.tile_shapes.size(); ++k) {
+            if ((rc = apply_tile_shape(c, k)) != MD_OK) return rc;
+            set_tiled(c, true);
+            double cost = 0.0;
+            if ((rc = cost_of(cost)) != MD_OK) return rc;
+            if (cost <= best_cost) {
+                best_cost = cost;
+                best = k;
+            }
         }
-        set_tiled(c, cost[1] <= cost[0]);
+        if ((rc = apply_tile_shape(c, best >= 0 ? best : start)) != MD_OK) return rc;
+        set_tiled(c, best >= 0);
         return MD_OK;
     }
     hipStream_t s = as_stream(stream);
@@ -1556,6 +1674,9 @@ int md_set_option(md_ctx *h, int32_t key, int64_t v)
         if (v != 0 && v != 1) return MD_ERR_ARG;
         c.batch_cell_order = (int)v;
         return MD_OK;
+    case MD_OPT_TILE_SHAPE:
+        if (v < 0 || 3 * (uint64_t)v >= c.tile_shapes.size()) return MD_ERR_ARG;
+        return apply_tile_shape(c, (int)v);
     }
     return MD_ERR_ARG;
 }
@@ -1572,6 +1693,8 @@ int md_get_option(const md_ctx *h, int32_t key, int64_t *v)
     case MD_OPT_TILED: *v = c.tiled; return MD_OK;
     case MD_OPT_BATCH_PACK: *v = c.batch_cap; return MD_OK;
     case MD_OPT_BATCH_ORDER: *v = c.batch_cell_order; return MD_OK;
+    case MD_OPT_TILE_SHAPE: *v = c.tile_shape; return MD_OK;
+    case MD_OPT_TILE_SHAPES: *v = (int64_t)(c.tile_shapes.size() / 3); return MD_OK;
     }
     return MD_ERR_ARG;
 }

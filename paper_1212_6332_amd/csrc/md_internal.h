@@ -264,6 +264,13 @@ struct Ctx {
     std::vector<int> box_nc, box_cell_off;
     std::vector<int> box_tile;         // per box: tx ty tz gx gy gz tile_cells mode
     int ntiles = 0;
+    // tile shapes (cells per tile along x, y, z) md_autotune chooses among:
+    // results do not depend on the shape (each atom's neighbours are summed in
+    // the same stencil and slot order), only the time does.  Buffers are
+    // sized for the largest cell and tile counts among them.
+    std::vector<int> tile_shapes;      // 3 per candidate; candidate 0 is the planner's
+    int tile_shape = 0;
+    int cap_cells = 0, cap_tiles = 0;
     int tile_grid = 1;                 // workgroups of the persistent tiled density pass
     int tile_lanes = 1;                // lanes per atom in the tiled passes (2: few tiles)
     bool tiled = false, tile_feasible = false;
