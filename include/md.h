@@ -372,7 +372,9 @@ int md_get_box(md_ctx *ctx, double *box_len, void *stream);
  * results.  Other contexts that can be tiled (one box, or boxes stepped by
  * the merged-box kernels; not with the barostat): times the passes of a step
  * (density, force with the fused kicks, a tenth of a list build) with the
- * per-atom kernels and with the tiled kernels in each candidate tile shape,
+ * per-atom kernels and with the tiled kernels in each candidate tile shape
+ * (a shape whose halo does not fit a tile's LDS on the current state is
+ * passed over, and no MD_FLAG_TILE_OVERFLOW is left behind for it),
  * and keeps the fastest as MD_OPT_TILED and MD_OPT_TILE_SHAPE (small systems,
  * with fewer tiles than the GPU has room for, are often faster per atom; the
  * best tile shape depends on the atoms per cell); *block is then the

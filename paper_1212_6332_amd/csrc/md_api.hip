@@ -1296,9 +1296,24 @@ int md_autotune(md_ctx *h, void *stream, int32_t *block)
         double best_cost = 0.0;
         set_tiled(c, false);
         if ((rc = cost_of(best_cost)) != MD_OK) return rc;
+        hipStream_t s = as_stream(stream);
         for (int k = 0; 3 * (size_t)k < c.tile_shapes.size(); ++k) {
             if ((rc = apply_tile_shape(c, k)) != MD_OK) return rc;
             set_tiled(c, true);
+            // a shape whose halo does not fit a tile's LDS on this state is no
+            // candidate: its build is checked here, and its halt cleared,
+            // instead of moving the context to the per-atom passes
+            launch_build(c, false, s);
+            unsigned w[kFlagWords];
+            if ((rc = read_flags(c, s, w)) != MD_OK) return rc;
+            if (w[kHaltWord]) {
+                launch_fill_u32(c.dev.flags + kHaltWord, 2, 0u, s);
+                launch_clear_bits(c, MD_FLAG_TILE_OVERFLOW, s);
+                c.list_valid = false;
+                continue;
+            }
+            c.list_valid = true;
+            c.density_valid = c.forces_valid = false;
             double cost = 0.0;
             if ((rc = cost_of(cost)) != MD_OK) return rc;
             if (cost <= best_cost) {

@@ -258,8 +258,10 @@ class System:
     @_mutates
     def autotune(self):
         """md_autotune: the fastest block shape of the persistent multi-box
-        stepper (workgroup size, box packing, visiting order), or tiled versus
-        per-atom passes elsewhere; returns the stepper's workgroup size."""
+        stepper (workgroup size, box packing, visiting order), or elsewhere the
+        per-atom passes or the tiled passes with one of the candidate tile
+        shapes (a shape whose halo overflows a tile's LDS on the current state
+        is passed over); returns the stepper's workgroup size."""
         b = C.c_int32()
         _check(lib().md_autotune(self._h, _stream(), C.byref(b)), "md_autotune")
         return int(b.value)

@@ -128,12 +128,10 @@ def test_batched_overflow_takes_the_call_again():
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
-def test_tile_overflow_moves_to_per_atom_passes():
+def cube():
     """3,400 atoms moved into a 2x2x2-cell cube of a tiled box (8 cells per
-    axis): the halo of every tile around it exceeds the LDS of a workgroup.
-    The context moves to the per-atom passes and raises the row capacity
-    (rows in the cube hold about 1,700 neighbours), and the forces are the
-    oracle's."""
+    axis): the halo of every tile around it exceeds the LDS of a workgroup,
+    and rows in the cube hold about 1,700 neighbours."""
     wl = W.fcc4m(ncell=14)
     L = float(wl.box_len[0, 0])
     pos = O.wrap(wl.pos, L)
@@ -143,6 +141,14 @@ def test_tile_overflow_moves_to_per_atom_passes():
     assert far.size == 3400
     pos[far] = 2 * w + rng.uniform(0.0, 2 * w, size=(far.size, 3))
     wl.pos = pos
+    count, ids = O.neighbor_list(pos, L, O.rlist(wl.pot.rc, wl.skin, L), maxn=4096)
+    return wl, O.forces(pos, L, O.Pot(wl.pot), count, ids)
+
+
+def test_tile_overflow_moves_to_per_atom_passes():
+    """The cube: the context moves to the per-atom passes and raises the row
+    capacity, and the forces are the oracle's."""
+    wl, ref = cube()
     S = md.System.from_workload(wl)
     assert S.get_option(md.MD_OPT_TILED) == 1
     S.set_state(wl.pos)
@@ -150,8 +156,26 @@ def test_tile_overflow_moves_to_per_atom_passes():
     assert S.get_option(md.MD_OPT_TILED) == 0
     assert S.max_neighbors > 1500
     S.close()
-    count, ids = O.neighbor_list(pos, L, O.rlist(wl.pot.rc, wl.skin, L), maxn=4096)
-    ref = O.forces(pos, L, O.Pot(wl.pot), count, ids)
+    assert rel(f.cpu().numpy(), ref["f"]) <= TOL
+    assert abs(float(eb[0]) - ref["E"]) <= TOL * abs(ref["E"])
+
+
+def test_autotune_passes_over_tile_shapes_that_overflow():
+    """The cube timed by md_autotune before any pass: the build of every
+    candidate tile shape overflows and is passed over, the per-atom passes
+    are kept, no overflow condition is left behind, and the forces are the
+    oracle's."""
+    wl, ref = cube()
+    S = md.System.from_workload(wl)
+    assert S.get_option(md.MD_OPT_TILE_SHAPES) >= 1
+    S.set_state(wl.pos)
+    S.autotune()
+    assert S.get_option(md.MD_OPT_TILED) == 0
+    assert S.status()[0] & md.MD_FLAG_TILE_OVERFLOW == 0
+    f, e, eb = S.forces()
+    assert S.status()[0] & md.MD_FLAG_TILE_OVERFLOW == 0
+    assert S.max_neighbors > 1500
+    S.close()
     assert rel(f.cpu().numpy(), ref["f"]) <= TOL
     assert abs(float(eb[0]) - ref["E"]) <= TOL * abs(ref["E"])
 
