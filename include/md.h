@@ -381,8 +381,8 @@ int md_get_box(md_ctx *ctx, double *box_len, void *stream);
  * unchanged MD_OPT_BATCH_BLOCK.  Positions and velocities are restored
  * afterwards, and the next md_step rebuilds the lists and recomputes the
  * forces from them: called between md_set_state and the first md_step, the
- * trajectory is bitwise that of an untuned context (with the chosen tiled or
- * per-atom setting).  Synchronises.  Other contexts are left unchanged. */
+ * trajectory is bitwise that of an untuned context with the chosen settings
+ * (tiled or per-atom passes, tile shape).  Synchronises.  Other contexts are left unchanged. */
 int md_autotune(md_ctx *ctx, void *stream, int32_t *block);
 
 /* Benchmarking: launch one pass `reps` times on `stream`, bracketed by HIP
@@ -434,11 +434,19 @@ enum {
                                tile shapes (cells per tile along each axis)
                                cuts its boxes into tiles, 0 .. MD_OPT_TILE_SHAPES
                                - 1 (0: the planner's choice, the default).  The
-                               shape changes no result (each atom's neighbours
-                               are summed in the same order); the next pass
+                               lists are the same for every shape and each
+                               atom's neighbours are visited in the same order;
+                               only the atoms of a tile beyond one per thread
+                               of its workgroup (at most 64 of them) have their
+                               rows summed by 16 lanes, so results differ
+                               between shapes in rounding only.  The next pass
                                builds the lists again                          */
-    MD_OPT_TILE_SHAPES = 9  /* read only: number of candidate tile shapes (1 for
+    MD_OPT_TILE_SHAPES = 9, /* read only: number of candidate tile shapes (1 for
                                systems of few tiles)                           */
+    MD_OPT_TILE_DIMS = 10   /* read only: cells per tile along x, y and z of the
+                               current tile shape, x | y << 8 | z << 16 (boxes
+                               with fewer than the largest + 2 cells per axis
+                               are one tile each)                              */
 };
 int md_set_option(md_ctx *ctx, int32_t key, int64_t value);
 int md_get_option(const md_ctx *ctx, int32_t key, int64_t *value);

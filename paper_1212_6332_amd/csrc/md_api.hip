@@ -309,8 +309,9 @@ void tile_table(const Ctx &c, std::vector<int> &ht);
 
 // Switch to candidate tile shape k: the tile grid, the cell numbering and the
 // device tables that describe them (their buffers were sized for every
-// candidate at creation); lists and graphs are built again.  Results do not
-// change, only the time of the passes.
+// candidate at creation); lists and graphs are built again.  The lists do not
+// change; results change in rounding only (the rows of the atoms of a tile
+// beyond one per thread are summed by several lanes).
 int apply_tile_shape(Ctx &c, int k)
 {
     if (k < 0 || 3 * (size_t)k >= c.tile_shapes.size()) return MD_ERR_ARG;
@@ -1710,6 +1711,11 @@ int md_get_option(const md_ctx *h, int32_t key, int64_t *v)
     case MD_OPT_BATCH_ORDER: *v = c.batch_cell_order; return MD_OK;
     case MD_OPT_TILE_SHAPE: *v = c.tile_shape; return MD_OK;
     case MD_OPT_TILE_SHAPES: *v = (int64_t)(c.tile_shapes.size() / 3); return MD_OK;
+    case MD_OPT_TILE_DIMS: {
+        const int *d = &c.tile_shapes[3 * (size_t)c.tile_shape];
+        *v = (int64_t)d[0] | (int64_t)d[1] << 8 | (int64_t)d[2] << 16;
+        return MD_OK;
+    }
     }
     return MD_ERR_ARG;
 }

@@ -534,19 +534,75 @@ __device__ __forceinline__ void for_row_all(const NList &nl, int i, int N, int p
                                           rc2, cut2row, body);
 }
 
-// Sum over the P lanes (1 or 2, adjacent) that share the row of one atom: a
-// DPP quad permutation swaps the values of lanes 2k and 2k + 1, so both end
-// with the same sum.
+// The value of the lane that DPP control CTRL names (within a row of 16).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the P lanes (1, 2, 4, 8 or 16, adjacent and aligned) that share
+// the row of one atom, by a butterfly of DPP exchanges within a row of 16
+// lanes: lane k with k ^ 1 (quad_perm [1, 0, 3, 2]), then with k ^ 2
+// (quad_perm [2, 3, 0, 1]), then the two quads of each half row
+// (row_half_mirror), then the two halves (row_mirror).  Each step adds two
+// values that are equal across the lanes of each side, so every lane ends
+// with the same sum, in the same order of additions.
 template <int P>
 __device__ __forceinline__ double lanes_sum(double v)
 {
-    if constexpr (P == 2) {
-        constexpr int swap_pairs = 0xB1;  // quad_perm [1, 0, 3, 2]
-        int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), swap_pairs, 0xf, 0xf, false);
-        int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), swap_pairs, 0xf, 0xf, false);
-        v += __hiloint2double(hi, lo);
-    }
+    static_assert(P == 1 || P == 2 || P == 4 || P == 8 || P == 16, "lanes per row");
+    if constexpr (P >= 2) v += dpp_f64<0xB1>(v);
+    if constexpr (P >= 4) v += dpp_f64<0x4E>(v);
+    if constexpr (P >= 8) v += dpp_f64<0x141>(v);
+    if constexpr (P >= 16) v += dpp_f64<0x140>(v);
     return v;
+}
+
+template <int V>
+struct Lanes {
+    static constexpr int value = V;
+};
+
+// The atoms of a tile, atom(lanes, slot, lane of the row): P lanes on each
+// row (one, or two in systems of few tiles).  With one lane per row, a tile
+// of n atoms, kT < n <= 1.5 kT, runs its first kT atoms one per thread and
+// the surplus e = n - kT with S lanes on each row, S the largest of 16, 8, 4
+// and 2 with e S <= kT: a second pass over the surplus atoms then costs every
+// wavefront about 1/S of a row, where one lane per row would cost the
+// wavefronts holding them a whole row while the others wait.  The analytic
+// kinds take only S = 16 (e <= 64; more variants cost their kernels
+// registers), larger surpluses one lane per row.  Only these rows are summed
+// in another order (per lane, then across the S lanes), so results depend on
+// the tiling in rounding only.
+template <int KIND>
+constexpr bool kAllSurplus = KIND == MD_POT_SPLINE || KIND == kTyped;
+
+template <int P, bool ALL, class Atom>
+__device__ __forceinline__ void tile_atoms(const Tile &t, Atom &&atom)
+{
+    const int n = t.s1 - t.s0, tid = (int)threadIdx.x;
+    const int e = n - kT;
+    if (P == 1 && e > 0 && (ALL ? 2 * e : 16 * e) <= kT) {
+        atom(Lanes<1>{}, t.s0 + tid, 0);
+        auto surplus = [&](auto lanes) {
+            constexpr int S = decltype(lanes)::value;
+            const int i = t.s0 + kT + tid / S;
+            if (i < t.s1) atom(lanes, i, tid % S);
+        };
+        if (16 * e <= kT) {
+            surplus(Lanes<16>{});
+        } else if constexpr (ALL) {
+            if (8 * e <= kT) surplus(Lanes<8>{});
+            else if (4 * e <= kT) surplus(Lanes<4>{});
+            else surplus(Lanes<2>{});
+        }
+        return;
+    }
+    for (int i = t.s0 + tid / P; i < t.s1; i += kT / P)
+        atom(Lanes<P>{}, i, P == 1 ? 0 : tid % P);
 }
 
 // Tile m of persistent workgroup b (of P), or -1.  Workgroups are dispatched
@@ -638,9 +694,9 @@ __global__ __launch_bounds__(kT) void k_tile_density(int N, int G, State st, Box
     if (halted(flags)) return;
     const Pot pot = pinned(pot_arg);
     unsigned bad = 0;
-    const int part = P == 1 ? 0 : (int)threadIdx.x % P;
     run_tiles<false>(G, st, bx, bd, nl, rec, hmax, [&](const Tile &t) {
-        for (int i = t.s0 + (int)threadIdx.x / P; i < t.s1; i += kT / P) {
+        tile_atoms<P, kAllSurplus<KIND>>(t, [&](auto lanes, int i, int part) {
+            constexpr int S = decltype(lanes)::value;
             double xi = st.x[i], yi = st.y[i], zi = st.z[i];
             double rho = 0.0;
             const int ai = KIND == kTyped ? st.type[i] : 0;
@@ -651,10 +707,10 @@ __global__ __launch_bounds__(kT) void k_tile_density(int N, int G, State st, Box
                     rho += dens<KIND>(pot, r2 * rsqrt_nr(r2), bad);
             };
             const double *cr = (KIND == kTyped && pot.cut2) ? pot.cut2 + ai * pot.nt : nullptr;
-            for_row_all<KIND == kTyped, false, P>(nl, i, N, part, rec, xi, yi, zi, t.L, t.invL,
+            for_row_all<KIND == kTyped, false, S>(nl, i, N, part, rec, xi, yi, zi, t.L, t.invL,
                                                   pot.rc2, cr, body);
-            rho = lanes_sum<P>(rho);
-            if (P > 1 && part != 0) continue;
+            rho = lanes_sum<S>(rho);
+            if (S > 1 && part != 0) return;
             double F, Fp;
             if constexpr (KIND == kTyped)
                 embed_typed(pot, rho, ai, F, Fp, bad);
@@ -663,7 +719,7 @@ __global__ __launch_bounds__(kT) void k_tile_density(int N, int G, State st, Box
             st.rho[i] = rho;
             st.Femb[i] = F;
             st.Fp[i] = Fp;
-        }
+        });
     });
     raise_flags(flags, bad);
 }
@@ -691,8 +747,8 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
         tile_setup(bx, bd, g, t);
         stage_list<true>(g, st, nl, rec, hmax);
         const double thr2 = bx.thr2[t.b];
-        const int part = P == 1 ? 0 : (int)threadIdx.x % P;
-        for (int i = t.s0 + (int)threadIdx.x / P; i < t.s1; i += kT / P) {
+        tile_atoms<P, kAllSurplus<KIND>>(t, [&](auto lanes, int i, int part) {
+            constexpr int S = decltype(lanes)::value;
             double xi = st.x[i], yi = st.y[i], zi = st.z[i];
             double fpi = st.Fp[i];
             // the epilogue's inputs are loaded before the row, so their
@@ -742,16 +798,16 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
                 }
             };
             const double *cr = (KIND == kTyped && pot.cut2) ? pot.cut2 + ai * pot.nt : nullptr;
-            for_row_all<KIND == kTyped, true, P>(nl, i, N, part, rec, xi, yi, zi, t.L, t.invL,
+            for_row_all<KIND == kTyped, true, S>(nl, i, N, part, rec, xi, yi, zi, t.L, t.invL,
                                                  pot.rc2, cr, body);
-            ax = lanes_sum<P>(ax);
-            ay = lanes_sum<P>(ay);
-            az = lanes_sum<P>(az);
+            ax = lanes_sum<S>(ax);
+            ay = lanes_sum<S>(ay);
+            az = lanes_sum<S>(az);
             if constexpr (ENERGY) {
-                ep = lanes_sum<P>(ep);
-                wv = lanes_sum<P>(wv);
+                ep = lanes_sum<S>(ep);
+                wv = lanes_sum<S>(wv);
             }
-            if (P > 1 && part != 0) continue;
+            if (S > 1 && part != 0) return;
             ax *= sg;
             ay *= sg;
             az *= sg;
@@ -790,7 +846,7 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
                 st.vy[i] = vy;
                 st.vz[i] = vz;
             }
-        }
+        });
     }
     if constexpr (MODE == 2) {
         // one request per wavefront, and none once the flag is already raised

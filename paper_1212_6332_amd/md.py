@@ -24,7 +24,8 @@ MD_ERR_NONFINITE, MD_ERR_DEVICE, MD_ERR_STATE, MD_ERR_NOMEM, MD_ERR_SCRATCH = -5
  MD_FLAG_BOX_RANGE) = 1, 2, 4, 8, 16
 MD_POT_FS, MD_POT_SMTB, MD_POT_SPLINE, MD_POT_BSPLINE = 1, 2, 3, 4
 MD_OPT_BATCHED, MD_OPT_BATCH_BLOCK, MD_OPT_USE_GRAPH, MD_OPT_GRAPH_STEPS, MD_OPT_TILED = 1, 2, 3, 4, 5
-MD_OPT_BATCH_PACK, MD_OPT_BATCH_ORDER, MD_OPT_TILE_SHAPE, MD_OPT_TILE_SHAPES = 6, 7, 8, 9
+(MD_OPT_BATCH_PACK, MD_OPT_BATCH_ORDER, MD_OPT_TILE_SHAPE, MD_OPT_TILE_SHAPES,
+ MD_OPT_TILE_DIMS) = 6, 7, 8, 9, 10
 (MD_PASS_BUILD, MD_PASS_DENSITY, MD_PASS_FORCE, MD_PASS_KICK_DRIFT, MD_PASS_FORCE_STEP,
  MD_PASS_PRESSURE) = 0, 1, 2, 3, 4, 5
 
