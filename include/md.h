@@ -446,7 +446,8 @@ enum {
     MD_OPT_TILE_DIMS = 10   /* read only: cells per tile along x, y and z of the
                                current tile shape, x | y << 8 | z << 16 (boxes
                                with fewer than the largest + 2 cells per axis
-                               are one tile each)                              */
+                               are one tile each); 0 when the context cannot
+                               run the tiled passes                            */
 };
 int md_set_option(md_ctx *ctx, int32_t key, int64_t value);
 int md_get_option(const md_ctx *ctx, int32_t key, int64_t *value);

@@ -1713,7 +1713,7 @@ int md_get_option(const md_ctx *h, int32_t key, int64_t *v)
     case MD_OPT_TILE_SHAPES: *v = (int64_t)(c.tile_shapes.size() / 3); return MD_OK;
     case MD_OPT_TILE_DIMS: {
         const int *d = &c.tile_shapes[3 * (size_t)c.tile_shape];
-        *v = (int64_t)d[0] | (int64_t)d[1] << 8 | (int64_t)d[2] << 16;
+        *v = c.tile_feasible ? (int64_t)d[0] | (int64_t)d[1] << 8 | (int64_t)d[2] << 16 : 0;
         return MD_OK;
     }
     }
