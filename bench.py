@@ -355,8 +355,8 @@ def bench_pressure(steps=100, warmup=10, reps=10):
     S = md.System.from_workload(wl)
     S.set_state(wl.pos, wl.vel)
     p0, _ = S.pressure()
-    ms_plain = S.time_pass(md.MD_PASS_FORCE, reps)
-    ms_virial = S.time_pass(md.MD_PASS_PRESSURE, reps)
+    ms_plain = median_pass(S, md.MD_PASS_FORCE, reps)
+    ms_virial = median_pass(S, md.MD_PASS_PRESSURE, reps)
     S.set_barostat(0.0, 1000.0, 1.0)
     wall, _, reb = timed_steps(S, steps, warmup)
     L = float(S.box()[0])
@@ -381,9 +381,9 @@ def bench_thermostat(steps=100, warmup=10, reps=10):
     S = md.System.from_workload(wl)
     S.set_state(wl.pos, wl.vel)
     S.step(1)
-    ms_plain = S.time_pass(md.MD_PASS_FORCE_STEP, reps)
+    ms_plain = median_pass(S, md.MD_PASS_FORCE_STEP, reps)
     S.set_thermostat(te, tau)
-    ms_fric = S.time_pass(md.MD_PASS_FORCE_STEP, reps)
+    ms_fric = median_pass(S, md.MD_PASS_FORCE_STEP, reps)
     t_of = lambda: 2 * float(S.kinetic()[0]) / (3 * wl.n_atoms * W.KB_EV)
     t0 = t_of()
     wall, _, reb = timed_steps(S, steps, warmup)
@@ -397,6 +397,40 @@ def bench_thermostat(steps=100, warmup=10, reps=10):
             "kinetic_T_start_K": t0, "kinetic_T_end_K": t1}
 
 
+def bench_frozen(steps=100, warmup=10, reps=10):
+    """The 4M-atom box with a frozen slab (the atoms in the tenth of the box
+    with the smallest x keep zero velocity and their positions): steps, and the
+    fused force pass with and without the atom states."""
+    import numpy as np
+    import torch
+    from paper_1212_6332_amd import md, workloads as W
+
+    wl = W.fcc4m()
+    L = float(wl.box_len[0, 0])
+    x = wl.pos[:, 0] - L * np.floor(wl.pos[:, 0] / L)
+    frozen = x < 0.1 * L
+    S = md.System.from_workload(wl)
+    S.set_state(wl.pos, wl.vel)
+    S.step(1)
+    ms_plain = median_pass(S, md.MD_PASS_FORCE_STEP, reps)
+    S.set_frozen(frozen.astype(np.uint8))
+    ms_frozen = median_pass(S, md.MD_PASS_FORCE_STEP, reps)
+    idx = torch.as_tensor(np.nonzero(frozen)[0], device="cuda")
+    p0 = S.get_state()[0][idx].clone()
+    wall, _, reb = timed_steps(S, steps, warmup)
+    d = S.get_state()[0][idx] - p0
+    # a frozen atom keeps its position up to the periodic wrap of the list builds
+    # (one rounding of the added box edge)
+    still = bool((d - L * torch.round(d / L)).abs().max() <= 1e-12 * L)
+    S.close()
+    return {"workload": "fcc4m with a frozen slab (x < L / 10, "
+                        f"{int(frozen.sum()):,} of {wl.n_atoms:,} atoms)",
+            "frozen_atom_steps_per_s": wl.n_atoms * steps / wall,
+            "frozen_ms_per_step": wall / steps * 1e3, "rebuilds": int(reb),
+            "force_step_pass_ms": ms_plain, "force_step_pass_with_frozen_ms": ms_frozen,
+            "frozen_atoms_in_place": still}
+
+
 def bench_alloy(steps=100, warmup=10, reps=10):
     """The 4M-atom binary FCC alloy (per-type-pair spline tables, two masses):
     steps, and the force, density and list-build passes."""
@@ -408,9 +442,9 @@ def bench_alloy(steps=100, warmup=10, reps=10):
     S.autotune()                  # tiled or per-atom passes and the tile shape, by timing
     shape = int(S.get_option(md.MD_OPT_TILE_SHAPE))
     wall, _, reb = timed_steps(S, steps, warmup)
-    ms = {"force_step": S.time_pass(md.MD_PASS_FORCE_STEP, reps),
-          "density": S.time_pass(md.MD_PASS_DENSITY, reps),
-          "build": S.time_pass(md.MD_PASS_BUILD, reps)}
+    ms = {"force_step": median_pass(S, md.MD_PASS_FORCE_STEP, reps),
+          "density": median_pass(S, md.MD_PASS_DENSITY, reps),
+          "build": median_pass(S, md.MD_PASS_BUILD, reps)}
     S.close()
     return {"workload": "alloy: binary FCC 100^3 cells (4,000,000 atoms, 30 % species 1), "
                         "per-type-pair 5,000-knot splines, rc 5.3 A, skin 0.3 A, 300 K",
@@ -609,7 +643,8 @@ def main():
     if not args.no_extras:
         for key, leg in (("batched", bench_batched), ("adjoint", bench_adjoint),
                          ("bcc128k", bench_c2), ("pressure", bench_pressure),
-                         ("thermostat", bench_thermostat), ("alloy", bench_alloy),
+                         ("thermostat", bench_thermostat), ("frozen", bench_frozen),
+                         ("alloy", bench_alloy),
                          ("fcc32m", bench_32m)):
             out[key] = leg()
             log(f"{key} done ({time.perf_counter() - t0:.1f} s)")
