@@ -644,7 +644,12 @@ int64_t grid_cells(const Ctx &c, const std::vector<int> &bt, std::vector<int> &c
     return cells;
 }
 
-// The device tile table: tile(8B) | tile_off(B+1) | tile_box(ntiles).
+// The device tile table: tile(8B) | tile_off(B+1) | tile_box(cap_tiles) |
+// order(ntiles).  order is the sweep of the density and force passes: within
+// each die's share of the tiles (workgroups go round robin over the dies, and
+// the share is cut as in xcd_tile), the full tiles first, then the thinner
+// tiles at the upper faces of a box (when its cells per axis are not a
+// multiple of the tile's), so that the passes end on short tiles.
 void tile_table(const Ctx &c, std::vector<int> &ht)
 {
     const int B = c.B;
@@ -658,6 +663,29 @@ void tile_table(const Ctx &c, std::vector<int> &ht)
         g += t[3] * t[4] * t[5];
     }
     ht[9 * B] = g;
+    ht.resize(9 * (size_t)B + 1 + c.cap_tiles + c.ntiles, 0);
+    int *order = &ht[9 * (size_t)B + 1 + c.cap_tiles];
+    std::vector<int> cells(c.ntiles, 0);
+    g = 0;
+    for (int b = 0; b < B; ++b) {
+        const int *t = &c.box_tile[8 * b];
+        const int nc = c.box_nc[b], gx = t[3], gy = t[4], gz = t[5];
+        for (int k = 0; k < gx * gy * gz; ++k) {
+            int kx = k % gx, ky = (k / gx) % gy, kz = k / (gx * gy);
+            cells[g + k] = t[7] == kTileA ? std::min(t[0], nc - kx * t[0]) *
+                                                std::min(t[1], nc - ky * t[1]) *
+                                                std::min(t[2], nc - kz * t[2])
+                                          : nc * nc * nc;
+        }
+        g += gx * gy * gz;
+    }
+    const int q = c.ntiles / 8, r = c.ntiles % 8;
+    for (int x = 0; x < 8; ++x) {
+        const int lo = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q, n = q + (x < r);
+        for (int k = 0; k < n; ++k) order[lo + k] = lo + k;
+        std::stable_sort(order + lo, order + lo + n,
+                         [&](int u, int v) { return cells[u] > cells[v]; });
+    }
 }
 
 // Tile geometry.  Tiles of tx x ty x tz cells are chosen so that a tile
@@ -915,13 +943,14 @@ int create_impl(const md_system *sys, const md_potential *pot, md_ctx **out, voi
     {
         std::vector<int> ht;
         tile_table(c, ht);
-        if ((rc = dev_alloc(c, &c.d_tiles, 9 * (size_t)B + 1 + c.cap_tiles)) != MD_OK)
+        if ((rc = dev_alloc(c, &c.d_tiles, 9 * (size_t)B + 1 + 2 * (size_t)c.cap_tiles)) != MD_OK)
             return fail(rc);
         if ((rc = h2d(c, c.d_tiles, ht.data(), ht.size() * sizeof(int))) != MD_OK)
             return fail(rc);
         c.bx.tile = c.d_tiles;
         c.bx.tile_off = c.d_tiles + 8 * B;
         c.bx.tile_box = c.d_tiles + 9 * B + 1;
+        c.bx.tile_order = c.d_tiles + 9 * B + 1 + c.cap_tiles;
         if (c.tile_feasible) {
             tiled_prepare(c);
             if ((rc = dev_alloc(c, &c.nl.tsrc, (size_t)c.cap_tiles * c.hmax)) != MD_OK)

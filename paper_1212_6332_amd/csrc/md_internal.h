@@ -144,6 +144,7 @@ struct Boxes {
     const int *tile;                   // per box: tx ty tz gx gy gz tile_cells mode
     const int *tile_off;               // per box: first global tile index [B+1]
     const int *tile_box;               // per global tile: its box
+    const int *tile_order;             // per place of the passes' sweep: its tile
 };
 
 // Scratch of the list build.
@@ -276,7 +277,7 @@ struct Ctx {
     bool tiled = false, tile_feasible = false;
     int hmax = 0;                      // LDS records per tile
     size_t tile_lds = 0;               // dynamic LDS bytes of a tiled-pass workgroup
-    int *d_tiles = nullptr;            // tile(8B) | tile_off(B+1) | tile_box(ntiles)
+    int *d_tiles = nullptr;            // tile(8B) | tile_off(B+1) | tile_box(cap) | order(ntiles)
     double *d_boxd = nullptr;          // L | invL | rl2 | thr2, each [B]
     int *d_boxi = nullptr;             // nc | cell_off | atom_off(B+1) | box_of(N)
     Boxes bx{};

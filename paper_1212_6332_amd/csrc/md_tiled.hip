@@ -64,11 +64,17 @@ struct alignas(256) HaloLds {
     int total;
 };
 
-__device__ __forceinline__ int xcd_tile(int b, int G)
+// Tile of workgroup b of a one-workgroup-per-tile launch of G workgroups:
+// workgroups are dispatched round robin over the 8 dies, and the workgroups
+// of one die take one contiguous eighth of the tiles (neighbouring tiles share
+// halo cells, which then pass through one L2), in the sweep order `order`
+// (null: tile index order).
+__device__ __forceinline__ int xcd_tile(int b, int G, const int *order)
 {
     const int X = 8;
     int q = G / X, r = G % X, k = b % X, w = b / X;
-    return (k < r) ? k * (q + 1) + w : r * (q + 1) + (k - r) * q + w;
+    const int p = (k < r) ? k * (q + 1) + w : r * (q + 1) + (k - r) * q + w;
+    return order ? order[p] : p;
 }
 
 __device__ __forceinline__ void tile_setup(const Boxes &bx, const Build &bd, int g, Tile &t)
@@ -358,7 +364,7 @@ __global__ __launch_bounds__(kT) void k_tile_nlist(const unsigned *gate, int N, 
     extern __shared__ __attribute__((aligned(256))) double rec[];
     __shared__ HaloLds H;
     Tile t;
-    const int g = xcd_tile(blockIdx.x, gridDim.x);
+    const int g = xcd_tile(blockIdx.x, gridDim.x, nullptr);
     tile_setup(bx, bd, g, t);
     halo_table(t, bx, bd, H);
     stage<false>(t, st, H, rec, hmax, flags, nl.tsrc + (size_t)g * hmax);
@@ -607,18 +613,20 @@ __device__ __forceinline__ void tile_atoms(const Tile &t, Atom &&atom)
 
 // Tile m of persistent workgroup b (of P), or -1.  Workgroups are dispatched
 // round robin over the 8 XCDs; the workgroups of one XCD sweep one contiguous
-// eighth of the tiles together, so neighbouring tiles (which share halo
-// cells) are staged through the same L2 at about the same time.
-__device__ __forceinline__ int tile_at(int b, int m, int P, int G)
+// eighth of the tiles together (in the sweep order of the tile table), so
+// neighbouring tiles (which share halo cells) are staged through the same L2
+// at about the same time.
+__device__ __forceinline__ int tile_at(int b, int m, int P, int G, const int *order)
 {
     if (P % 8 == 0) {
         int x = b % 8, Q = P / 8;
-        int lo = (int)((long long)G * x / 8), hi = (int)((long long)G * (x + 1) / 8);
+        int q = G / 8, r = G % 8;
+        int lo = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q, hi = lo + q + (x < r);
         int g = lo + b / 8 + m * Q;
-        return g < hi ? g : -1;
+        return g < hi ? order[g] : -1;
     }
     int g = b + m * P;
-    return g < G ? g : -1;
+    return g < G ? order[g] : -1;
 }
 
 // Persistent driver of the tiled passes: each workgroup takes its tiles in
@@ -633,13 +641,13 @@ __device__ __forceinline__ void run_tiles(int G, const State &st, const Boxes &b
     constexpr int R = 5;  // records per thread: hmax <= R * 1024
     const int P = gridDim.x, tid = threadIdx.x;
     int m = 0;
-    int g = tile_at(blockIdx.x, 0, P, G);
+    int g = tile_at(blockIdx.x, 0, P, G, bx.tile_order);
     if (g < 0) return;
     Tile t;
     tile_setup(bx, bd, g, t);
     stage_list<WITH_FP>(g, st, nl, rec, hmax);
     while (true) {
-        const int gn = tile_at(blockIdx.x, m + 1, P, G);
+        const int gn = tile_at(blockIdx.x, m + 1, P, G, bx.tile_order);
         Tile tn = t;
         int totn = 0;
         if (gn >= 0) {
@@ -742,7 +750,7 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
     // one workgroup per tile (with the persistent driver the fused variant
     // needs more registers than it gains)
     {
-        const int g = xcd_tile(blockIdx.x, gridDim.x);
+        const int g = xcd_tile(blockIdx.x, gridDim.x, bx.tile_order);
         Tile t;
         tile_setup(bx, bd, g, t);
         stage_list<true>(g, st, nl, rec, hmax);
