@@ -109,6 +109,27 @@ def test_tiles_with_surplus_atoms_match_oracle(name):
     assert surplus > 0   # some shape has tiles with surplus atoms
 
 
+def test_tile_dims_option():
+    """MD_OPT_TILE_DIMS reads each candidate's cells per tile (the planner's
+    first); a B-spline context, which runs the per-atom passes only, reads 0."""
+    wl = W.fcc4m(ncell=50)
+    S = md.System.from_workload(wl)
+    seen = set()
+    for k in range(S.get_option(md.MD_OPT_TILE_SHAPES)):
+        S.set_option(md.MD_OPT_TILE_SHAPE, k)
+        d = S.get_option(md.MD_OPT_TILE_DIMS)
+        dims = (d & 255, (d >> 8) & 255, d >> 16)
+        assert all(1 <= v <= 6 for v in dims), dims
+        seen.add(dims)
+    assert len(seen) == S.get_option(md.MD_OPT_TILE_SHAPES)
+    with pytest.raises(md.MDError):
+        S.set_option(md.MD_OPT_TILE_DIMS, 0)        # read only
+    S.close()
+    B = md.System.from_workload(W.adjoint64())
+    assert B.get_option(md.MD_OPT_TILED) == 0 and B.get_option(md.MD_OPT_TILE_DIMS) == 0
+    B.close()
+
+
 def test_tile_shape_lists_match_oracle_sampled():
     """A non-default tile shape: sampled rows and forces against the oracle."""
     wl = W.alloy(ncell=56)
