@@ -414,10 +414,14 @@ enum {
                                (default when B > 1), 0 the merged-box kernels     */
     MD_OPT_BATCH_BLOCK = 2, /* workgroup size of the persistent kernel (256/512/1024) */
     MD_OPT_USE_GRAPH = 3,   /* md_step replays a captured HIP graph (default 1)     */
-    MD_OPT_GRAPH_STEPS = 4, /* steps per captured graph (default 9; in tiled
+    MD_OPT_GRAPH_STEPS = 4, /* steps per captured graph (default 40; in tiled
                                contexts all but the last one or two steps of a
                                graph fuse the next kick and drift into the force
-                               pass, with bitwise the same trajectory)            */
+                               pass, with bitwise the same trajectory).  The
+                               remainder of an md_step call that is not a
+                               multiple runs as one more graph of that many
+                               steps (kept for the next call with the same
+                               remainder); a single step is launched directly  */
     MD_OPT_TILED = 5,       /* 1: list build, density and force stage each tile's
                                neighbour records in LDS (default where the tiles
                                fit); 0: per-atom kernels gathering from HBM       */

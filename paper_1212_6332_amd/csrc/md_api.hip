@@ -115,9 +115,10 @@ int check_potential(const md_potential *p)
 
 void graph_reset(Ctx &c)
 {
-    if (c.graph_exec) (void)hipGraphExecDestroy(c.graph_exec);
-    c.graph_exec = nullptr;
-    c.graph_len = 0;
+    for (Ctx::StepGraph *g : {&c.graph, &c.tail_graph}) {
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        *g = Ctx::StepGraph{};
+    }
     batched_graph_reset(c);
 }
 
@@ -456,9 +457,10 @@ void launch_step(Ctx &c, hipStream_t s, bool kick_drift, int force_mode)
 // kick-drift kernel) and the steps alternate between the two position
 // buffers; the last one or two steps are not fused, so that the state ends
 // where it began: in the primary buffer, with velocities at the full step.
-int capture_steps(Ctx &c, int nsteps)
+int capture_steps(Ctx &c, int nsteps, Ctx::StepGraph &out)
 {
-    graph_reset(c);
+    if (out.exec) (void)hipGraphExecDestroy(out.exec);
+    out = Ctx::StepGraph{};
     hipGraph_t g = nullptr;
     const State prim = c.st;
     State alt = prim;
@@ -472,31 +474,39 @@ int capture_steps(Ctx &c, int nsteps)
         launch_step(c, c.cap_stream, k == 0 || k > fused, k < fused ? 2 : 1);
     }
     c.st = prim;
-    c.graph_fused = fused;
     HIP_TRY(hipStreamEndCapture(c.cap_stream, &g));
-    hipError_t e = hipGraphInstantiate(&c.graph_exec, g, nullptr, nullptr, 0);
+    hipError_t e = hipGraphInstantiate(&out.exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-        c.graph_exec = nullptr;
+        out.exec = nullptr;
         return MD_ERR_DEVICE;
     }
-    c.graph_len = nsteps;
+    out.len = nsteps;
+    out.fused = fused;
     return MD_OK;
 }
 
-// nsteps steps of the captured graphs and then single steps; *graphs: the
-// graphs launched.
-int run_steps(Ctx &c, int nsteps, hipStream_t s, int *graphs)
+// nsteps steps: graphs of graph_steps steps, then one graph of the
+// remainder (kept for the next call with the same remainder), or with graphs
+// off single steps.  *graphs: the full graphs launched; *tail: whether the
+// remainder graph was.
+int run_steps(Ctx &c, int nsteps, hipStream_t s, int *graphs, bool *tail)
 {
     int done = 0;
     *graphs = 0;
-    if (c.use_graph && nsteps >= c.graph_steps) {
-        if (!c.graph_exec || c.graph_len != c.graph_steps) {
-            int rc = capture_steps(c, c.graph_steps);
-            if (rc != MD_OK) return rc;
+    *tail = false;
+    if (c.use_graph) {
+        if (nsteps >= c.graph_steps && c.graph.len != c.graph_steps)
+            ENSURE(capture_steps(c, c.graph_steps, c.graph));
+        for (; nsteps - done >= c.graph_steps; done += c.graph_steps, ++*graphs)
+            HIP_TRY(hipGraphLaunch(c.graph.exec, s));
+        const int rest = nsteps - done;
+        if (rest >= 2) {
+            if (c.tail_graph.len != rest) ENSURE(capture_steps(c, rest, c.tail_graph));
+            HIP_TRY(hipGraphLaunch(c.tail_graph.exec, s));
+            *tail = true;
+            done = nsteps;
         }
-        for (; done + c.graph_len <= nsteps; done += c.graph_len, ++*graphs)
-            HIP_TRY(hipGraphLaunch(c.graph_exec, s));
     }
     for (; done < nsteps; ++done) launch_step(c, s, true, 1);
     return MD_OK;
@@ -530,7 +540,8 @@ int steps_merged(Ctx &c, int nsteps, hipStream_t s)
         if (round > 8) return MD_ERR_NLIST_OVERFLOW;
         launch_step_mark(c, s);
         int graphs = 0;
-        ENSURE(run_steps(c, left, s, &graphs));
+        bool tail = false;
+        ENSURE(run_steps(c, left, s, &graphs, &tail));
         unsigned w[kFlagWords];
         ENSURE(read_flags(c, s, w));
         if (!w[kHaltWord]) break;
@@ -539,15 +550,20 @@ int steps_merged(Ctx &c, int nsteps, hipStream_t s)
         const uint64_t mark = ((uint64_t)w[kMarkWord + 1] << 32) | w[kMarkWord];
         const int k = (int)(now - mark);
         if (k >= left) return MD_ERR_STATE;
-        if (k < graphs * c.graph_len) {
-            // inside a graph, odd fused steps run on the other position buffer
-            const int j = k % c.graph_len;
-            if (j < c.graph_fused && j % 2 == 1) {
-                const size_t nb = sizeof(double) * (size_t)c.N;
-                HIP_TRY(hipMemcpyAsync(c.st.x, c.st.xo, nb, hipMemcpyDeviceToDevice, s));
-                HIP_TRY(hipMemcpyAsync(c.st.y, c.st.yo, nb, hipMemcpyDeviceToDevice, s));
-                HIP_TRY(hipMemcpyAsync(c.st.z, c.st.zo, nb, hipMemcpyDeviceToDevice, s));
-            }
+        // inside a graph, odd fused steps run on the other position buffer
+        int j = -1, fused = 0;
+        if (k < graphs * c.graph.len) {
+            j = k % c.graph.len;
+            fused = c.graph.fused;
+        } else if (tail && k < graphs * c.graph.len + c.tail_graph.len) {
+            j = k - graphs * c.graph.len;
+            fused = c.tail_graph.fused;
+        }
+        if (j >= 0 && j < fused && j % 2 == 1) {
+            const size_t nb = sizeof(double) * (size_t)c.N;
+            HIP_TRY(hipMemcpyAsync(c.st.x, c.st.xo, nb, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(c.st.y, c.st.yo, nb, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(c.st.z, c.st.zo, nb, hipMemcpyDeviceToDevice, s));
         }
         launch_fill_u32(c.dev.flags + 1, 1, 0u, s);  // its rebuild request
         ENSURE(regrow(c, w, s));

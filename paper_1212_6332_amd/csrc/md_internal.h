@@ -330,13 +330,16 @@ struct Ctx {
     Thermo thermo{1.0, 0.0, 0};
     double thermo_te = 0.0, thermo_tau = 0.0;
 
-    // graph replay of md_step
+    // graph replay of md_step: graphs of graph_steps steps, and one more for
+    // the remainder of the last call that was not a multiple of it
     bool use_graph = true;
-    int graph_steps = 9;
+    int graph_steps = 40;
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    int graph_len = 0;
-    int graph_fused = 0;               // leading steps of the graph with the fused kick and drift
+    struct StepGraph {
+        hipGraphExec_t exec = nullptr;
+        int len = 0;                   // steps
+        int fused = 0;                 // leading steps with the fused kick and drift
+    } graph, tail_graph;
 
     // allocations to free
     std::vector<void *> allocs;        // device blocks of the context (hipMalloc)
