@@ -71,3 +71,30 @@ def test_nve_energy_at_full_size():
     S.close()
     assert flags == 0 and steps == 1000 and builds > 10
     assert drift / wl.n_atoms <= 1e-4, drift / wl.n_atoms
+
+
+
+def test_benchmark_box_trajectory_matches_oracle():
+    """The 4,000,000-atom SMTB box the benchmark times (whose 4 x 4 x 3-cell
+    tiles include about 900 with more atoms than a workgroup has threads, so
+    surplus rows shared by 16 lanes are in every step): 30 steps in one
+    captured graph with the fused kicks and device-decided rebuilds against
+    the oracle's velocity Verlet, positions within 1e-10 Angstrom, velocities
+    within 1e-9 relative, the same number of rebuilds."""
+    wl = W.fcc4m()
+    L = float(wl.box_len[0, 0])
+    nsteps = 30
+    S = md.System.from_workload(wl)
+    S.set_state(wl.pos, wl.vel)
+    S.step(nsteps)
+    p, v = (t.cpu().numpy() for t in S.get_state())
+    flags, builds, steps = S.status()
+    S.close()
+    x, vo, _, _, reb = O.vv(O.wrap(wl.pos, L), wl.vel, L, O.Pot(wl.pot), wl.mass, wl.dt,
+                            wl.skin, nsteps, energies=False)
+    assert flags == 0 and steps == nsteps and reb >= 1
+    assert builds == 1 + reb
+    d = p - x
+    d -= L * np.round(d / L)
+    assert np.abs(d).max() < 1e-10
+    assert np.abs(v - vo).max() <= 1e-9 * np.abs(vo).max()
