@@ -61,9 +61,9 @@ def force_pass_bytes(n_atoms, mean_list):
 def step_force_bytes(n_atoms, mean_list):
     """The force kernel as the step runs it (this step's second half kick,
     the next step's first half kick and drift fused): the force pass's bytes
-    plus the list's reference positions in (24) and the drifted positions
-    out (24)."""
-    return n_atoms * (156.0 + 4.0 * mean_list)
+    without the force out (it goes into the velocities only) plus the list's
+    reference positions in (24) and the drifted positions out (24)."""
+    return n_atoms * (132.0 + 4.0 * mean_list)
 
 
 def density_pass_bytes(n_atoms, mean_list):

@@ -819,9 +819,14 @@ __global__ __launch_bounds__(kT) void k_tile_force(int N, int G, State st, Boxes
             ax *= sg;
             ay *= sg;
             az *= sg;
-            st.fx[i] = ax;
-            st.fy[i] = ay;
-            st.fz[i] = az;
+            // with the next kick fused (MODE 2) the forces go straight into
+            // the velocities: the next force pass overwrites them before any
+            // kernel reads them (a sequence of steps ends with an unfused one)
+            if constexpr (MODE != 2) {
+                st.fx[i] = ax;
+                st.fy[i] = ay;
+                st.fz[i] = az;
+            }
             if constexpr (ENERGY) {
                 st.eat[i] = fma(0.5, ep, st.Femb[i]);
                 st.wat[i] = wv;
