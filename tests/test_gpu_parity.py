@@ -226,6 +226,29 @@ def test_step_energy_conservation():
     S.close()
 
 
+def test_default_graphs_and_remainder_graphs_equal_direct_launches():
+    """md_step calls of 83, 41, 83 and 2 steps with the default graph length
+    (two 40-step graphs and a 3-step remainder graph, one graph and a single
+    step, the remainder graph kept from the first call, a 2-step remainder
+    graph) against one launch per kernel: bitwise the same trajectory,
+    rebuild count and flags."""
+    wl = CASES["smtb5324"]()
+    out = []
+    for use_graph in (1, 0):
+        S = md.System.from_workload(wl)
+        S.set_option(md.MD_OPT_USE_GRAPH, use_graph)
+        assert S.get_option(md.MD_OPT_GRAPH_STEPS) == 40
+        S.set_state(wl.pos, wl.vel)
+        for n in (83, 41, 83, 2):
+            S.step(n)
+        p, v = S.get_state()
+        out.append((p.cpu().numpy(), v.cpu().numpy(), S.status()))
+        S.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    assert out[0][2] == out[1][2] and out[0][2][2] == 209
+    assert out[0][2][1] >= 3
+
+
 @pytest.mark.parametrize("name,graph_steps", [("spline1024", 9), ("spline1024", 8),
                                                ("smtb5324", 9), ("smtb5324", 4)])
 def test_graph_replay_equals_direct_launches(name, graph_steps):
