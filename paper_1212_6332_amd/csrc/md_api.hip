@@ -427,11 +427,13 @@ int ensure_density(Ctx &c, hipStream_t s)
 // them); force_mode: 1 the force pass ends with the half kick, 2 it also
 // performs the next step's half kick and drift into the second position
 // buffer.  The device's rebuild request is counted and cleared right after
-// the gated build, before a fused force pass can raise the next one.  With
-// the barostat (eq. 5) the coordinates and boxes are scaled after the drift,
-// and the force pass computes energies and the virial for the next pressure
-// (eq. 6) and scale factor.
-void launch_step(Ctx &c, hipStream_t s, bool kick_drift, int force_mode)
+// the gated build, before a fused force pass can raise the next one.
+// fp_only: the density pass stores F' alone (in tiled contexts; the
+// densities and embedding energies of a step inside a sequence are never
+// read).  With the barostat (eq. 5) the coordinates and boxes are scaled
+// after the drift, and the force pass computes energies and the virial for
+// the next pressure (eq. 6) and scale factor.
+void launch_step(Ctx &c, hipStream_t s, bool kick_drift, int force_mode, bool fp_only = false)
 {
     if (c.baro_on) {
         launch_kick_drift(c, s);
@@ -447,7 +449,7 @@ void launch_step(Ctx &c, hipStream_t s, bool kick_drift, int force_mode)
     if (kick_drift) launch_kick_drift(c, s);
     launch_build(c, true, s);
     launch_step_end(c, s);
-    launch_density(c, s);
+    launch_density(c, s, fp_only);
     launch_force(c, false, force_mode, s);
 }
 
@@ -471,7 +473,9 @@ int capture_steps(Ctx &c, int nsteps, Ctx::StepGraph &out)
     HIP_TRY(hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeRelaxed));
     for (int k = 0; k < nsteps; ++k) {
         c.st = (k < fused && k % 2) ? alt : prim;
-        launch_step(c, c.cap_stream, k == 0 || k > fused, k < fused ? 2 : 1);
+        // the densities and embedding energies of all but the last step are
+        // never read: their density passes store F' alone
+        launch_step(c, c.cap_stream, k == 0 || k > fused, k < fused ? 2 : 1, k < nsteps - 1);
     }
     c.st = prim;
     HIP_TRY(hipStreamEndCapture(c.cap_stream, &g));

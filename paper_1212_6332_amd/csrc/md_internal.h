@@ -204,7 +204,7 @@ void ctx_free(Ctx &c, void *p);
 void launch_refresh_frozen(Ctx &c, hipStream_t s);
 void launch_get_state(Ctx &c, double *pos, double *vel, hipStream_t s);
 void launch_build(Ctx &c, bool gated, hipStream_t s);
-void launch_density(Ctx &c, hipStream_t s);
+void launch_density(Ctx &c, hipStream_t s, bool fp_only = false);  // fp_only: F' alone (tiled)
 void launch_embed(Ctx &c, hipStream_t s);
 // kick: 0 none, 1 half kick, 2 half kick and the next step's half kick and
 // drift into the other position buffer (tiled contexts only)
@@ -227,7 +227,7 @@ void launch_clear_bits(Ctx &c, unsigned mask, hipStream_t s);  // status bits of
 // Tiled passes (md_tiled.hip).
 void tiled_prepare(Ctx &c);
 void launch_tile_nlist(Ctx &c, const unsigned *gate, hipStream_t s);
-void launch_tile_density(Ctx &c, hipStream_t s);
+void launch_tile_density(Ctx &c, hipStream_t s, bool fp_only);
 void launch_tile_force(Ctx &c, bool energy, int kick, hipStream_t s);
 void launch_tile_get_neighbors(Ctx &c, int32_t *counts, int32_t *ids, int32_t cols, hipStream_t s);
 void launch_pack_positions(Ctx &c, hipStream_t s);

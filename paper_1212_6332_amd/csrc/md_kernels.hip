@@ -1120,10 +1120,10 @@ void launch_build(Ctx &c, bool gated, hipStream_t s)
     if (!gated) k_count_build<<<1, 1, 0, s>>>(c.dev.flags);
 }
 
-void launch_density(Ctx &c, hipStream_t s)
+void launch_density(Ctx &c, hipStream_t s, bool fp_only)
 {
     if (c.tiled) {
-        launch_tile_density(c, s);
+        launch_tile_density(c, s, fp_only);
         return;
     }
     // with the barostat the box lengths live on the device only

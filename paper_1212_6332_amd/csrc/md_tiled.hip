@@ -696,7 +696,7 @@ __device__ __forceinline__ void run_tiles(int G, const State &st, const Boxes &b
 template <int KIND, int P>
 __global__ __launch_bounds__(kT) void k_tile_density(int N, int G, State st, Boxes bx, Build bd,
                                                      NList nl, Pot pot_arg, int hmax,
-                                                     unsigned *flags)
+                                                     unsigned *flags, int fp_only)
 {
     extern __shared__ __attribute__((aligned(256))) double rec[];
     if (halted(flags)) return;
@@ -724,9 +724,12 @@ __global__ __launch_bounds__(kT) void k_tile_density(int N, int G, State st, Box
                 embed_typed(pot, rho, ai, F, Fp, bad);
             else
                 embed<KIND>(pot, rho, F, Fp, bad);
-            st.rho[i] = rho;
-            st.Femb[i] = F;
+            // inside a sequence of steps only F' is read (by the force pass)
             st.Fp[i] = Fp;
+            if (!fp_only) {
+                st.rho[i] = rho;
+                st.Femb[i] = F;
+            }
         });
     });
     raise_flags(flags, bad);
@@ -973,21 +976,21 @@ void launch_tile_nlist(Ctx &c, const unsigned *gate, hipStream_t s)
 }
 
 template <int L>
-static void tile_density_lanes(Ctx &c, hipStream_t s)
+static void tile_density_lanes(Ctx &c, hipStream_t s, int fp_only)
 {
     const int N = (int)c.N, P = c.tile_grid, G = c.ntiles;
     switch (c.pot.kind) {
-    case MD_POT_FS: k_tile_density<MD_POT_FS, L><<<P, kT, c.tile_lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
-    case MD_POT_SMTB: k_tile_density<MD_POT_SMTB, L><<<P, kT, c.tile_lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
-    case kTyped: k_tile_density<kTyped, L><<<P, kT, c.tile_lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
-    default: k_tile_density<MD_POT_SPLINE, L><<<P, kT, c.tile_lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags); break;
+    case MD_POT_FS: k_tile_density<MD_POT_FS, L><<<P, kT, c.tile_lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags, fp_only); break;
+    case MD_POT_SMTB: k_tile_density<MD_POT_SMTB, L><<<P, kT, c.tile_lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags, fp_only); break;
+    case kTyped: k_tile_density<kTyped, L><<<P, kT, c.tile_lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags, fp_only); break;
+    default: k_tile_density<MD_POT_SPLINE, L><<<P, kT, c.tile_lds, s>>>(N, G, c.st, c.bx, c.bd, c.nl, c.pot, c.hmax, c.dev.flags, fp_only); break;
     }
 }
 
-void launch_tile_density(Ctx &c, hipStream_t s)
+void launch_tile_density(Ctx &c, hipStream_t s, bool fp_only)
 {
-    if (c.tile_lanes == 2) tile_density_lanes<2>(c, s);
-    else tile_density_lanes<1>(c, s);
+    if (c.tile_lanes == 2) tile_density_lanes<2>(c, s, fp_only);
+    else tile_density_lanes<1>(c, s, fp_only);
 }
 
 template <int L>
