@@ -1356,6 +1356,8 @@ int md_autotune(md_ctx *h, void *stream, int32_t *block)
             launch_build(c, false, s);
             unsigned w[kFlagWords];
             if ((rc = read_flags(c, s, w)) != MD_OK) return rc;
+            // the build sorted the state either way: densities and forces are stale
+            c.density_valid = c.forces_valid = false;
             if (w[kHaltWord]) {
                 launch_fill_u32(c.dev.flags + kHaltWord, 2, 0u, s);
                 launch_clear_bits(c, MD_FLAG_TILE_OVERFLOW, s);
@@ -1363,7 +1365,6 @@ int md_autotune(md_ctx *h, void *stream, int32_t *block)
                 continue;
             }
             c.list_valid = true;
-            c.density_valid = c.forces_valid = false;
             double cost = 0.0;
             if ((rc = cost_of(cost)) != MD_OK) return rc;
             if (cost <= best_cost) {
