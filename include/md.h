@@ -253,8 +253,10 @@ int md_forces(md_ctx *ctx, double *f_out, double *e_atom, double *e_box, void *s
  * list refresh: nsteps of half kick, drift, conditional list rebuild
  * decided on the device, density + embedding, force, half kick.  Brings the
  * list and forces up to date first if needed (nsteps = 0 does only that,
- * with the kernels that would take the steps).  The step sequence is
- * captured once in a HIP graph and replayed.  Waits for the steps and reads
+ * with the kernels that would take the steps).  The steps are captured in
+ * HIP graphs of MD_OPT_GRAPH_STEPS steps (and one of the remainder) and
+ * replayed; a graph is kept until a setting or the list capacity changes.
+ * Waits for the steps and reads
  * the device status word at the end: a list that outgrew its capacity
  * inside the steps is handled as described at the top (with several boxes
  * in the persistent stepper, the call is taken again from its start state
