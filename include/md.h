@@ -255,7 +255,8 @@ int md_forces(md_ctx *ctx, double *f_out, double *e_atom, double *e_box, void *s
  * list and forces up to date first if needed (nsteps = 0 does only that,
  * with the kernels that would take the steps).  The steps are captured in
  * HIP graphs of MD_OPT_GRAPH_STEPS steps (and one of the remainder) and
- * replayed; a graph is kept until a setting or the list capacity changes.
+ * replayed (captured again after a change of settings, tiling or list
+ * capacity).
  * Waits for the steps and reads
  * the device status word at the end: a list that outgrew its capacity
  * inside the steps is handled as described at the top (with several boxes
