@@ -256,9 +256,8 @@ int md_forces(md_ctx *ctx, double *f_out, double *e_atom, double *e_box, void *s
  * with the kernels that would take the steps).  The steps are captured in
  * HIP graphs of MD_OPT_GRAPH_STEPS steps (and one of the remainder) and
  * replayed (captured again after a change of settings, tiling or list
- * capacity).
- * Waits for the steps and reads
- * the device status word at the end: a list that outgrew its capacity
+ * capacity).  Waits for the steps and reads the device status word at the
+ * end: a list that outgrew its capacity
  * inside the steps is handled as described at the top (with several boxes
  * in the persistent stepper, the call is taken again from its start state
  * with the larger capacity); MD_ERR_TABLE_RANGE or MD_ERR_NONFINITE report
