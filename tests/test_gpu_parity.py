@@ -298,3 +298,27 @@ def test_error_flags():
     S.density()
     assert S.status()[0] & md.MD_FLAG_TABLE_RANGE
     S.close()
+
+
+def test_densities_and_energies_after_graph_steps_are_current():
+    """Inside a captured graph only F' is stored by all but the last step's
+    density pass: after md_step (a 40-step graph and a 5-step remainder
+    graph), md_density, md_embed and the energies equal those of a fresh
+    context set to the final state."""
+    wl = CASES["smtb5324"]()
+    S = md.System.from_workload(wl)
+    S.set_state(wl.pos, wl.vel)
+    S.step(45)
+    p, v = S.get_state()
+    rho = S.density().cpu().numpy()
+    F, Fp = (t.cpu().numpy() for t in S.embed())
+    f, e, eb = (t.cpu().numpy() for t in S.forces())
+    S.close()
+    T = md.System.from_workload(wl)
+    T.set_state(p, v)
+    rho2 = T.density().cpu().numpy()
+    F2, Fp2 = (t.cpu().numpy() for t in T.embed())
+    f2, e2, eb2 = (t.cpu().numpy() for t in T.forces())
+    T.close()
+    for a, b in ((rho, rho2), (F, F2), (Fp, Fp2), (f, f2), (e, e2), (eb, eb2)):
+        assert rel(a, b) <= 1e-12
