@@ -169,9 +169,12 @@ def bench_main(steps, warmup, reps):
     S = md.System.from_workload(wl)
     S.set_state(wl.pos, wl.vel)
     S.autotune()                  # tiled or per-atom passes and the tile shape, by timing
+    dims = int(S.get_option(md.MD_OPT_TILE_DIMS))
     tuned = {"tiled": int(S.get_option(md.MD_OPT_TILED)),
              "tile_shape": int(S.get_option(md.MD_OPT_TILE_SHAPE)),
-             "tile_shapes": int(S.get_option(md.MD_OPT_TILE_SHAPES))}
+             "tile_shapes": int(S.get_option(md.MD_OPT_TILE_SHAPES)),
+             "tile_cells": [dims & 255, (dims >> 8) & 255, dims >> 16],
+             "graph_steps": int(S.get_option(md.MD_OPT_GRAPH_STEPS))}
     S.forces(energy=False)
     entries, pairs = list_stats(S, wl.pot.rc)
     n = wl.n_atoms
