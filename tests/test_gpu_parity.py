@@ -76,6 +76,10 @@ CASES = {
     "spline2662": lambda: W.bcc128k(ncell=11),
     "smtb5324": lambda: W.fcc4m(ncell=11),         # 6 cells per axis: edge tiles, halo mode A
     "spline4394": lambda: W.bcc128k(ncell=13),     # 6 cells per axis, halo mode A
+    # 600 boxes of 108 to 2,048 atoms through the merged-box kernels: one tile
+    # per box (halo mode B), enough tiles for one lane per row, and the boxes
+    # of 1,372 atoms with their surplus rows shared by two lanes
+    "batch600": lambda: W.batch2048(n_boxes=600),
 }
 
 
